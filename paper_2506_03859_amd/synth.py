@@ -1,0 +1,116 @@
+"""Seeded synthetic input matrices shaped like the paper's experiments.
+
+This module only builds test inputs A; it holds none of the low-rank method's
+arithmetic, and both the HIP path's tests and the CPU oracle's tests take their
+inputs from here.
+
+Constructions (all seeded, numpy PCG64 unless stated):
+
+* ``spectral(m, n, sigma, seed)``: A = U diag(sigma) V^T with U (m x k) and
+  V (n x k) Haar-distributed orthonormal factors, obtained by QR of standard
+  Gaussian matrices with the sign of diag(R) forced positive (Section 5: the
+  factors are orthonormalised Gaussian matrices).
+* ``matrix1`` / ``matrix2``: the paper's square test matrices of Section 5,
+  sigma_j = j^-2 (slow decay) and sigma_j = exp(-j/20) (fast decay).
+* ``exp_floor_spectrum``: sigma_i = exp(-i/50) + 1e-6 (additive floor).
+* ``tall_lowrank``: L diag(1/i) R + N with Gaussian L (m x r), R (r x n) and
+  i.i.d. N(0, var) noise, the tall fixed-rank workload.
+* ``integer_matrix``: small-integer-valued matrices, for which any ordering
+  of a short FP32 sum is exact.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.PCG64(int(seed)))
+
+
+def haar_columns(rows: int, cols: int, rng: np.random.Generator) -> np.ndarray:
+    """rows x cols matrix with orthonormal columns, Haar distributed (rows >= cols)."""
+    g = rng.standard_normal((rows, cols))
+    q, r = np.linalg.qr(g, mode="reduced")
+    d = np.sign(np.diag(r))
+    d[d == 0] = 1.0
+    return q * d[None, :]
+
+
+def spectral(m: int, n: int, sigma: np.ndarray, seed: int) -> np.ndarray:
+    """A = U diag(sigma) V^T in float64, U, V Haar, len(sigma) <= min(m, n)."""
+    sigma = np.asarray(sigma, dtype=np.float64)
+    k = sigma.shape[0]
+    assert k <= min(m, n)
+    rng = _rng(seed)
+    u = haar_columns(m, k, rng)
+    v = haar_columns(n, k, rng)
+    return (u * sigma[None, :]) @ v.T
+
+
+def spectral_torch(m: int, n: int, sigma: np.ndarray, seed: int, device: str = "cpu"):
+    """Same construction as ``spectral`` with the QR and product done by torch in
+    float64 on ``device`` (for sizes where a CPU QR takes minutes). The Gaussian
+    draws still come from numpy PCG64 so the input is defined by the seed; the
+    result can differ from ``spectral`` in the last bits (different QR)."""
+    import torch
+
+    sigma = np.asarray(sigma, dtype=np.float64)
+    k = sigma.shape[0]
+    rng = _rng(seed)
+
+    def haar_t(rows, cols):
+        g = torch.from_numpy(rng.standard_normal((rows, cols))).to(device)
+        q, r = torch.linalg.qr(g, mode="reduced")
+        d = torch.sign(torch.diagonal(r))
+        d[d == 0] = 1.0
+        return q * d[None, :]
+
+    u = haar_t(m, k)
+    v = haar_t(n, k)
+    s = torch.from_numpy(sigma).to(device)
+    return (u * s[None, :]) @ v.T
+
+
+def matrix1_sigma(n: int) -> np.ndarray:
+    return 1.0 / np.arange(1, n + 1, dtype=np.float64) ** 2
+
+
+def matrix2_sigma(n: int) -> np.ndarray:
+    return np.exp(-np.arange(1, n + 1, dtype=np.float64) / 20.0)
+
+
+def exp_floor_sigma(k: int, decay: float = 50.0, floor: float = 1e-6) -> np.ndarray:
+    return np.exp(-np.arange(1, k + 1, dtype=np.float64) / decay) + floor
+
+
+def matrix1(n: int, seed: int) -> np.ndarray:
+    """Section 5 Matrix 1: n x n, sigma_j = 1/j^2."""
+    return spectral(n, n, matrix1_sigma(n), seed)
+
+
+def matrix2(n: int, seed: int) -> np.ndarray:
+    """Section 5 Matrix 2: n x n, sigma_j = exp(-j/20)."""
+    return spectral(n, n, matrix2_sigma(n), seed)
+
+
+def tall_lowrank(m: int, n: int, r: int, noise_var: float, seed: int,
+                 dtype=np.float64) -> np.ndarray:
+    """L diag(1/i)_{i<=r} R + N; L m x r and R r x n standard Gaussian, N i.i.d.
+    N(0, noise_var). Built in float64 then cast."""
+    rng = _rng(seed)
+    left = rng.standard_normal((m, r))
+    right = rng.standard_normal((r, n))
+    scale = 1.0 / np.arange(1, r + 1, dtype=np.float64)
+    a = (left * scale[None, :]) @ right
+    a += np.sqrt(noise_var) * rng.standard_normal((m, n))
+    return a.astype(dtype, copy=False)
+
+
+def integer_matrix(m: int, n: int, seed: int, amax: int = 1024) -> np.ndarray:
+    """Integer-valued entries in [-amax, amax] (float64 storage)."""
+    rng = _rng(seed)
+    return rng.integers(-amax, amax + 1, size=(m, n)).astype(np.float64)
+
+
+def gaussian_matrix(m: int, n: int, seed: int) -> np.ndarray:
+    return _rng(seed).standard_normal((m, n))
