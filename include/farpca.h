@@ -1,0 +1,140 @@
+/* farpca.h - C-ABI of the MI355X (gfx950) implementation of the accelerated
+ * farPCA hot path: the blocked, adaptive randomized QB / PCA loop of
+ * Algorithm 1 (farPCA, Section 2.1) with the sparse test matrices of
+ * Definitions 2.1-2.4 (farPCASB = Algorithm 2; farPCASS, farPCASG, farPCAB of
+ * Sections 3.2 and 5) of Jiang, Fu, Xu, "Accelerating Randomized Algorithms for
+ * Low-Rank Matrix Approximation" (arXiv 2506.03859).
+ *
+ * Conventions
+ *  - All matrices are row-major FP32 unless stated.  A is m x n with leading
+ *    dimension lda >= n (elements).  Any m, n >= 1 is accepted (m < n too).
+ *  - Pointers named d* are device pointers (global memory of the current HIP
+ *    device), owned by the caller.  The library never allocates or frees device
+ *    memory: every scratch buffer lives in the caller's workspace.
+ *  - `stream` is a hipStream_t passed as void*; all device work is enqueued on
+ *    it.  farpca_run is host-synchronous: it reads the error indicator after
+ *    every block (one 8-byte device-to-host copy) and returns after the final
+ *    decomposition has been written.
+ *  - Errors are returned as negative status codes; no exception crosses the
+ *    ABI.  On error the output buffers are unspecified.
+ *  - A plan holds host-side state only.  One plan must not be used by two
+ *    threads at once; distinct plans may run concurrently on distinct streams
+ *    with distinct workspaces.
+ */
+#ifndef FARPCA_H_
+#define FARPCA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define FARPCA_OK 0              /* fixed precision: E < tol^2 ||A||_F^2 reached; fixed rank: done */
+#define FARPCA_NOT_CONVERGED 1   /* block cap reached first; outputs valid at l = blocks * b       */
+#define FARPCA_E_INVALID (-1)    /* invalid parameter                                              */
+#define FARPCA_E_NOMEM (-2)      /* workspace smaller than farpca_plan reported                    */
+#define FARPCA_E_DEVICE (-3)     /* a HIP call failed                                              */
+#define FARPCA_E_NONFINITE (-4)  /* A holds NaN or Inf                                             */
+
+/* test matrices (Definitions 2.1-2.4) */
+#define FARPCA_GAUSSIAN 0         /* dense standard Gaussian G_j (farPCA, Algorithm 1)           */
+#define FARPCA_STD_BERNOULLI 1    /* standardized Bernoulli (B-p)/sqrt(p(1-p)) (Def. 2.3, Alg. 2) */
+#define FARPCA_SPARSE_SIGN 2      /* sparse sign (Def. 2.2; zeta > 0: zeta nonzeros per row)     */
+#define FARPCA_SPARSE_GAUSSIAN 3  /* sparse Gaussian B o G / sqrt(p) (Def. 2.4)                  */
+#define FARPCA_BERNOULLI 4        /* plain 0/1 Bernoulli (Def. 2.1, farPCAB of Section 5)        */
+
+#define FARPCA_DTYPE_F32 0
+
+typedef struct farpca_params {
+  int64_t m, n, lda;   /* A is m x n, row-major, leading dimension lda >= n                  */
+  int32_t a_dtype;     /* FARPCA_DTYPE_F32                                                   */
+  int32_t sketch;      /* FARPCA_GAUSSIAN ... FARPCA_BERNOULLI                               */
+  double tol;          /* relative Frobenius tolerance eps > 0 (fixed precision, Section 5.2):
+                          stop once E < eps^2 ||A||_F^2 (strict); ignored when rank > 0     */
+  int64_t rank;        /* k > 0: fixed-rank use (Section 5.1), blocks until l = j b >= k     */
+  int32_t block;       /* b in [1, 64]; 0 = min(max(20, floor(min(m,n)/100)), 50) (5.2/5.4)  */
+  int32_t power;       /* P >= 0 power steps per block (shift active for P > 2)              */
+  int64_t max_blocks;  /* 0 = ceil(min(m,n) / (2 b)) (Section 5.2); l is also capped at min(m,n) */
+  double sketch_p;     /* Bernoulli / density p in (0,1); 0 = p1 = max(1e-3, ln N/N) for
+                          FARPCA_STD_BERNOULLI, p2 = max(1e-3, 10/N) otherwise, N = max(m,n) */
+  int32_t sketch_zeta; /* FARPCA_SPARSE_SIGN: zeta in [1, b] nonzeros +-1/sqrt(zeta) per row
+                          of Omega_j; 0 = i.i.d. entries of Definition 2.2                   */
+  int32_t reserved0;
+  uint64_t seed;       /* key of the counter-based generator (Philox4x64-10)                 */
+} farpca_params;
+
+typedef struct farpca_info {
+  int64_t rank_l;        /* basis size l = blocks * b                                         */
+  int64_t rank_out;      /* columns written to U, S, V (k in fixed-rank use, else l)          */
+  int32_t blocks;        /* blocks computed                                                   */
+  int32_t status;        /* FARPCA_OK or FARPCA_NOT_CONVERGED                                 */
+  double norm_a2;        /* ||A||_F^2 (FP64)                                                  */
+  double err_indicator;  /* E = ||A||_F^2 - ||Q^T A||_F^2 after the last block (FP64)         */
+  int32_t eig_sweeps;    /* Jacobi sweeps of the final eigendecomposition                     */
+  int32_t dropped;       /* nonzero if a block direction was dropped as numerically dependent
+                            (its column of U, V is zero and its singular value 0)     */
+} farpca_info;
+
+typedef struct farpca_plan_s farpca_plan_t;
+
+/* Validate parameters and size the work.  On success *out holds a new plan,
+ * *l_max the largest basis size the run can reach (U, V need l_max columns,
+ * S l_max entries) and *workspace_bytes the device workspace farpca_run needs.
+ * Returns FARPCA_OK or FARPCA_E_INVALID. */
+int farpca_plan(const farpca_params *params, farpca_plan_t **out, int64_t *l_max,
+                size_t *workspace_bytes);
+
+/* Run the method (Algorithms 1/2 with the steps of the plan).
+ *  dA     device, m x n FP32 (lda), read only
+ *  dWork  device workspace, >= workspace_bytes, 256-byte aligned, contents ignored
+ *  dU     device, m x l_max FP32 (leading dimension l_max): left singular vectors
+ *  dS     device, l_max FP64: singular values, descending
+ *  dV     device, n x l_max FP32 (leading dimension l_max): right singular vectors
+ *  info   host, filled on return (may be NULL)
+ *  dEhist device, l_max / b FP64 or NULL: E after every block
+ * Only the first info->rank_out columns / entries of U, S, V are written. */
+int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_bytes, void *dU,
+               double *dS, void *dV, farpca_info *info, double *dEhist, void *stream);
+
+void farpca_free(farpca_plan_t *plan);
+const char *farpca_status_str(int status);
+
+/* ---- step entry points (same kernels as farpca_run; used by the parity tests)
+ * farpca_omega: test matrix Omega_j of block j (blocks count from 0).
+ *   dMask  device n x uint64: bit c set iff entry (r, c) is nonzero
+ *   dNeg   device n x uint64: bit c set iff entry (r, c) is negative
+ *   dDense device n x 64 FP32: the matrix the sketch multiplies by, i.e. the
+ *          definition's values (standardized Bernoulli: B_j - p, the unscaled
+ *          form of Algorithm 2); columns >= b are zero.
+ * farpca_sketch: dS (m x 64 FP32, columns >= b zero) = A * dDense, computed by
+ *   the sparse gather kernel (dense GEMM for FARPCA_GAUSSIAN); standardized
+ *   Bernoulli: A B_j - z with z = A (p 1_n) (Section 3.1).
+ * Both need the workspace of farpca_plan. */
+int farpca_omega(farpca_plan_t *plan, int64_t block_j, void *dWork, size_t work_bytes,
+                 uint64_t *dMask, uint64_t *dNeg, float *dDense, void *stream);
+int farpca_sketch(farpca_plan_t *plan, const void *dA, int64_t block_j, void *dWork,
+                  size_t work_bytes, float *dS, void *stream);
+
+/* FP32 matrix-core products used by the loop (N <= 64, C row-major ldc):
+ *  farpca_gemm_nn: C[M x N] = A[M x K] X[K x N]       (A lda, X ldx)
+ *  farpca_gemm_tn: C[M x N] = A^T Y, A is K x M       (A lda, Y ldy)
+ * dPart: device scratch of farpca_gemm_scratch_bytes(M) bytes (split-K partials). */
+size_t farpca_gemm_scratch_bytes(int64_t M);
+int farpca_gemm_nn(const float *dA, int64_t lda, const float *dX, int64_t ldx, float *dC,
+                   int64_t ldc, int64_t M, int64_t N, int64_t K, float *dPart, void *stream);
+int farpca_gemm_tn(const float *dA, int64_t lda, const float *dY, int64_t ldy, float *dC,
+                   int64_t ldc, int64_t M, int64_t N, int64_t K, float *dPart, void *stream);
+
+/* FP64 symmetric eigendecomposition (block Jacobi) of K (l x l, row-major):
+ * dW (l) descending, dV (l x l) eigenvectors in columns.  dWork holds
+ * farpca_eig_scratch_bytes(l) bytes.  Returns the sweep count (>= 0) or an error. */
+size_t farpca_eig_scratch_bytes(int64_t l);
+int farpca_eig(const double *dK, int64_t l, double *dW, double *dV, void *dWork, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FARPCA_H_ */

@@ -23,4 +23,6 @@ from .omega import (  # noqa: F401
     SKETCHES, omega_dense, bernoulli_mask, sparse_sign_fixed_mask_signs,
     threshold32, default_p, sketch_scale,
 )
-from .farpca import FarpcaParams, farpca, eig_svd, default_block, default_maxit  # noqa: F401
+from .farpca import (  # noqa: F401
+    FarpcaParams, farpca, eig_svd, default_block, default_maxit, projection_svd,
+)

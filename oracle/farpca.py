@@ -201,3 +201,12 @@ def farpca(a: np.ndarray, params: FarpcaParams, keep_bases: bool = False,
     if keep_bases:
         res.Y, res.W = y, w_big
     return res
+
+
+def projection_svd(a: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Singular values (descending) of C = Q^T A with Q an orthonormal basis of
+    range(Y): the direct SVD of Section 2.1 written out plainly (Householder QR
+    and LAPACK SVD), without the Gram matrices Z and T.  Used as the
+    definition the final step reaches for a given basis."""
+    q, _ = np.linalg.qr(np.asarray(y, dtype=np.float64))
+    return np.linalg.svd(q.T @ np.asarray(a, dtype=np.float64), compute_uv=False)

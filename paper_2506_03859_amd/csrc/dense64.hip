@@ -1,0 +1,505 @@
+// FP64 work on the small dimensions of the method: b x b Gram matrices and
+// their Cholesky factors (the orthonormalisation that replaces eigSVD, and the
+// basis extension of the indicator step), the setup pass (||A||_F^2 and, for
+// the standardized Bernoulli matrix, z = A (p 1_n)), and the indicator update
+// E = ||A||_F^2 - sum_j ||C_j||_F^2 (the identity of Section 2.1).
+// All reductions use a fixed partition and a fixed order: results are
+// bitwise repeatable.
+#include "internal.h"
+
+namespace farpca_int {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------ Gram
+// part[blk][i][j] = sum over rows k of block blk of X[k][i] X[k][j] (FP64).
+constexpr int kGramRows = 32;
+
+__global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ X, int64_t ldx,
+                                                   int64_t K, int b, int64_t rows_per_blk,
+                                                   double *__restrict__ part) {
+  __shared__ float xs[kGramRows][kMaxBlock + 1];
+  const int t = threadIdx.x;
+  const int ti = (t >> 4) * 4, tj = (t & 15) * 4;   // 4x4 output sub-block
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+  const int64_t k_begin = (int64_t)blockIdx.x * rows_per_blk;
+  int64_t k_end = k_begin + rows_per_blk;
+  if (k_end > K) k_end = K;
+  for (int64_t k0 = k_begin; k0 < k_end; k0 += kGramRows) {
+    __syncthreads();
+    for (int e = t; e < kGramRows * kMaxBlock; e += 256) {
+      const int r = e / kMaxBlock, c = e % kMaxBlock;
+      const int64_t k = k0 + r;
+      xs[r][c] = (k < k_end && c < b) ? X[k * ldx + c] : 0.0f;
+    }
+    __syncthreads();
+    for (int r = 0; r < kGramRows; ++r) {
+      double xi[4], xj[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) { xi[a] = (double)xs[r][ti + a]; xj[a] = (double)xs[r][tj + a]; }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = fma(xi[a], xj[c], acc[a][c]);
+    }
+  }
+  double *o = part + (int64_t)blockIdx.x * kMaxBlock * kMaxBlock;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o[(ti + a) * kMaxBlock + tj + c] = acc[a][c];
+}
+
+__global__ void gram_reduce_kernel(const double *__restrict__ part, int nblk, int b,
+                                   double *__restrict__ G) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kMaxBlock * kMaxBlock) return;
+  const int i = e / kMaxBlock, j = e % kMaxBlock;
+  double s = 0.0;
+  for (int q = 0; q < nblk; ++q) s += part[(int64_t)q * kMaxBlock * kMaxBlock + e];
+  G[e] = (i < b && j < b) ? s : 0.0;
+}
+
+int gram_num_partials(int64_t K) {
+  int64_t rows = (K + 255) / 256;
+  rows = ((rows + kGramRows - 1) / kGramRows) * kGramRows;
+  if (rows < kGramRows) rows = kGramRows;
+  return (int)((K + rows - 1) / rows);
+}
+
+void launch_gram(const float *X, int64_t ldx, int64_t K, int b, double *part, double *G,
+                 hipStream_t st) {
+  int64_t rows = (K + 255) / 256;
+  rows = ((rows + kGramRows - 1) / kGramRows) * kGramRows;
+  if (rows < kGramRows) rows = kGramRows;
+  const int nblk = (int)((K + rows - 1) / rows);
+  hipLaunchKernelGGL(gram_kernel, dim3(nblk), dim3(256), 0, st, X, ldx, K, b, rows, part);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(kMaxBlock * kMaxBlock / 256), dim3(256), 0, st, part,
+                     nblk, b, G);
+}
+
+// --------------------------------------------------------- Cholesky + inverse
+// G (kMaxBlock x kMaxBlock, FP64, valid b x b) = R^T R; Rinv = R^{-1} (upper),
+// so that X Rinv has orthonormal columns spanning X.  A column whose pivot
+// after elimination falls to drop_rel * (its own diagonal) or below is
+// numerically dependent on the previous ones (for FP32 data the residual is
+// rounding noise): it is dropped - its column of Rinv is zero, so the
+// corresponding output column is exactly zero - and it is not used to
+// eliminate later columns.  flags[0] |= 1 when a column is dropped.  (The
+// method's Z^{-1} is read as the pseudo-inverse on such directions.)
+__global__ __launch_bounds__(64) void chol_inv_kernel(const double *__restrict__ G, int b,
+                                                      double drop_rel, double *__restrict__ Rinv,
+                                                      int *__restrict__ flags) {
+  __shared__ double a[kMaxBlock][kMaxBlock + 1];
+  __shared__ double ri[kMaxBlock][kMaxBlock + 1];
+  __shared__ double dg[kMaxBlock];
+  __shared__ int dropped[kMaxBlock];
+  const int t = threadIdx.x;
+  for (int i = 0; i < kMaxBlock; ++i) a[i][t] = G[i * kMaxBlock + t];
+  __syncthreads();
+  dg[t] = a[t][t];
+  dropped[t] = 0;
+  __syncthreads();
+  // right-looking Cholesky on the upper triangle: a[k][j] becomes R[k][j]
+  for (int k = 0; k < b; ++k) {
+    if (t == 0) {
+      const double piv = a[k][k];
+      if (!(piv > drop_rel * dg[k]) || !(piv > 0.0)) {   // also catches NaN
+        dropped[k] = 1;
+        a[k][k] = 1.0;
+        atomicOr(flags, 1);
+      } else {
+        a[k][k] = sqrt(piv);
+      }
+    }
+    __syncthreads();
+    if (t > k && t < b) a[k][t] = dropped[k] ? 0.0 : a[k][t] / a[k][k];
+    __syncthreads();
+    if (t > k && t < b && !dropped[k]) {
+      const double rkt = a[k][t];
+      for (int i = k + 1; i <= t; ++i) a[i][t] -= a[k][i] * rkt;
+    }
+    __syncthreads();
+  }
+  // inverse of the upper factor, column j by thread j (dropped columns zero)
+  if (t < b && !dropped[t]) {
+    const int j = t;
+    for (int i = 0; i < kMaxBlock; ++i) ri[i][j] = 0.0;
+    ri[j][j] = 1.0 / a[j][j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= j; ++k) s = fma(a[i][k], ri[k][j], s);
+      ri[i][j] = dropped[i] ? 0.0 : -s / a[i][i];
+    }
+  } else {
+    for (int i = 0; i < kMaxBlock; ++i) ri[i][t] = 0.0;
+  }
+  __syncthreads();
+  for (int i = 0; i < kMaxBlock; ++i) Rinv[i * kMaxBlock + t] = ri[i][t];
+}
+
+void launch_chol_inv(const double *G, int b, double drop_rel, double *Rinv, int *flags,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(64), 0, st, G, b, drop_rel, Rinv, flags);
+}
+
+// ------------------------------------------------------------ small apply
+// Y[K x b] = X[K x b] * M[b x b] (M FP64, kMaxBlock x kMaxBlock), FP64 sums.
+__global__ __launch_bounds__(256) void apply_small_kernel(const float *__restrict__ X, int64_t ldx,
+                                                          int64_t K, int b,
+                                                          const double *__restrict__ Mg,
+                                                          float *__restrict__ Y, int64_t ldy) {
+  __shared__ double Ms[kMaxBlock][kMaxBlock];
+  __shared__ float xs[64][kMaxBlock + 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256) Ms[e / kMaxBlock][e % kMaxBlock] = Mg[e];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  for (int e = t; e < 64 * kMaxBlock; e += 256) {
+    const int r = e / kMaxBlock, c = e % kMaxBlock;
+    const int64_t k = r0 + r;
+    xs[r][c] = (k < K && c < b) ? X[k * ldx + c] : 0.0f;
+  }
+  __syncthreads();
+  const int r = t >> 2, cq = (t & 3) * 16;
+  double acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+  for (int k = 0; k < b; ++k) {
+    const double x = (double)xs[r][k];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = fma(x, Ms[k][cq + c], acc[c]);
+  }
+  const int64_t row = r0 + r;
+  if (row < K) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (cq + c < b) Y[row * ldy + cq + c] = (float)acc[c];
+  }
+}
+
+void launch_apply_small(const float *X, int64_t ldx, int64_t K, int b, const double *M,
+                        float *Y, int64_t ldy, hipStream_t st) {
+  hipLaunchKernelGGL(apply_small_kernel, dim3((unsigned)((K + 63) / 64)), dim3(256), 0, st, X, ldx,
+                     K, b, M, Y, ldy);
+}
+
+// ------------------------------------------------------------ setup pass
+// One wave per row at a time; each workgroup (4 waves) owns a fixed row range.
+constexpr int kSetupWgs = 1024;
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void setup_kernel(const float *__restrict__ A, int64_t lda,
+                                                    int64_t m, int64_t n, int64_t rows_per_wg,
+                                                    double *__restrict__ part_sq,
+                                                    double *__restrict__ rowsum,
+                                                    int *__restrict__ flags) {
+  __shared__ double wsum[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t rb = (int64_t)blockIdx.x * rows_per_wg;
+  int64_t re = rb + rows_per_wg;
+  if (re > m) re = m;
+  double sq = 0.0;
+  bool bad = false;
+  for (int64_t row = rb + wave; row < re; row += 4) {
+    const float *p = A + row * lda;
+    double s = 0.0, q = 0.0;
+    if (VEC) {
+      const int64_t n4 = n / 4;
+      for (int64_t c = lane; c < n4; c += 64) {
+        const float4 v = reinterpret_cast<const float4 *>(p)[c];
+        const double x0 = v.x, x1 = v.y, x2 = v.z, x3 = v.w;
+        s += (x0 + x1) + (x2 + x3);
+        q = fma(x0, x0, q); q = fma(x1, x1, q); q = fma(x2, x2, q); q = fma(x3, x3, q);
+        bad |= !isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w);
+      }
+      for (int64_t c = n4 * 4 + lane; c < n; c += 64) {
+        const double x = p[c];
+        s += x; q = fma(x, x, q);
+        bad |= !isfinite(p[c]);
+      }
+    } else {
+      for (int64_t c = lane; c < n; c += 64) {
+        const double x = p[c];
+        s += x; q = fma(x, x, q);
+        bad |= !isfinite(p[c]);
+      }
+    }
+    s = wave_sum(s);
+    q = wave_sum(q);
+    if (lane == 0) rowsum[row] = s;
+    sq += q;
+  }
+  if (bad) atomicOr(flags, 2);
+  if (lane == 0) wsum[wave] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) part_sq[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+}
+
+int setup_num_partials(int64_t m) {
+  const int64_t rows = (m + kSetupWgs - 1) / kSetupWgs;
+  return (int)((m + rows - 1) / rows);
+}
+
+void launch_setup(const float *A, int64_t lda, int64_t m, int64_t n, double *part_sq,
+                  double *rowsum, int *flags, hipStream_t st) {
+  const int64_t rows = (m + kSetupWgs - 1) / kSetupWgs;
+  const int nwg = (int)((m + rows - 1) / rows);
+  const bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  if (vec) hipLaunchKernelGGL((setup_kernel<true>), dim3(nwg), dim3(256), 0, st, A, lda, m, n, rows,
+                              part_sq, rowsum, flags);
+  else hipLaunchKernelGGL((setup_kernel<false>), dim3(nwg), dim3(256), 0, st, A, lda, m, n, rows,
+                          part_sq, rowsum, flags);
+}
+
+// ------------------------------------------------------ fixed-order sums
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double *__restrict__ part, int count,
+                                                           double *__restrict__ out, int mode,
+                                                           double *__restrict__ hist, int64_t j) {
+  __shared__ double ws[4];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int q = t; q < count; q += 256) s += part[q];
+  s = wave_sum(s);
+  if ((t & 63) == 0) ws[t >> 6] = s;
+  __syncthreads();
+  if (t == 0) {
+    const double tot = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+    if (mode == 0) {
+      out[0] = tot;
+    } else {          // indicator: E -= tot, record history
+      const double e = out[0] - tot;
+      out[0] = e;
+      if (hist) hist[j] = e;
+    }
+  }
+}
+
+void launch_sum_partials(const double *part, int count, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, part, count, out, 0,
+                     (double *)nullptr, (int64_t)0);
+}
+
+void launch_indicator_update(const double *part, int count, double *E, double *E_hist, int64_t j,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, part, count, E, 1, E_hist, j);
+}
+
+__global__ void scale_rowsum_kernel(const double *__restrict__ rowsum, int64_t m, double p,
+                                    float *__restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) z[i] = (float)(p * rowsum[i]);
+}
+
+void launch_scale_rowsum(const double *rowsum, int64_t m, double p, float *z, hipStream_t st) {
+  hipLaunchKernelGGL(scale_rowsum_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                     rowsum, m, p, z);
+}
+
+// ||X||_F^2 of a K x b block, one partial per workgroup (fixed partition).
+constexpr int kSqWgs = 256;
+__global__ __launch_bounds__(256) void sqnorm_kernel(const float *__restrict__ X, int64_t ldx,
+                                                     int64_t K, int b, int64_t rows_per_wg,
+                                                     double *__restrict__ part) {
+  __shared__ double ws[4];
+  const int t = threadIdx.x;
+  const int64_t rb = (int64_t)blockIdx.x * rows_per_wg;
+  int64_t re = rb + rows_per_wg;
+  if (re > K) re = K;
+  double q = 0.0;
+  const int c = t & 63;
+  for (int64_t r = rb + (t >> 6); r < re; r += 4) {
+    if (c < b) { const double x = X[r * ldx + c]; q = fma(x, x, q); }
+  }
+  q = wave_sum(q);
+  if ((t & 63) == 0) ws[t >> 6] = q;
+  __syncthreads();
+  if (t == 0) part[blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+int sqnorm_num_partials(int64_t K) {
+  const int64_t rows = (K + kSqWgs - 1) / kSqWgs;
+  return (int)((K + rows - 1) / rows);
+}
+
+void launch_sqnorm(const float *X, int64_t ldx, int64_t K, int b, double *part, hipStream_t st) {
+  const int64_t rows = (K + kSqWgs - 1) / kSqWgs;
+  const int nwg = (int)((K + rows - 1) / rows);
+  hipLaunchKernelGGL(sqnorm_kernel, dim3(nwg), dim3(256), 0, st, X, ldx, K, b, rows, part);
+}
+
+// ------------------------------------------------------------ block helpers
+__global__ void copy_block_kernel(const float *__restrict__ X, int64_t ldx, int64_t K, int b,
+                                  float *__restrict__ D, int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = idx / 64, c = idx % 64;
+  if (r < K && c < b) D[r * ldd + c] = X[r * ldx + c];
+}
+
+void launch_copy_block(const float *X, int64_t ldx, int64_t K, int b, float *dst, int64_t ldd,
+                       hipStream_t st) {
+  const int64_t total = K * 64;
+  hipLaunchKernelGGL(copy_block_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, X,
+                     ldx, K, b, dst, ldd);
+}
+
+__global__ void axpy_block_kernel(float *__restrict__ X, int64_t ldx, const float *__restrict__ G,
+                                  int64_t ldg, int64_t K, int b, const double *__restrict__ alpha) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = idx / 64, c = idx % 64;
+  const float a = (float)alpha[0];
+  if (r < K && c < b && a != 0.0f) X[r * ldx + c] -= a * G[r * ldg + c];
+}
+
+void launch_axpy_block(float *X, int64_t ldx, const float *G, int64_t ldg, int64_t K, int b,
+                       const double *alpha_dev, hipStream_t st) {
+  const int64_t total = K * 64;
+  hipLaunchKernelGGL(axpy_block_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, X,
+                     ldx, G, ldg, K, b, alpha_dev);
+}
+
+// Shift update of the power iteration (Algorithm 1 / 2): with s the smallest
+// singular value of the block (sqrt of the smallest Gram eigenvalue),
+// if alpha < s then alpha = (s + alpha) / 2.
+__global__ void alpha_update_kernel(const double *__restrict__ w, int b, double *__restrict__ alpha) {
+  double lmin = w[b - 1];           // eigenvalues in descending order
+  if (lmin < 0.0) lmin = 0.0;
+  const double s = sqrt(lmin);
+  if (alpha[0] < s) alpha[0] = (s + alpha[0]) * 0.5;
+}
+
+void launch_alpha_update(const double *w, int b, double *alpha, hipStream_t st) {
+  hipLaunchKernelGGL(alpha_update_kernel, dim3(1), dim3(1), 0, st, w, b, alpha);
+}
+
+}  // namespace farpca_int
+
+namespace farpca_int {
+
+// ------------------------------------------------ final Gram K = X^T X (l x l)
+// X is n x l FP32 (ldx).  Upper 64 x 64 tiles only; grid z splits the rows of
+// X (partials part[z][lp][lp], reduced in a fixed order and mirrored).
+__global__ __launch_bounds__(256) void gram_big_kernel(const float *__restrict__ X, int64_t ldx,
+                                                       int64_t n, int64_t l, int64_t lp,
+                                                       int64_t rows_per_split,
+                                                       double *__restrict__ part) {
+  const int ti_blk = blockIdx.x, tj_blk = blockIdx.y;
+  if (tj_blk < ti_blk) return;
+  __shared__ float xi_s[kGramRows][65];
+  __shared__ float xj_s[kGramRows][65];
+  const int t = threadIdx.x;
+  const int ti = (t >> 4) * 4, tj = (t & 15) * 4;
+  const int64_t ci0 = (int64_t)ti_blk * 64, cj0 = (int64_t)tj_blk * 64;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+  const int64_t kb = (int64_t)blockIdx.z * rows_per_split;
+  int64_t ke = kb + rows_per_split;
+  if (ke > n) ke = n;
+  for (int64_t k0 = kb; k0 < ke; k0 += kGramRows) {
+    __syncthreads();
+    for (int e = t; e < kGramRows * 64; e += 256) {
+      const int r = e / 64, c = e % 64;
+      const int64_t k = k0 + r;
+      xi_s[r][c] = (k < ke && ci0 + c < l) ? X[k * ldx + ci0 + c] : 0.0f;
+      xj_s[r][c] = (k < ke && cj0 + c < l) ? X[k * ldx + cj0 + c] : 0.0f;
+    }
+    __syncthreads();
+    for (int r = 0; r < kGramRows; ++r) {
+      double xi[4], xj[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) { xi[a] = (double)xi_s[r][ti + a]; xj[a] = (double)xj_s[r][tj + a]; }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = fma(xi[a], xj[c], acc[a][c]);
+    }
+  }
+  double *o = part + (int64_t)blockIdx.z * lp * lp;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o[(ci0 + ti + a) * lp + cj0 + tj + c] = acc[a][c];
+}
+
+__global__ void gram_big_reduce_kernel(const double *__restrict__ part, int nsplit, int64_t l,
+                                       int64_t lp, double *__restrict__ K) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= l * l) return;
+  int64_t i = e / l, j = e % l;
+  if (i / 64 > j / 64) { const int64_t s = i; i = j; j = s; }   // read the upper tile
+  double s = 0.0;
+  for (int q = 0; q < nsplit; ++q) s += part[(int64_t)q * lp * lp + i * lp + j];
+  K[e] = s;
+}
+
+static int gram_big_split(int64_t n, int64_t l) {
+  const int64_t lp = (l + 63) / 64 * 64;
+  const int64_t tiles = (lp / 64) * (lp / 64 + 1) / 2;
+  int64_t s = (1024 + tiles - 1) / tiles;
+  if (s > n / 256) s = n / 256;
+  const int64_t cap = (int64_t)(256ll << 20) / (lp * lp * 8);   // partials <= 256 MiB
+  if (s > cap) s = cap;
+  if (s > 32) s = 32;
+  if (s < 1) s = 1;
+  return (int)s;
+}
+
+size_t gram_big_workspace_bytes(int64_t n, int64_t l) {
+  const int64_t lp = (l + 63) / 64 * 64;
+  return (size_t)gram_big_split(n, l) * lp * lp * 8;   // >= one full partial
+}
+
+void launch_gram_big(const float *X, int64_t ldx, int64_t n, int64_t l, double *K, void *work,
+                     size_t work_bytes, hipStream_t st) {
+  const int64_t lp = (l + 63) / 64 * 64;
+  int s = gram_big_split(n, l);
+  const int64_t fit = (int64_t)(work_bytes / ((size_t)lp * lp * 8));
+  if (s > fit) s = (int)(fit < 1 ? 1 : fit);
+  int64_t rows = (n + s - 1) / s;
+  rows = (rows + kGramRows - 1) / kGramRows * kGramRows;
+  const int ns = (int)((n + rows - 1) / rows);
+  double *part = static_cast<double *>(work);
+  dim3 grid((unsigned)(lp / 64), (unsigned)(lp / 64), (unsigned)ns);
+  hipLaunchKernelGGL(gram_big_kernel, grid, dim3(256), 0, st, X, ldx, n, l, lp, rows, part);
+  hipLaunchKernelGGL(gram_big_reduce_kernel, dim3((unsigned)((l * l + 255) / 256)), dim3(256), 0, st,
+                     part, ns, l, lp, K);
+}
+
+// Y[r][c] = (float)(X[r][c] * f(c)), f = 1 or 1/s[c] (0 where s[c] == 0).
+__global__ void convert_kernel(const double *__restrict__ X, int64_t rows, int64_t cols, int64_t ldx,
+                               const double *__restrict__ s, float *__restrict__ Y, int64_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t r = e / cols, c = e % cols;
+  double f = 1.0;
+  if (s) f = (s[c] > 0.0) ? 1.0 / s[c] : 0.0;
+  Y[r * ldy + c] = (float)(X[r * ldx + c] * f);
+}
+
+void launch_convert_f64_f32(const double *X, int64_t rows, int64_t cols, int64_t ldx,
+                            const double *s, float *Y, int64_t ldy, hipStream_t st) {
+  const int64_t tot = rows * cols;
+  hipLaunchKernelGGL(convert_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, X, rows,
+                     cols, ldx, s, Y, ldy);
+}
+
+__global__ void sqrt_clip_kernel(const double *__restrict__ w, int64_t l, double *__restrict__ s) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < l) s[i] = w[i] > 0.0 ? sqrt(w[i]) : 0.0;
+}
+
+void launch_sqrt_clip(const double *w, int64_t l, double *s, hipStream_t st) {
+  hipLaunchKernelGGL(sqrt_clip_kernel, dim3((unsigned)((l + 255) / 256)), dim3(256), 0, st, w, l, s);
+}
+
+}  // namespace farpca_int

@@ -1,0 +1,350 @@
+// FP64 symmetric eigensolver for the final small decomposition of the method
+// (Algorithm 1/2 final steps: the eigendecomposition whose square roots are
+// the singular values of C = Q^T A), and for the b x b Gram of the power block
+// (smallest singular value for the shift).
+//
+// Method: two-sided cyclic Jacobi.  Small matrices (<= 64) are solved by one
+// workgroup entirely in LDS.  Larger ones use block Jacobi: the index set is
+// cut into blocks of 16, blocks are paired by a round-robin tournament, every
+// pair's 32 x 32 principal submatrix is diagonalised in LDS (one workgroup per
+// pair), and the whole matrix is then rotated block-by-block,
+// M[S_p, S_q] <- R_p^T M[S_p, S_q] R_q, V[:, S_q] <- V[:, S_q] R_q - every
+// output block depends only on the same input block, so the update runs in
+// place with one workgroup per block.  Sweeps repeat until every off-diagonal
+// entry is negligible relative to its diagonal pair.  Padding rows/columns are
+// exactly zero and never couple (their rotations are the identity).
+#include "internal.h"
+
+namespace farpca_int {
+
+constexpr double kJacobiRel = 1e-14;
+constexpr int kInnerMaxSweeps = 30;
+
+__device__ __forceinline__ bool negligible(double apq, double app, double aqq, double floor_abs) {
+  const double x = fabs(apq);
+  return x == 0.0 || x <= kJacobiRel * sqrt(fabs(app) * fabs(aqq)) || x <= floor_abs;
+}
+
+__device__ __forceinline__ int rr_player(int pos, int step, int n) {
+  // circle method: position 0 fixed, the others rotate
+  return pos == 0 ? 0 : ((pos - 1 + step) % (n - 1)) + 1;
+}
+
+// Cyclic Jacobi on an S x S symmetric matrix a (LDS, stride LD) accumulating
+// rotations into v (LDS, stride LD, holds the starting orthogonal matrix).
+template <int S, int LD, int NT>
+__device__ void jacobi_lds(double *a, double *v, double floor_abs) {
+  constexpr int H = S / 2;
+  __shared__ double cs_c[H], cs_s[H], cs_t[H];
+  __shared__ int cs_p[H], cs_q[H], cs_on[H];
+  __shared__ int any_rot;
+  const int tid = threadIdx.x;
+  for (int sweep = 0; sweep < kInnerMaxSweeps; ++sweep) {
+    if (tid == 0) any_rot = 0;
+    __syncthreads();
+    for (int step = 0; step < S - 1; ++step) {
+      if (tid < H) {
+        const int p = rr_player(tid, step, S), q = rr_player(S - 1 - tid, step, S);
+        const double app = a[p * LD + p], aqq = a[q * LD + q], apq = a[p * LD + q];
+        double c = 1.0, s = 0.0, t = 0.0;
+        int on = 0;
+        if (!negligible(apq, app, aqq, floor_abs)) {
+          const double theta = (aqq - app) / (2.0 * apq);
+          t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(fma(theta, theta, 1.0)));
+          c = 1.0 / sqrt(fma(t, t, 1.0));
+          s = t * c;
+          on = 1;
+          any_rot = 1;
+        }
+        cs_c[tid] = c; cs_s[tid] = s; cs_t[tid] = t; cs_p[tid] = p; cs_q[tid] = q; cs_on[tid] = on;
+      }
+      __syncthreads();
+      // A <- J^T A J, one 2x2 block (pair ia rows, pair ib columns) at a time
+      for (int e = tid; e < H * H; e += NT) {
+        const int ia = e / H, ib = e % H;
+        if (!cs_on[ia] && !cs_on[ib]) continue;
+        const int pa = cs_p[ia], qa = cs_q[ia], pb = cs_p[ib], qb = cs_q[ib];
+        if (ia == ib) {
+          const double apq = a[pa * LD + qa];
+          const double t = cs_t[ia];
+          a[pa * LD + pa] -= t * apq;
+          a[qa * LD + qa] += t * apq;
+          a[pa * LD + qa] = 0.0;
+          a[qa * LD + pa] = 0.0;
+          continue;
+        }
+        const double ca = cs_c[ia], sa = cs_s[ia], cb = cs_c[ib], sb = cs_s[ib];
+        const double x11 = a[pa * LD + pb], x12 = a[pa * LD + qb];
+        const double x21 = a[qa * LD + pb], x22 = a[qa * LD + qb];
+        const double y11 = ca * x11 - sa * x21, y12 = ca * x12 - sa * x22;
+        const double y21 = sa * x11 + ca * x21, y22 = sa * x12 + ca * x22;
+        a[pa * LD + pb] = cb * y11 - sb * y12;
+        a[pa * LD + qb] = sb * y11 + cb * y12;
+        a[qa * LD + pb] = cb * y21 - sb * y22;
+        a[qa * LD + qb] = sb * y21 + cb * y22;
+      }
+      // V <- V J
+      for (int e = tid; e < S * H; e += NT) {
+        const int r = e / H, ib = e % H;
+        if (!cs_on[ib]) continue;
+        const int pb = cs_p[ib], qb = cs_q[ib];
+        const double c = cs_c[ib], s = cs_s[ib];
+        const double vp = v[r * LD + pb], vq = v[r * LD + qb];
+        v[r * LD + pb] = c * vp - s * vq;
+        v[r * LD + qb] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    if (!any_rot) break;
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------- small (<= 64)
+constexpr int kSmallLd = 65;
+
+__global__ __launch_bounds__(256) void eig_small_kernel(const double *__restrict__ K, int s, int ldk,
+                                                        double *__restrict__ w, double *__restrict__ V,
+                                                        int ldv) {
+  __shared__ double a[64 * kSmallLd];
+  __shared__ double v[64 * kSmallLd];
+  __shared__ double fl;
+  __shared__ int perm[64];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e / 64, j = e % 64;
+    a[i * kSmallLd + j] = (i < s && j < s) ? K[i * ldk + j] : 0.0;
+    v[i * kSmallLd + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < s; ++i) mx = fmax(mx, fabs(a[i * kSmallLd + i]));
+    fl = mx * 1e-300;
+  }
+  __syncthreads();
+  jacobi_lds<64, kSmallLd, 256>(a, v, fl);
+  __syncthreads();
+  // descending order among the first s positions (ties by index)
+  if (tid < s) {
+    const double wi = a[tid * kSmallLd + tid];
+    int rank = 0;
+    for (int j = 0; j < s; ++j) {
+      const double wj = a[j * kSmallLd + j];
+      rank += (wj > wi) || (wj == wi && j < tid);
+    }
+    perm[rank] = tid;
+  }
+  __syncthreads();
+  if (tid < s) w[tid] = a[perm[tid] * kSmallLd + perm[tid]];
+  for (int e = tid; e < s * s; e += 256) {
+    const int r = e / s, k = e % s;
+    V[r * ldv + k] = v[r * kSmallLd + perm[k]];
+  }
+}
+
+void launch_eig_small(const double *K, int s, int ldk, double *w, double *Vout, int ldv,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(eig_small_kernel, dim3(1), dim3(256), 0, st, K, s, ldk, w, Vout, ldv);
+}
+
+// ------------------------------------------------------------- block Jacobi
+constexpr int kBlk = 16;           // block width
+constexpr int kSub = 2 * kBlk;     // subproblem size
+constexpr int kSubLd = kSub + 1;
+
+__device__ __forceinline__ int sub_index(int u, int bi, int bj) {
+  return u < kBlk ? bi * kBlk + u : bj * kBlk + (u - kBlk);
+}
+
+// One workgroup per pair: diagonalise M[S, S], S = block(bi) U block(bj).
+__global__ __launch_bounds__(64) void bj_pair_kernel(const double *__restrict__ M, int64_t lp, int nb,
+                                                     int step, double *__restrict__ R,
+                                                     const double *__restrict__ floor_abs) {
+  __shared__ double a[kSub * kSubLd];
+  __shared__ double v[kSub * kSubLd];
+  const int pair = blockIdx.x, tid = threadIdx.x;
+  const int bi = rr_player(pair, step, nb), bj = rr_player(nb - 1 - pair, step, nb);
+  for (int e = tid; e < kSub * kSub; e += 64) {
+    const int u = e / kSub, x = e % kSub;
+    a[u * kSubLd + x] = M[(int64_t)sub_index(u, bi, bj) * lp + sub_index(x, bi, bj)];
+    v[u * kSubLd + x] = (u == x) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  jacobi_lds<kSub, kSubLd, 64>(a, v, floor_abs[0]);
+  __syncthreads();
+  double *Rp = R + (int64_t)pair * kSub * kSub;
+  for (int e = tid; e < kSub * kSub; e += 64) Rp[e] = v[(e / kSub) * kSubLd + (e % kSub)];
+}
+
+// Rotate M (pair blocks) and V (row tiles x pair columns) in place.
+__global__ __launch_bounds__(256) void bj_update_kernel(double *__restrict__ M, double *__restrict__ V,
+                                                        int64_t lp, int nb, int step,
+                                                        const double *__restrict__ R) {
+  __shared__ double blk[kSub * kSubLd];
+  __shared__ double tmp[kSub * kSubLd];
+  __shared__ double rq[kSub * kSubLd];
+  __shared__ double rp[kSub * kSubLd];
+  const int npairs = nb / 2;
+  const int tid = threadIdx.x;
+  const int64_t nm = (int64_t)npairs * npairs;
+  const int64_t id = blockIdx.x;
+  const bool is_m = id < nm;
+  int p, q;
+  int64_t rowtile = 0;
+  if (is_m) { p = (int)(id / npairs); q = (int)(id % npairs); }
+  else { const int64_t k = id - nm; rowtile = k / npairs; q = (int)(k % npairs); p = -1; }
+  const int qi = rr_player(q, step, nb), qj = rr_player(nb - 1 - q, step, nb);
+  for (int e = tid; e < kSub * kSub; e += 256) {
+    rq[(e / kSub) * kSubLd + e % kSub] = R[(int64_t)q * kSub * kSub + e];
+  }
+  if (is_m) {
+    const int pi = rr_player(p, step, nb), pj = rr_player(nb - 1 - p, step, nb);
+    for (int e = tid; e < kSub * kSub; e += 256) {
+      const int u = e / kSub, x = e % kSub;
+      rp[u * kSubLd + x] = R[(int64_t)p * kSub * kSub + e];
+      blk[u * kSubLd + x] = M[(int64_t)sub_index(u, pi, pj) * lp + sub_index(x, qi, qj)];
+    }
+    __syncthreads();
+    // tmp = blk * R_q
+    for (int e = tid; e < kSub * kSub; e += 256) {
+      const int u = e / kSub, x = e % kSub;
+      double s = 0.0;
+      for (int k = 0; k < kSub; ++k) s = fma(blk[u * kSubLd + k], rq[k * kSubLd + x], s);
+      tmp[u * kSubLd + x] = s;
+    }
+    __syncthreads();
+    // M block = R_p^T * tmp
+    for (int e = tid; e < kSub * kSub; e += 256) {
+      const int u = e / kSub, x = e % kSub;
+      double s = 0.0;
+      for (int k = 0; k < kSub; ++k) s = fma(rp[k * kSubLd + u], tmp[k * kSubLd + x], s);
+      M[(int64_t)sub_index(u, pi, pj) * lp + sub_index(x, qi, qj)] = s;
+    }
+  } else {
+    const int64_t r0 = rowtile * kSub;
+    for (int e = tid; e < kSub * kSub; e += 256) {
+      const int u = e / kSub, x = e % kSub;
+      blk[u * kSubLd + x] = V[(r0 + u) * lp + sub_index(x, qi, qj)];
+    }
+    __syncthreads();
+    for (int e = tid; e < kSub * kSub; e += 256) {
+      const int u = e / kSub, x = e % kSub;
+      double s = 0.0;
+      for (int k = 0; k < kSub; ++k) s = fma(blk[u * kSubLd + k], rq[k * kSubLd + x], s);
+      V[(r0 + u) * lp + sub_index(x, qi, qj)] = s;
+    }
+  }
+}
+
+// Count off-diagonal entries that are not negligible; also floor = max|diag| * 1e-300.
+__global__ __launch_bounds__(1024) void bj_check_kernel(const double *__restrict__ M, int64_t lp,
+                                                        int *__restrict__ count,
+                                                        double *__restrict__ floor_abs) {
+  __shared__ double mx[1024];
+  const int tid = threadIdx.x;
+  double m = 0.0;
+  for (int64_t i = tid; i < lp; i += 1024) m = fmax(m, fabs(M[i * lp + i]));
+  mx[tid] = m;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (tid < s) mx[tid] = fmax(mx[tid], mx[tid + s]);
+    __syncthreads();
+  }
+  const double fl = mx[0] * 1e-300;
+  int c = 0;
+  for (int64_t e = tid; e < lp * lp; e += 1024) {
+    const int64_t i = e / lp, j = e % lp;
+    if (i < j && !negligible(M[i * lp + j], M[i * lp + i], M[j * lp + j], fl)) ++c;
+  }
+  if (c) atomicAdd(count, c);
+  if (tid == 0) floor_abs[0] = fl;
+}
+
+__global__ void bj_init_kernel(const double *__restrict__ K, int64_t l, int64_t lp,
+                               double *__restrict__ M, double *__restrict__ V) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= lp * lp) return;
+  const int64_t i = e / lp, j = e % lp;
+  M[e] = (i < l && j < l) ? K[i * l + j] : 0.0;
+  V[e] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ void bj_rank_kernel(const double *__restrict__ M, int64_t l, int64_t lp,
+                               int *__restrict__ perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= l) return;
+  const double wi = M[i * lp + i];
+  int64_t rank = 0;
+  for (int64_t j = 0; j < l; ++j) {
+    const double wj = M[j * lp + j];
+    rank += (wj > wi) || (wj == wi && j < i);
+  }
+  perm[rank] = (int)i;
+}
+
+__global__ void bj_gather_kernel(const double *__restrict__ M, const double *__restrict__ V,
+                                 int64_t l, int64_t lp, const int *__restrict__ perm,
+                                 double *__restrict__ w, double *__restrict__ Vout) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= l * l) return;
+  const int64_t r = e / l, k = e % l;
+  const int src = perm[k];
+  Vout[e] = V[r * lp + src];
+  if (r == 0) w[k] = M[(int64_t)src * lp + src];
+}
+
+static int64_t padded(int64_t l) { return (l + kSub - 1) / kSub * kSub; }
+
+size_t eig_workspace_bytes(int64_t l) {
+  const int64_t lp = padded(l);
+  const int64_t nb = lp / kBlk;
+  size_t bytes = 0;
+  bytes += (size_t)lp * lp * 8 * 2;                 // M, V
+  bytes += (size_t)(nb / 2) * kSub * kSub * 8;      // rotations
+  bytes += (size_t)lp * 4 + 64;                     // perm, counters
+  bytes += 256;
+  return bytes;
+}
+
+int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, hipStream_t st) {
+  if (l <= 64) {
+    launch_eig_small(K, (int)l, (int)l, w, Vout, (int)l, st);
+    return 1;
+  }
+  const int64_t lp = padded(l);
+  const int nb = (int)(lp / kBlk);
+  const int npairs = nb / 2;
+  char *p = static_cast<char *>(work);
+  double *M = reinterpret_cast<double *>(p); p += (size_t)lp * lp * 8;
+  double *V = reinterpret_cast<double *>(p); p += (size_t)lp * lp * 8;
+  double *R = reinterpret_cast<double *>(p); p += (size_t)npairs * kSub * kSub * 8;
+  int *perm = reinterpret_cast<int *>(p); p += (size_t)lp * 4;
+  p = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(p) + 63) & ~uintptr_t(63));
+  int *count = reinterpret_cast<int *>(p);
+  double *floor_abs = reinterpret_cast<double *>(p + 8);
+
+  const int64_t tot = lp * lp;
+  hipLaunchKernelGGL(bj_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, K, l, lp, M, V);
+  int sweeps = 0;
+  const int max_sweeps = 40;
+  for (; sweeps < max_sweeps; ++sweeps) {
+    hipMemsetAsync(count, 0, sizeof(int), st);
+    hipLaunchKernelGGL(bj_check_kernel, dim3(1), dim3(1024), 0, st, M, lp, count, floor_abs);
+    int h_count = 0;
+    hipMemcpyAsync(&h_count, count, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    if (h_count == 0) break;
+    for (int step = 0; step < nb - 1; ++step) {
+      hipLaunchKernelGGL(bj_pair_kernel, dim3(npairs), dim3(64), 0, st, M, lp, nb, step, R, floor_abs);
+      const int64_t nwg = (int64_t)npairs * npairs + (lp / kSub) * npairs;
+      hipLaunchKernelGGL(bj_update_kernel, dim3((unsigned)nwg), dim3(256), 0, st, M, V, lp, nb, step, R);
+    }
+  }
+  hipLaunchKernelGGL(bj_rank_kernel, dim3((unsigned)((l + 255) / 256)), dim3(256), 0, st, M, l, lp, perm);
+  hipLaunchKernelGGL(bj_gather_kernel, dim3((unsigned)((l * l + 255) / 256)), dim3(256), 0, st, M, V,
+                     l, lp, perm, w, Vout);
+  return sweeps;
+}
+
+}  // namespace farpca_int

@@ -1,0 +1,491 @@
+// Host orchestration and C-ABI of the accelerated farPCA loop (Algorithm 1 /
+// Algorithm 2 of arXiv 2506.03859) on one gfx950 GPU.
+//
+// Per block j (b columns):
+//   Omega_j from the counter-based generator (Definitions 2.1-2.4)
+//   S   = A Omega_j                 sparse gather kernel (dense MFMA product for
+//                                   the Gaussian matrix); standardized Bernoulli:
+//                                   A B_j - z, z = A (p 1_n) (Section 3.1)
+//   P >= 1, k = 1..P:
+//     T  <- (I - Q Q^T) T  (twice)   T = S for k = 1, T = A G otherwise
+//     X   = A^T T - alpha G          = A^T(AG) - W Z^{-1} W^T G - alpha G of
+//                                   Algorithm 1, evaluated with the orthonormal
+//                                   basis Q of Y (W Z^{-1} W^T = A^T Q Q^T A)
+//     G   = orth(X)                  CholeskyQR (3 passes, FP64 Gram); the shift
+//                                   update uses the block's smallest singular
+//                                   value (P > 2)
+//   Y_j = A G (P >= 1) or S (P = 0)
+//   Y_j <- (I - Q Q^T) Y_j (twice), Q_j = orth(Y_j), Q = [Q, Q_j]
+//   C_j^T = A^T Q_j, E = E - ||C_j||_F^2   (E = ||A||^2 - tr(T Z^{-1}) of
+//                                   Algorithm 1, since tr(T Z^{-1}) = ||Q^T A||_F^2)
+//   stop when E < tol^2 ||A||_F^2 (Section 5.2), l >= k (Section 5.1) or at the cap.
+// Final: K = C C^T (FP64), K = U~ diag(lambda) U~^T (Jacobi), Sigma = lambda^{1/2},
+//        U = Q U~, V = C^T U~ Sigma^{-1}  (the final steps of Algorithm 1 up to a
+//        rotation of the basis).
+// Every step runs in a kernel of this library; the host only sequences
+// launches and reads E (8 bytes) after each block.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/farpca.h"
+#include "internal.h"
+
+using namespace farpca_int;
+
+// squared relative pivot below which a block direction counts as dependent
+static constexpr double kDropRel = 1e-10;
+
+struct farpca_plan_s {
+  farpca_params prm;
+  int b;
+  int P;
+  int kind;
+  int zeta;
+  double p;
+  uint32_t thr;
+  double dense_scale;   // scale of Omega's nonzeros in the dense copy
+  float sketch_scale;   // scale applied to the sketch sums
+  int64_t maxblk;
+  int64_t lmax;
+  int64_t ldq;          // leading dimension of Q and C^T
+  int64_t nchunks;
+  // workspace layout (byte offsets)
+  size_t off_q, off_ct, off_s, off_y, off_x, off_g, off_om, off_mask, off_neg, off_colptr,
+      off_ent, off_z, off_rowsum, off_r, off_part, off_gpart, off_g64, off_rinv, off_w64,
+      off_v64, off_setup, off_sq, off_scal, off_ehist, off_kbig, off_eig, off_wfin, off_vfin,
+      off_u32, off_gbig, total;
+  size_t gbig_bytes;
+};
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Carver {
+  size_t cur = 0;
+  size_t take(size_t bytes) {
+    const size_t o = cur;
+    cur = align_up(cur + bytes);
+    return o;
+  }
+};
+
+#define HIP_OK(x)                                   \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) return FARPCA_E_DEVICE;   \
+  } while (0)
+
+int64_t imin(int64_t a, int64_t b) { return a < b ? a : b; }
+int64_t imax(int64_t a, int64_t b) { return a > b ? a : b; }
+
+struct Ws {
+  char *base;
+  template <typename T>
+  T *at(size_t off) const { return reinterpret_cast<T *>(base + off); }
+};
+
+}  // namespace
+
+extern "C" const char *farpca_status_str(int status) {
+  switch (status) {
+    case FARPCA_OK: return "ok";
+    case FARPCA_NOT_CONVERGED: return "block cap reached before the tolerance";
+    case FARPCA_E_INVALID: return "invalid parameter";
+    case FARPCA_E_NOMEM: return "workspace too small";
+    case FARPCA_E_DEVICE: return "HIP error";
+    case FARPCA_E_NONFINITE: return "A holds NaN or Inf";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_t *l_max,
+                           size_t *workspace_bytes) {
+  if (!prm || !out) return FARPCA_E_INVALID;
+  *out = nullptr;
+  const farpca_params &q = *prm;
+  if (q.m < 1 || q.n < 1 || q.lda < q.n) return FARPCA_E_INVALID;
+  if (q.a_dtype != FARPCA_DTYPE_F32) return FARPCA_E_INVALID;
+  if (q.sketch < FARPCA_GAUSSIAN || q.sketch > FARPCA_BERNOULLI) return FARPCA_E_INVALID;
+  if (q.block < 0 || q.block > kMaxBlock || q.power < 0 || q.power > 64) return FARPCA_E_INVALID;
+  if (q.rank < 0 || q.max_blocks < 0) return FARPCA_E_INVALID;
+  if (q.rank == 0 && !(q.tol > 0.0 && std::isfinite(q.tol))) return FARPCA_E_INVALID;
+  if (!(q.sketch_p >= 0.0 && q.sketch_p < 1.0)) return FARPCA_E_INVALID;
+  const int64_t mn = imin(q.m, q.n), big = imax(q.m, q.n);
+  int b = q.block ? q.block : (int)imin(imax(20, mn / 100), 50);
+  if (b > mn) {
+    if (q.block) return FARPCA_E_INVALID;
+    b = (int)mn;
+  }
+  if (q.sketch_zeta < 0 || q.sketch_zeta > b) return FARPCA_E_INVALID;
+
+  farpca_plan_s *pl = new (std::nothrow) farpca_plan_s();
+  if (!pl) return FARPCA_E_INVALID;
+  pl->prm = q;
+  pl->b = b;
+  pl->P = q.power;
+  pl->kind = q.sketch;
+  pl->zeta = (q.sketch == FARPCA_SPARSE_SIGN) ? q.sketch_zeta : 0;
+  double p = q.sketch_p;
+  if (p == 0.0) {
+    p = (q.sketch == FARPCA_STD_BERNOULLI) ? std::fmax(1e-3, std::log((double)big) / (double)big)
+                                           : std::fmax(1e-3, 10.0 / (double)big);
+  }
+  pl->p = p;
+  const double tp = std::floor(p * 4294967296.0);
+  const bool uses_p = q.sketch != FARPCA_GAUSSIAN && pl->zeta == 0;
+  if (uses_p && tp < 1.0) { delete pl; return FARPCA_E_INVALID; }
+  pl->thr = (uint32_t)(tp >= 4294967295.0 ? 4294967295.0 : tp);
+  switch (q.sketch) {
+    case FARPCA_SPARSE_SIGN:
+      pl->dense_scale = pl->zeta ? 1.0 / std::sqrt((double)pl->zeta) : 1.0 / std::sqrt(p);
+      break;
+    case FARPCA_SPARSE_GAUSSIAN: pl->dense_scale = 1.0 / std::sqrt(p); break;
+    default: pl->dense_scale = 1.0; break;
+  }
+  pl->sketch_scale = (float)pl->dense_scale;
+
+  int64_t maxblk = q.max_blocks ? q.max_blocks : (mn + 2 * b - 1) / (2 * b);
+  if (q.rank > 0) maxblk = (q.rank + b - 1) / b;
+  maxblk = imin(maxblk, mn / b);
+  if (maxblk < 1) maxblk = 1;
+  pl->maxblk = maxblk;
+  pl->lmax = maxblk * b;
+  pl->ldq = (pl->lmax + 3) / 4 * 4;
+  pl->nchunks = (q.n + kChunk - 1) / kChunk;
+
+  const int64_t m = q.m, n = q.n, lmax = pl->lmax, ldq = pl->ldq;
+  const int64_t mnl = imax(imax(m, n), ldq);
+  Carver c;
+  pl->off_q = c.take((size_t)m * ldq * 4);
+  pl->off_ct = c.take((size_t)n * ldq * 4);
+  pl->off_s = c.take((size_t)m * kBld * 4);
+  pl->off_y = c.take((size_t)m * kBld * 4);
+  pl->off_x = c.take((size_t)n * kBld * 4);
+  pl->off_g = c.take((size_t)n * kBld * 4);
+  pl->off_om = c.take((size_t)n * kBld * 4);
+  pl->off_mask = c.take((size_t)n * 8);
+  pl->off_neg = c.take((size_t)n * 8);
+  pl->off_colptr = c.take((size_t)pl->nchunks * (kMaxBlock + 1) * 4);
+  pl->off_ent = c.take((size_t)pl->nchunks * kChunk * kMaxBlock * sizeof(ChunkEntry));
+  pl->off_z = c.take((size_t)m * 4);
+  pl->off_rowsum = c.take((size_t)m * 8);
+  pl->off_r = c.take((size_t)ldq * kBld * 4);
+  pl->off_part = c.take((size_t)16 * mnl * kBld * 4);
+  pl->off_gpart = c.take((size_t)256 * kMaxBlock * kMaxBlock * 8);   // <= 256 partials for any K
+  pl->off_g64 = c.take((size_t)kMaxBlock * kMaxBlock * 8);
+  pl->off_rinv = c.take((size_t)kMaxBlock * kMaxBlock * 8);
+  pl->off_w64 = c.take((size_t)kMaxBlock * 8);
+  pl->off_v64 = c.take((size_t)kMaxBlock * kMaxBlock * 8);
+  pl->off_setup = c.take((size_t)setup_num_partials(m) * 8);
+  pl->off_sq = c.take((size_t)256 * 8);                               // <= 256 partials for any K
+  pl->off_scal = c.take(64);                        // nA2, E, alpha, flags
+  pl->off_ehist = c.take((size_t)maxblk * 8);
+  pl->off_kbig = c.take((size_t)lmax * lmax * 8);
+  pl->off_eig = c.take(eig_workspace_bytes(lmax));
+  pl->off_wfin = c.take((size_t)lmax * 8);
+  pl->off_vfin = c.take((size_t)lmax * lmax * 8);
+  pl->off_u32 = c.take((size_t)lmax * lmax * 4);
+  const size_t gbig = gram_big_workspace_bytes(n, lmax);
+  pl->off_gbig = c.take(gbig);
+  pl->gbig_bytes = gbig;
+  pl->total = c.cur;
+  *out = pl;
+  if (l_max) *l_max = lmax;
+  if (workspace_bytes) *workspace_bytes = pl->total;
+  return FARPCA_OK;
+}
+
+extern "C" void farpca_free(farpca_plan_t *plan) { delete plan; }
+
+namespace {
+
+OmegaSpec omega_spec(const farpca_plan_s *pl) {
+  OmegaSpec s;
+  s.kind = pl->kind;
+  s.b = pl->b;
+  s.zeta = pl->zeta;
+  s.thr = pl->thr;
+  s.dense_scale = pl->dense_scale;
+  s.p = pl->p;
+  s.seed = pl->prm.seed;
+  return s;
+}
+
+// Omega_j into the workspace (dense copy, masks, column lists).
+void gen_omega(const farpca_plan_s *pl, const Ws &w, int64_t j, hipStream_t st,
+               uint64_t *mask = nullptr, uint64_t *neg = nullptr, float *dense = nullptr) {
+  const bool lists = pl->kind != FARPCA_GAUSSIAN;
+  launch_omega(omega_spec(pl), pl->prm.n, j, mask ? mask : w.at<uint64_t>(pl->off_mask),
+               neg ? neg : w.at<uint64_t>(pl->off_neg), dense ? dense : w.at<float>(pl->off_om),
+               lists ? w.at<uint32_t>(pl->off_colptr) : nullptr,
+               lists ? w.at<ChunkEntry>(pl->off_ent) : nullptr, sketch_lds_row_stride_bytes(), st);
+}
+
+// S = A Omega_j (standardized Bernoulli: A B_j - z), m x kBld.
+void sketch(const farpca_plan_s *pl, const Ws &w, const float *A, float *S, hipStream_t st) {
+  const farpca_params &q = pl->prm;
+  float *part = w.at<float>(pl->off_part);
+  if (pl->kind == FARPCA_GAUSSIAN) {
+    launch_gemm_nn(A, q.lda, w.at<float>(pl->off_om), kBld, S, kBld, q.m, kBld, q.n, 1.f, 0.f,
+                   gemm_choose_ksplit(q.m, q.n, 0), part, st);
+    return;
+  }
+  const float *z = (pl->kind == FARPCA_STD_BERNOULLI) ? w.at<float>(pl->off_z) : nullptr;
+  const float scale = pl->sketch_scale;
+  const int ns = sketch_choose_split(q.m, q.n);
+  if (ns <= 1) {
+    launch_sketch_full(A, q.lda, q.m, q.n, pl->b, w.at<uint32_t>(pl->off_colptr),
+                       w.at<ChunkEntry>(pl->off_ent), S, 1, scale, z, -1.f, st);
+  } else {
+    launch_sketch_full(A, q.lda, q.m, q.n, pl->b, w.at<uint32_t>(pl->off_colptr),
+                       w.at<ChunkEntry>(pl->off_ent), part, ns, scale, z, -1.f, st);
+    // number of splits actually launched
+    const int64_t nchunks = pl->nchunks;
+    const int64_t cps = (nchunks + ns - 1) / ns;
+    const int nsp = (int)((nchunks + cps - 1) / cps);
+    launch_reduce_partials(part, nsp, q.m, kBld, S, kBld, scale, 0.f, nullptr, 0, 0.f, z, -1.f, st);
+  }
+}
+
+// T <- (I - Q Q^T) T, applied twice (block classical Gram-Schmidt with
+// reorthogonalisation), Q = first l columns of the basis.
+void project_out(const farpca_plan_s *pl, const Ws &w, int64_t l, float *T, hipStream_t st) {
+  if (l == 0) return;
+  const farpca_params &q = pl->prm;
+  float *Q = w.at<float>(pl->off_q);
+  float *r = w.at<float>(pl->off_r);
+  float *part = w.at<float>(pl->off_part);
+  for (int pass = 0; pass < 2; ++pass) {
+    launch_gemm_tn(Q, pl->ldq, T, kBld, r, kBld, l, pl->b, q.m, 1.f, 0.f,
+                   gemm_choose_ksplit(l, q.m, 1), part, st);
+    launch_gemm_nn(Q, pl->ldq, r, kBld, T, kBld, q.m, pl->b, l, -1.f, 1.f, 1, part, st);
+  }
+}
+
+// X (K x b) <- orthonormal basis of its range, CholeskyQR with `passes`
+// passes; numerically dependent columns (residual below 1e-5 of the column,
+// i.e. rounding noise of the FP32 data) become exactly zero.  If gram_eig,
+// the eigenvalues of the first Gram go to w64 (descending).
+void cholqr(const farpca_plan_s *pl, const Ws &w, float *X, int64_t K, int passes, bool gram_eig,
+            hipStream_t st) {
+  double *gpart = w.at<double>(pl->off_gpart);
+  double *G = w.at<double>(pl->off_g64);
+  double *Rinv = w.at<double>(pl->off_rinv);
+  int *flags = reinterpret_cast<int *>(w.at<double>(pl->off_scal) + 3);
+  for (int pass = 0; pass < passes; ++pass) {
+    launch_gram(X, kBld, K, pl->b, gpart, G, st);
+    if (pass == 0 && gram_eig)
+      launch_eig_small(G, pl->b, kMaxBlock, w.at<double>(pl->off_w64), w.at<double>(pl->off_v64),
+                       kMaxBlock, st);
+    launch_chol_inv(G, pl->b, kDropRel, Rinv, flags, st);
+    launch_apply_small(X, kBld, K, pl->b, Rinv, X, kBld, st);
+  }
+}
+
+}  // namespace
+
+extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_bytes,
+                          void *dU, double *dS, void *dV, farpca_info *info, double *dEhist,
+                          void *stream) {
+  if (!plan || !dA || !dWork || !dU || !dS || !dV) return FARPCA_E_INVALID;
+  farpca_plan_s *pl = plan;
+  if (work_bytes < pl->total) return FARPCA_E_NOMEM;
+  if ((reinterpret_cast<uintptr_t>(dWork) & 255) != 0) return FARPCA_E_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const farpca_params &q = pl->prm;
+  const int64_t m = q.m, n = q.n;
+  const int b = pl->b;
+  const float *A = static_cast<const float *>(dA);
+  Ws w{static_cast<char *>(dWork)};
+  double *scal = w.at<double>(pl->off_scal);
+  double *nA2 = scal + 0, *E = scal + 1, *alpha = scal + 2;
+  int *flags = reinterpret_cast<int *>(scal + 3);
+  double *ehist = dEhist ? dEhist : w.at<double>(pl->off_ehist);
+  float *Q = w.at<float>(pl->off_q);
+  float *Ct = w.at<float>(pl->off_ct);
+  float *S = w.at<float>(pl->off_s);
+  float *Yb = w.at<float>(pl->off_y);
+  float *X = w.at<float>(pl->off_x);
+  float *part = w.at<float>(pl->off_part);
+
+  HIP_OK(hipMemsetAsync(scal, 0, 64, st));
+  // a0: ||A||_F^2 in FP64, row sums (z for the standardized Bernoulli matrix), finiteness.
+  launch_setup(A, q.lda, m, n, w.at<double>(pl->off_setup), w.at<double>(pl->off_rowsum), flags, st);
+  launch_sum_partials(w.at<double>(pl->off_setup), setup_num_partials(m), nA2, st);
+  double h_scal[4];
+  HIP_OK(hipMemcpyAsync(h_scal, scal, 32, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  int h_flags = 0;
+  std::memcpy(&h_flags, &h_scal[3], sizeof(int));
+  if (h_flags & 2) return FARPCA_E_NONFINITE;
+  const double norm_a2 = h_scal[0];
+  HIP_OK(hipMemcpyAsync(E, nA2, 8, hipMemcpyDeviceToDevice, st));
+  if (pl->kind == FARPCA_STD_BERNOULLI)
+    launch_scale_rowsum(w.at<double>(pl->off_rowsum), m, pl->p, w.at<float>(pl->off_z), st);
+  const double thr = q.tol * q.tol * norm_a2;
+
+  int64_t l = 0;
+  int status = FARPCA_NOT_CONVERGED;
+  int blocks = 0;
+  double e_host = norm_a2;
+  for (int64_t j = 0; j < pl->maxblk; ++j) {
+    gen_omega(pl, w, j, st);
+    sketch(pl, w, A, S, st);
+    float *Ysrc = S;
+    if (pl->P > 0) {
+      float *G = w.at<float>(pl->off_g);
+      HIP_OK(hipMemsetAsync(alpha, 0, 8, st));
+      float *T = S;
+      for (int k = 1; k <= pl->P; ++k) {
+        project_out(pl, w, l, T, st);
+        launch_gemm_tn(A, q.lda, T, kBld, X, kBld, n, b, m, 1.f, 0.f,
+                       gemm_choose_ksplit(n, m, 1), part, st);
+        if (k >= 2 && pl->P > 2) launch_axpy_block(X, kBld, G, kBld, n, b, alpha, st);
+        cholqr(pl, w, X, n, 3, pl->P > 2, st);
+        if (k >= 2 && pl->P > 2) launch_alpha_update(w.at<double>(pl->off_w64), b, alpha, st);
+        launch_copy_block(X, kBld, n, b, G, kBld, st);
+        if (k < pl->P) {
+          launch_gemm_nn(A, q.lda, G, kBld, S, kBld, m, b, n, 1.f, 0.f,
+                         gemm_choose_ksplit(m, n, 0), part, st);
+          T = S;
+        }
+      }
+      launch_gemm_nn(A, q.lda, G, kBld, Yb, kBld, m, b, n, 1.f, 0.f, gemm_choose_ksplit(m, n, 0),
+                     part, st);
+      Ysrc = Yb;
+    }
+    // Basis extension: Y_j against Q, orthonormalise, append; C_j^T = A^T Q_j.
+    project_out(pl, w, l, Ysrc, st);
+    cholqr(pl, w, Ysrc, m, 3, false, st);
+    launch_copy_block(Ysrc, kBld, m, b, Q + l, pl->ldq, st);
+    launch_gemm_tn(A, q.lda, Ysrc, kBld, Ct + l, pl->ldq, n, b, m, 1.f, 0.f,
+                   gemm_choose_ksplit(n, m, 1), part, st);
+    launch_sqnorm(Ct + l, pl->ldq, n, b, w.at<double>(pl->off_sq), st);
+    launch_indicator_update(w.at<double>(pl->off_sq), sqnorm_num_partials(n), E, ehist, j, st);
+    l += b;
+    blocks = (int)(j + 1);
+    HIP_OK(hipMemcpyAsync(&e_host, E, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (q.rank > 0) {
+      if (l >= q.rank) { status = FARPCA_OK; break; }
+    } else if (e_host < thr) {
+      status = FARPCA_OK;
+      break;
+    }
+  }
+
+  // Final decomposition: K = C C^T = (C^T)^T C^T, eigenpairs descending.
+  const int64_t rout = (q.rank > 0) ? imin(q.rank, l) : l;
+  double *Kbig = w.at<double>(pl->off_kbig);
+  double *wfin = w.at<double>(pl->off_wfin);
+  double *vfin = w.at<double>(pl->off_vfin);
+  float *u32 = w.at<float>(pl->off_u32);
+  launch_gram_big(Ct, pl->ldq, n, l, Kbig, w.at<void>(pl->off_gbig), pl->gbig_bytes, st);
+  const int sweeps = eig_sym(Kbig, l, wfin, vfin, w.at<void>(pl->off_eig), st);
+  launch_sqrt_clip(wfin, rout, dS, st);
+  // U = Q U~ (first rout columns)
+  launch_convert_f64_f32(vfin, l, rout, l, nullptr, u32, rout, st);
+  for (int64_t c0 = 0; c0 < rout; c0 += kBld) {
+    const int64_t nc = imin(kBld, rout - c0);
+    launch_gemm_nn(Q, pl->ldq, u32 + c0, rout, static_cast<float *>(dU) + c0, pl->lmax, m, nc, l,
+                   1.f, 0.f, 1, part, st);
+  }
+  // V = C^T U~ Sigma^{-1}
+  launch_convert_f64_f32(vfin, l, rout, l, dS, u32, rout, st);
+  for (int64_t c0 = 0; c0 < rout; c0 += kBld) {
+    const int64_t nc = imin(kBld, rout - c0);
+    launch_gemm_nn(Ct, pl->ldq, u32 + c0, rout, static_cast<float *>(dV) + c0, pl->lmax, n, nc, l,
+                   1.f, 0.f, 1, part, st);
+  }
+  double h_tail[4];
+  HIP_OK(hipMemcpyAsync(h_tail, scal, 32, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  HIP_OK(hipGetLastError());
+  if (info) {
+    info->rank_l = l;
+    info->rank_out = rout;
+    info->blocks = blocks;
+    info->status = status;
+    info->norm_a2 = norm_a2;
+    info->err_indicator = h_tail[1];
+    info->eig_sweeps = sweeps;
+    int fl = 0;
+    std::memcpy(&fl, &h_tail[3], sizeof(int));
+    info->dropped = fl & 1;
+  }
+  return status;
+}
+
+extern "C" int farpca_omega(farpca_plan_t *plan, int64_t block_j, void *dWork, size_t work_bytes,
+                            uint64_t *dMask, uint64_t *dNeg, float *dDense, void *stream) {
+  if (!plan || !dWork || !dMask || !dNeg || !dDense || block_j < 0) return FARPCA_E_INVALID;
+  if (work_bytes < plan->total) return FARPCA_E_NOMEM;
+  Ws w{static_cast<char *>(dWork)};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  gen_omega(plan, w, block_j, st, dMask, dNeg, dDense);
+  HIP_OK(hipGetLastError());
+  return FARPCA_OK;
+}
+
+extern "C" int farpca_sketch(farpca_plan_t *plan, const void *dA, int64_t block_j, void *dWork,
+                             size_t work_bytes, float *dS, void *stream) {
+  if (!plan || !dA || !dWork || !dS || block_j < 0) return FARPCA_E_INVALID;
+  if (work_bytes < plan->total) return FARPCA_E_NOMEM;
+  farpca_plan_s *pl = plan;
+  Ws w{static_cast<char *>(dWork)};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const farpca_params &q = pl->prm;
+  if (pl->kind == FARPCA_STD_BERNOULLI) {
+    int *flags = reinterpret_cast<int *>(w.at<double>(pl->off_scal) + 3);
+    launch_setup(static_cast<const float *>(dA), q.lda, q.m, q.n, w.at<double>(pl->off_setup),
+                 w.at<double>(pl->off_rowsum), flags, st);
+    launch_scale_rowsum(w.at<double>(pl->off_rowsum), q.m, pl->p, w.at<float>(pl->off_z), st);
+  }
+  gen_omega(pl, w, block_j, st);
+  sketch(pl, w, static_cast<const float *>(dA), dS, st);
+  HIP_OK(hipGetLastError());
+  return FARPCA_OK;
+}
+
+extern "C" size_t farpca_gemm_scratch_bytes(int64_t M) { return (size_t)16 * M * kBld * 4; }
+
+extern "C" int farpca_gemm_nn(const float *dA, int64_t lda, const float *dX, int64_t ldx, float *dC,
+                              int64_t ldc, int64_t M, int64_t N, int64_t K, float *dPart,
+                              void *stream) {
+  if (!dA || !dX || !dC || M < 1 || K < 1 || N < 1 || N > kBld || lda < K || ldx < N || ldc < N)
+    return FARPCA_E_INVALID;
+  const int ks = gemm_choose_ksplit(M, K, 0);
+  if (ks > 1 && !dPart) return FARPCA_E_INVALID;
+  launch_gemm_nn(dA, lda, dX, ldx, dC, ldc, M, N, K, 1.f, 0.f, ks, dPart,
+                 static_cast<hipStream_t>(stream));
+  HIP_OK(hipGetLastError());
+  return FARPCA_OK;
+}
+
+extern "C" int farpca_gemm_tn(const float *dA, int64_t lda, const float *dY, int64_t ldy, float *dC,
+                              int64_t ldc, int64_t M, int64_t N, int64_t K, float *dPart,
+                              void *stream) {
+  if (!dA || !dY || !dC || M < 1 || K < 1 || N < 1 || N > kBld || lda < M || ldy < N || ldc < N)
+    return FARPCA_E_INVALID;
+  const int ks = gemm_choose_ksplit(M, K, 1);
+  if (ks > 1 && !dPart) return FARPCA_E_INVALID;
+  launch_gemm_tn(dA, lda, dY, ldy, dC, ldc, M, N, K, 1.f, 0.f, ks, dPart,
+                 static_cast<hipStream_t>(stream));
+  HIP_OK(hipGetLastError());
+  return FARPCA_OK;
+}
+
+extern "C" size_t farpca_eig_scratch_bytes(int64_t l) { return eig_workspace_bytes(l); }
+
+extern "C" int farpca_eig(const double *dK, int64_t l, double *dW, double *dV, void *dWork,
+                          void *stream) {
+  if (!dK || !dW || !dV || !dWork || l < 1) return FARPCA_E_INVALID;
+  const int sweeps = eig_sym(dK, l, dW, dV, dWork, static_cast<hipStream_t>(stream));
+  HIP_OK(hipGetLastError());
+  return sweeps;
+}

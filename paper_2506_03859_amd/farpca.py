@@ -1,0 +1,234 @@
+"""Python binding of libfarpca.so (argument marshalling only).
+
+The names follow the C-ABI in include/farpca.h: farpca_plan, farpca_run,
+farpca_free, farpca_omega, farpca_sketch, farpca_gemm_nn, farpca_gemm_tn,
+farpca_eig.  Device buffers are torch tensors on the current HIP device;
+every step of the method runs in the library's kernels.  ``solve`` is a
+convenience wrapper that allocates the caller-owned buffers the C-ABI asks for.
+
+Loading fails loudly when the library has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfarpca.so")
+
+SKETCH_IDS = {"gaussian": 0, "std_bernoulli": 1, "sparse_sign": 2, "sparse_gaussian": 3,
+              "bernoulli": 4}
+STATUS_OK = 0
+STATUS_NOT_CONVERGED = 1
+
+EXPORTED = ["farpca_plan", "farpca_run", "farpca_free", "farpca_status_str", "farpca_omega",
+            "farpca_sketch", "farpca_gemm_scratch_bytes", "farpca_gemm_nn", "farpca_gemm_tn",
+            "farpca_eig_scratch_bytes", "farpca_eig"]
+
+
+class FarpcaParams(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+                ("a_dtype", ctypes.c_int32), ("sketch", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("rank", ctypes.c_int64), ("block", ctypes.c_int32), ("power", ctypes.c_int32),
+                ("max_blocks", ctypes.c_int64), ("sketch_p", ctypes.c_double),
+                ("sketch_zeta", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class FarpcaInfo(ctypes.Structure):
+    _fields_ = [("rank_l", ctypes.c_int64), ("rank_out", ctypes.c_int64),
+                ("blocks", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("norm_a2", ctypes.c_double), ("err_indicator", ctypes.c_double),
+                ("eig_sweeps", ctypes.c_int32), ("dropped", ctypes.c_int32)]
+
+
+class FarpcaError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libfarpca.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FarpcaError(f"{path} not found: build it with `python -c 'import __graft_entry__ as g; "
+                          "g.build()'` (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+    lib.farpca_plan.argtypes = [ctypes.POINTER(FarpcaParams), ctypes.POINTER(vp),
+                                ctypes.POINTER(i64), ctypes.POINTER(sz)]
+    lib.farpca_plan.restype = ctypes.c_int
+    lib.farpca_run.argtypes = [vp, vp, vp, sz, vp, vp, vp, ctypes.POINTER(FarpcaInfo), vp, vp]
+    lib.farpca_run.restype = ctypes.c_int
+    lib.farpca_free.argtypes = [vp]
+    lib.farpca_free.restype = None
+    lib.farpca_status_str.argtypes = [ctypes.c_int]
+    lib.farpca_status_str.restype = ctypes.c_char_p
+    lib.farpca_omega.argtypes = [vp, i64, vp, sz, vp, vp, vp, vp]
+    lib.farpca_omega.restype = ctypes.c_int
+    lib.farpca_sketch.argtypes = [vp, vp, i64, vp, sz, vp, vp]
+    lib.farpca_sketch.restype = ctypes.c_int
+    lib.farpca_gemm_scratch_bytes.argtypes = [i64]
+    lib.farpca_gemm_scratch_bytes.restype = sz
+    for name in ("farpca_gemm_nn", "farpca_gemm_tn"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, i64, vp, i64, vp, i64, i64, i64, i64, vp, vp]
+        f.restype = ctypes.c_int
+    lib.farpca_eig_scratch_bytes.argtypes = [i64]
+    lib.farpca_eig_scratch_bytes.restype = sz
+    lib.farpca_eig.argtypes = [vp, i64, vp, vp, vp, vp]
+    lib.farpca_eig.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        msg = load_library().farpca_status_str(rc).decode()
+        raise FarpcaError(f"{what} failed: {rc} ({msg})")
+    return rc
+
+
+def make_params(m, n, lda=None, *, tol=0.0, rank=0, block=0, power=1, sketch="sparse_sign",
+                p=0.0, zeta=0, seed=0, max_blocks=0) -> FarpcaParams:
+    return FarpcaParams(m=m, n=n, lda=lda if lda is not None else n, a_dtype=0,
+                        sketch=SKETCH_IDS[sketch], tol=tol, rank=rank, block=block, power=power,
+                        max_blocks=max_blocks, sketch_p=p, sketch_zeta=zeta, reserved0=0, seed=seed)
+
+
+@dataclass
+class Plan:
+    handle: ctypes.c_void_p
+    l_max: int
+    workspace_bytes: int
+    params: FarpcaParams
+
+    def free(self):
+        if self.handle:
+            load_library().farpca_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+
+def farpca_plan(params: FarpcaParams) -> Plan:
+    lib = load_library()
+    h = ctypes.c_void_p()
+    lmax = ctypes.c_int64()
+    ws = ctypes.c_size_t()
+    _check(lib.farpca_plan(ctypes.byref(params), ctypes.byref(h), ctypes.byref(lmax), ctypes.byref(ws)),
+           "farpca_plan")
+    return Plan(h, lmax.value, ws.value, params)
+
+
+def farpca_free(plan: Plan) -> None:
+    plan.free()
+
+
+def farpca_run(plan: Plan, A, work, U, S, V, ehist=None, stream=None):
+    """Enqueue and run; returns (status, FarpcaInfo)."""
+    lib = load_library()
+    info = FarpcaInfo()
+    rc = lib.farpca_run(plan.handle, _ptr(A), _ptr(work), work.numel() * work.element_size(),
+                        _ptr(U), _ptr(S), _ptr(V), ctypes.byref(info),
+                        _ptr(ehist) if ehist is not None else None, _stream(stream))
+    _check(rc, "farpca_run")
+    return rc, info
+
+
+def farpca_omega(plan: Plan, block_j: int, work, mask, neg, dense, stream=None) -> int:
+    lib = load_library()
+    return _check(lib.farpca_omega(plan.handle, block_j, _ptr(work), work.numel(), _ptr(mask), _ptr(neg),
+                                   _ptr(dense), _stream(stream)), "farpca_omega")
+
+
+def farpca_sketch(plan: Plan, A, block_j: int, work, S, stream=None) -> int:
+    lib = load_library()
+    return _check(lib.farpca_sketch(plan.handle, _ptr(A), block_j, _ptr(work), work.numel(), _ptr(S),
+                                    _stream(stream)), "farpca_sketch")
+
+
+def farpca_gemm_scratch_bytes(M: int) -> int:
+    return int(load_library().farpca_gemm_scratch_bytes(M))
+
+
+def farpca_gemm_nn(A, X, C, M, N, K, part, lda=None, ldx=None, ldc=None, stream=None) -> int:
+    lib = load_library()
+    return _check(lib.farpca_gemm_nn(_ptr(A), lda or A.stride(0), _ptr(X), ldx or X.stride(0), _ptr(C),
+                                     ldc or C.stride(0), M, N, K, _ptr(part), _stream(stream)),
+                  "farpca_gemm_nn")
+
+
+def farpca_gemm_tn(A, Y, C, M, N, K, part, lda=None, ldy=None, ldc=None, stream=None) -> int:
+    lib = load_library()
+    return _check(lib.farpca_gemm_tn(_ptr(A), lda or A.stride(0), _ptr(Y), ldy or Y.stride(0), _ptr(C),
+                                     ldc or C.stride(0), M, N, K, _ptr(part), _stream(stream)),
+                  "farpca_gemm_tn")
+
+
+def farpca_eig_scratch_bytes(l: int) -> int:
+    return int(load_library().farpca_eig_scratch_bytes(l))
+
+
+def farpca_eig(K, W, V, work, stream=None) -> int:
+    lib = load_library()
+    return _check(lib.farpca_eig(_ptr(K), K.shape[0], _ptr(W), _ptr(V), _ptr(work), _stream(stream)),
+                  "farpca_eig")
+
+
+@dataclass
+class SolveResult:
+    U: object
+    S: object
+    V: object
+    info: FarpcaInfo
+    status: int
+    e_history: object
+
+
+def alloc_outputs(plan: Plan, device="cuda"):
+    import torch
+    p = plan.params
+    work = torch.empty(plan.workspace_bytes + 256, dtype=torch.uint8, device=device)
+    off = (-work.data_ptr()) % 256
+    work = work[off:off + plan.workspace_bytes]
+    U = torch.empty((p.m, plan.l_max), dtype=torch.float32, device=device)
+    S = torch.empty((plan.l_max,), dtype=torch.float64, device=device)
+    V = torch.empty((p.n, plan.l_max), dtype=torch.float32, device=device)
+    b = p.block or min(max(20, min(p.m, p.n) // 100), 50)
+    eh = torch.zeros((plan.l_max // max(1, b) + 1,), dtype=torch.float64, device=device)
+    return work, U, S, V, eh
+
+
+def solve(A, *, tol=0.0, rank=0, block=0, power=1, sketch="sparse_sign", p=0.0, zeta=0, seed=0,
+          max_blocks=0, stream=None) -> SolveResult:
+    """Run the whole method on a row-major FP32 CUDA tensor A (m x n)."""
+    import torch
+    if A.dtype != torch.float32 or not A.is_cuda or A.stride(1) != 1:
+        raise FarpcaError("A must be a row-major float32 tensor on the GPU")
+    m, n = A.shape
+    prm = make_params(m, n, A.stride(0), tol=tol, rank=rank, block=block, power=power, sketch=sketch,
+                      p=p, zeta=zeta, seed=seed, max_blocks=max_blocks)
+    plan = farpca_plan(prm)
+    try:
+        work, U, S, V, eh = alloc_outputs(plan, A.device)
+        status, info = farpca_run(plan, A, work, U, S, V, eh, stream)
+        k = info.rank_out
+        nb = info.blocks
+        return SolveResult(U[:, :k], S[:k], V[:, :k], info, status, eh[:nb])
+    finally:
+        plan.free()

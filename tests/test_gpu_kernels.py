@@ -1,0 +1,230 @@
+"""GPU parity of the individual kernels, called through the C-ABI:
+Omega generation (bit-exact against the oracle's independent generator),
+the sparse sketch (bit-exact on integer-valued A), the matrix-core products
+(bit-exact on small integers, FP32 error bound otherwise) and the FP64
+eigensolver."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import omega as om
+from paper_2506_03859_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import torch  # noqa: F401
+    from paper_2506_03859_amd import farpca as fpm
+    fpm.load_library()
+    return fpm
+
+
+def dev(x, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+OMEGA_CASES = [
+    ("sparse_sign", 0.0, 8, 64), ("sparse_sign", 0.0, 4, 50), ("sparse_sign", 0.0, 1, 20),
+    ("sparse_sign", 0.05, 0, 64), ("std_bernoulli", 0.5, 0, 20), ("std_bernoulli", 0.003, 0, 64),
+    ("sparse_gaussian", 0.05, 0, 64), ("bernoulli", 0.02, 0, 33), ("gaussian", 0.0, 0, 64),
+    ("gaussian", 0.0, 0, 7),
+]
+
+
+@pytest.mark.parametrize("sketch,p,zeta,b", OMEGA_CASES)
+def test_omega_bit_exact(fp, sketch, p, zeta, b):
+    import torch
+    n, seed = 1000, 1234
+    prm = fp.make_params(500, n, tol=0.1, block=b, power=1, sketch=sketch, p=p, zeta=zeta, seed=seed)
+    plan = fp.farpca_plan(prm)
+    try:
+        work, *_ = fp.alloc_outputs(plan)
+        mask = torch.zeros(n, dtype=torch.int64, device="cuda")
+        neg = torch.zeros(n, dtype=torch.int64, device="cuda")
+        dense = torch.zeros((n, 64), dtype=torch.float32, device="cuda")
+        for j in (0, 3):
+            print(f"omega {sketch} p={p} zeta={zeta} b={b} block={j}", flush=True)
+            fp.farpca_omega(plan, j, work, mask, neg, dense)
+            gm = host(mask).view(np.uint64)
+            gn = host(neg).view(np.uint64)
+            gd = host(dense)
+            ref = om.omega_dense(n, b, j, sketch, seed, p, zeta)
+            bits = (np.uint64(1) << np.arange(b, dtype=np.uint64))
+            gmask = (gm[:, None] & bits[None, :]) != 0
+            gneg = (gn[:, None] & bits[None, :]) != 0
+            if sketch == "gaussian":
+                assert gmask.all()
+            elif sketch == "std_bernoulli":
+                assert np.array_equal(gmask, ref > 0)
+            else:
+                assert np.array_equal(gmask, ref != 0)
+            assert np.array_equal(gneg, ref < 0)
+            assert np.all(gd[:, b:] == 0)
+            if sketch == "std_bernoulli":
+                expect = gmask.astype(np.float64) - p       # Algorithm 2's unscaled B - p
+            else:
+                expect = ref
+            if sketch in ("gaussian", "sparse_gaussian"):
+                # Box-Muller through the device math library: FP64 rounding, then FP32
+                assert np.allclose(gd[:, :b], expect, rtol=2 * U32, atol=1e-12)
+            else:
+                assert np.array_equal(gd[:, :b], expect.astype(np.float32))
+    finally:
+        plan.free()
+
+
+SKETCH_CASES = [
+    # (sketch, p, zeta, b, m, n)  scales chosen exact in binary for bit-exact sums
+    ("sparse_sign", 0.0, 4, 64, 1000, 700),
+    ("sparse_sign", 0.0, 16, 50, 3000, 1300),
+    ("sparse_sign", 0.25, 0, 20, 257, 64),
+    ("std_bernoulli", 0.5, 0, 64, 2000, 777),
+    ("bernoulli", 0.125, 0, 33, 1500, 1000),
+    ("sparse_sign", 0.0, 1, 8, 100, 12),
+]
+
+
+@pytest.mark.parametrize("sketch,p,zeta,b,m,n", SKETCH_CASES)
+def test_sketch_bit_exact_integer_A(fp, sketch, p, zeta, b, m, n):
+    import torch
+    a = synth.integer_matrix(m, n, seed=m + n, amax=1000)
+    prm = fp.make_params(m, n, tol=0.1, block=b, power=1, sketch=sketch, p=p, zeta=zeta, seed=77)
+    plan = fp.farpca_plan(prm)
+    try:
+        work, *_ = fp.alloc_outputs(plan)
+        S = torch.full((m, 64), float("nan"), dtype=torch.float32, device="cuda")
+        A = dev(a, torch.float32)
+        for j in (0, 5):
+            print(f"sketch {sketch} p={p} zeta={zeta} b={b} m={m} n={n} block={j}", flush=True)
+            fp.farpca_sketch(plan, A, j, work, S)
+            got = host(S)
+            if sketch == "std_bernoulli":
+                bm = om.bernoulli_mask(n, b, j, 77, p).astype(np.float64)
+                ref = a @ bm - (a @ (p * np.ones(n)))[:, None]     # Algorithm 2: A B_j - z
+            else:
+                ref = a @ om.omega_dense(n, b, j, sketch, 77, p, zeta)
+            assert np.array_equal(got[:, :b], ref.astype(np.float32))
+            assert np.all(got[:, b:] == 0)
+    finally:
+        plan.free()
+
+
+@pytest.mark.parametrize("sketch,p,zeta,b", [("sparse_gaussian", 0.05, 0, 64), ("sparse_sign", 0.0, 8, 64),
+                                             ("gaussian", 0.0, 0, 50), ("std_bernoulli", 0.01, 0, 64)])
+def test_sketch_real_A(fp, sketch, p, zeta, b):
+    import torch
+    m, n = 4000, 2500
+    a = synth.gaussian_matrix(m, n, seed=5).astype(np.float32)
+    prm = fp.make_params(m, n, tol=0.1, block=b, power=1, sketch=sketch, p=p, zeta=zeta, seed=91)
+    plan = fp.farpca_plan(prm)
+    try:
+        work, *_ = fp.alloc_outputs(plan)
+        S = torch.zeros((m, 64), dtype=torch.float32, device="cuda")
+        print(f"sketch real {sketch} p={p} zeta={zeta} b={b}", flush=True)
+        fp.farpca_sketch(plan, dev(a), 2, work, S)
+        got = host(S)[:, :b].astype(np.float64)
+        a64 = a.astype(np.float64)
+        if sketch == "std_bernoulli":
+            bm = om.bernoulli_mask(n, b, 2, 91, p).astype(np.float64)
+            ref = a64 @ bm - (a64 @ (p * np.ones(n)))[:, None]
+            absref = np.abs(a64) @ bm + np.abs(a64 @ (p * np.ones(n)))[:, None]
+        else:
+            o = om.omega_dense(n, b, 2, sketch, 91, p, zeta)
+            ref = a64 @ o
+            absref = np.abs(a64) @ np.abs(o)
+        nnz_row = max(1, int(np.ceil(n * (zeta / b if zeta else (p if sketch != "gaussian" else 1)))))
+        bound = 4 * U32 * math.sqrt(nnz_row) * absref + 4 * U32 * np.abs(ref)
+        assert np.all(np.abs(got - ref) <= bound + 1e-30)
+    finally:
+        plan.free()
+
+
+GEMM_SHAPES = [(1000, 777, 50), (130, 3000, 64), (64, 64, 1), (5000, 20000, 64), (1, 300, 7),
+               (257, 1500, 33), (3000, 64, 64)]
+
+
+@pytest.mark.parametrize("M,K,N", GEMM_SHAPES)
+@pytest.mark.parametrize("kind", ["nn", "tn"])
+def test_gemm_integer_exact(fp, M, K, N, kind):
+    import torch
+    rng = np.random.default_rng(M * 7 + K)
+    amax = 8 if K <= 20000 else 2
+    if kind == "nn":
+        a = rng.integers(-amax, amax + 1, size=(M, K)).astype(np.float32)
+    else:
+        a = rng.integers(-amax, amax + 1, size=(K, M)).astype(np.float32)
+    x = rng.integers(-amax, amax + 1, size=(K, N)).astype(np.float32)
+    C = torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")
+    part = torch.empty(fp.farpca_gemm_scratch_bytes(M) // 4 + 1, dtype=torch.float32, device="cuda")
+    print(f"gemm {kind} M={M} K={K} N={N}", flush=True)
+    if kind == "nn":
+        fp.farpca_gemm_nn(dev(a), dev(x), C, M, N, K, part)
+        ref = a.astype(np.int64) @ x.astype(np.int64)
+    else:
+        fp.farpca_gemm_tn(dev(a), dev(x), C, M, N, K, part)
+        ref = a.astype(np.int64).T @ x.astype(np.int64)
+    assert np.array_equal(host(C), ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("M,K,N", [(2000, 15000, 64), (15000, 2000, 64), (333, 4000, 50)])
+@pytest.mark.parametrize("kind", ["nn", "tn"])
+def test_gemm_float_error_bound(fp, M, K, N, kind):
+    import torch
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((M, K) if kind == "nn" else (K, M)).astype(np.float32)
+    x = rng.standard_normal((K, N)).astype(np.float32)
+    C = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+    part = torch.empty(fp.farpca_gemm_scratch_bytes(M) // 4 + 1, dtype=torch.float32, device="cuda")
+    print(f"gemm float {kind} M={M} K={K} N={N}", flush=True)
+    a64, x64 = a.astype(np.float64), x.astype(np.float64)
+    if kind == "nn":
+        fp.farpca_gemm_nn(dev(a), dev(x), C, M, N, K, part)
+        ref, absref = a64 @ x64, np.abs(a64) @ np.abs(x64)
+    else:
+        fp.farpca_gemm_tn(dev(a), dev(x), C, M, N, K, part)
+        ref, absref = a64.T @ x64, np.abs(a64).T @ np.abs(x64)
+    err = np.abs(host(C) - ref)
+    # probabilistic bound of FP32 summation: a few u sqrt(K) |A||X| per entry
+    assert np.all(err <= 6 * U32 * math.sqrt(K) * absref)
+
+
+@pytest.mark.parametrize("l", [5, 20, 64, 65, 100, 250])
+@pytest.mark.parametrize("spectrum", ["uniform", "graded"])
+def test_eig_vs_lapack(fp, l, spectrum):
+    import torch
+    rng = np.random.default_rng(l)
+    q = synth.haar_columns(l, l, rng)
+    if spectrum == "uniform":
+        lam = rng.uniform(0.1, 10.0, l)
+    else:
+        lam = np.logspace(8, -2, l)
+    k = (q * lam) @ q.T
+    k = (k + k.T) / 2
+    W = torch.zeros(l, dtype=torch.float64, device="cuda")
+    V = torch.zeros((l, l), dtype=torch.float64, device="cuda")
+    work = torch.zeros(fp.farpca_eig_scratch_bytes(l) // 8 + 64, dtype=torch.float64, device="cuda")
+    print(f"eig l={l} {spectrum}", flush=True)
+    sweeps = fp.farpca_eig(dev(k), W, V, work)
+    w, v = host(W), host(V)
+    ref = np.sort(np.linalg.eigvalsh(k))[::-1]
+    assert np.all(np.diff(w) <= 0)
+    assert np.allclose(w, ref, rtol=0, atol=1e-13 * np.abs(ref).max() * math.sqrt(l))
+    assert np.abs(v.T @ v - np.eye(l)).max() < 1e-12 * l
+    res = np.linalg.norm(k @ v - v * w, axis=0)
+    assert res.max() < 1e-13 * np.abs(ref).max() * math.sqrt(l)
+    assert 0 <= sweeps <= 40

@@ -6,7 +6,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import FarpcaParams, eig_svd, farpca
+from oracle import FarpcaParams, eig_svd, farpca, projection_svd
 from oracle import omega as om
 from paper_2506_03859_amd import synth
 
@@ -231,3 +231,13 @@ def test_expected_error_bound_eq_4_9(a_fast):
         r = farpca(a_fast, prm)
         errs.append(math.sqrt(max(r.err_indicator, 0.0)))
     assert np.mean(errs) <= bound
+
+
+@pytest.mark.parametrize("power", [1, 2])
+def test_projection_svd_matches_final_step(a_small, power):
+    # for well-conditioned Z the paper's final step (eig(Z), eig(D^T T D))
+    # and the plain QR + SVD definition agree
+    prm = FarpcaParams(tol=1e-2, block=20, power=power, sketch="sparse_sign", zeta=4, seed=5)
+    r = farpca(a_small, prm, keep_bases=True)
+    s = projection_svd(a_small, r.Y)
+    assert np.allclose(r.S, s, rtol=0, atol=1e-12 * s[0])
