@@ -134,6 +134,18 @@ int farpca_gemm_tn(const float *dA, int64_t lda, const float *dY, int64_t ldy, f
 size_t farpca_eig_scratch_bytes(int64_t l);
 int farpca_eig(const double *dK, int64_t l, double *dW, double *dV, void *dWork, void *stream);
 
+/* ---- opt-in kernel timing (process-wide, not thread-safe): while enabled,
+ * farpca_run records hipEvents on its stream around the kernels that stream A
+ * and, on return, adds their elapsed times per class.  Enabling resets the
+ * totals.  Events cost a few microseconds per launch; leave off in production. */
+#define FARPCA_PROF_SKETCH 0   /* sparse sketch kernel (partials not included)   */
+#define FARPCA_PROF_GEMM_TN 1  /* A^T T products (power steps, C_j^T = A^T Q_j)  */
+#define FARPCA_PROF_GEMM_NN 2  /* A G products (and the Gaussian sketch)        */
+#define FARPCA_PROF_EIG 3      /* final FP64 eigendecomposition                 */
+#define FARPCA_PROF_NCLASS 4
+void farpca_profile_enable(int on);
+int farpca_profile_get(int cls, double *total_ms, int64_t *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,7 +69,7 @@ __global__ void gram_reduce_kernel(const double *__restrict__ part, int nblk, in
 }
 
 int gram_num_partials(int64_t K) {
-  int64_t rows = (K + 255) / 256;
+  int64_t rows = (K + 63) / 64;
   rows = ((rows + kGramRows - 1) / kGramRows) * kGramRows;
   if (rows < kGramRows) rows = kGramRows;
   return (int)((K + rows - 1) / rows);
@@ -77,7 +77,7 @@ int gram_num_partials(int64_t K) {
 
 void launch_gram(const float *X, int64_t ldx, int64_t K, int b, double *part, double *G,
                  hipStream_t st) {
-  int64_t rows = (K + 255) / 256;
+  int64_t rows = (K + 63) / 64;   // at most 64 partials
   rows = ((rows + kGramRows - 1) / kGramRows) * kGramRows;
   if (rows < kGramRows) rows = kGramRows;
   const int nblk = (int)((K + rows - 1) / rows);
@@ -86,29 +86,28 @@ void launch_gram(const float *X, int64_t ldx, int64_t K, int b, double *part, do
                      nblk, b, G);
 }
 
-// --------------------------------------------------------- Cholesky + inverse
-// G (kMaxBlock x kMaxBlock, FP64, valid b x b) = R^T R; Rinv = R^{-1} (upper),
-// so that X Rinv has orthonormal columns spanning X.  A column whose pivot
-// after elimination falls to drop_rel * (its own diagonal) or below is
-// numerically dependent on the previous ones (for FP32 data the residual is
-// rounding noise): it is dropped - its column of Rinv is zero, so the
-// corresponding output column is exactly zero - and it is not used to
-// eliminate later columns.  flags[0] |= 1 when a column is dropped.  (The
-// method's Z^{-1} is read as the pseudo-inverse on such directions.)
-__global__ __launch_bounds__(64) void chol_inv_kernel(const double *__restrict__ G, int b,
-                                                      double drop_rel, double *__restrict__ Rinv,
-                                                      int *__restrict__ flags) {
+// --------------------------------------------------------- Cholesky factor
+// G (kMaxBlock x kMaxBlock, FP64, valid b x b) = R^T R.  The output F holds
+// R strictly above the diagonal and 1 / R_jj on the diagonal, so that the
+// rows of X R^{-1} (orthonormal columns spanning X) follow by forward
+// substitution (trsm_rows).  A column whose pivot after elimination falls to
+// drop_rel * (its own diagonal) or below is numerically dependent on the
+// previous ones (for FP32 data the residual is rounding noise): it is dropped
+// - F's diagonal entry is 0, so that output column is exactly zero - and it is
+// not used to eliminate later columns.  flags[0] |= 1 when a column is
+// dropped.  (The method's Z^{-1} is read as the pseudo-inverse there.)
+__global__ __launch_bounds__(256) void chol_kernel(const double *__restrict__ G, int b,
+                                                   double drop_rel, double *__restrict__ F,
+                                                   int *__restrict__ flags) {
   __shared__ double a[kMaxBlock][kMaxBlock + 1];
-  __shared__ double ri[kMaxBlock][kMaxBlock + 1];
   __shared__ double dg[kMaxBlock];
   __shared__ int dropped[kMaxBlock];
   const int t = threadIdx.x;
-  for (int i = 0; i < kMaxBlock; ++i) a[i][t] = G[i * kMaxBlock + t];
+  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256) a[e / kMaxBlock][e % kMaxBlock] = G[e];
   __syncthreads();
-  dg[t] = a[t][t];
-  dropped[t] = 0;
+  if (t < kMaxBlock) { dg[t] = a[t][t]; dropped[t] = 0; }
   __syncthreads();
-  // right-looking Cholesky on the upper triangle: a[k][j] becomes R[k][j]
+  const int j = t & 63, i_off = t >> 6;
   for (int k = 0; k < b; ++k) {
     if (t == 0) {
       const double piv = a[k][k];
@@ -123,72 +122,61 @@ __global__ __launch_bounds__(64) void chol_inv_kernel(const double *__restrict__
     __syncthreads();
     if (t > k && t < b) a[k][t] = dropped[k] ? 0.0 : a[k][t] / a[k][k];
     __syncthreads();
-    if (t > k && t < b && !dropped[k]) {
-      const double rkt = a[k][t];
-      for (int i = k + 1; i <= t; ++i) a[i][t] -= a[k][i] * rkt;
+    if (!dropped[k] && j > k && j < b) {
+      const double rkj = a[k][j];
+      for (int i = k + 1 + i_off; i <= j; i += 4) a[i][j] -= a[k][i] * rkj;
     }
     __syncthreads();
   }
-  // inverse of the upper factor, column j by thread j (dropped columns zero)
-  if (t < b && !dropped[t]) {
-    const int j = t;
-    for (int i = 0; i < kMaxBlock; ++i) ri[i][j] = 0.0;
-    ri[j][j] = 1.0 / a[j][j];
-    for (int i = j - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int k = i + 1; k <= j; ++k) s = fma(a[i][k], ri[k][j], s);
-      ri[i][j] = dropped[i] ? 0.0 : -s / a[i][i];
-    }
-  } else {
-    for (int i = 0; i < kMaxBlock; ++i) ri[i][t] = 0.0;
-  }
-  __syncthreads();
-  for (int i = 0; i < kMaxBlock; ++i) Rinv[i * kMaxBlock + t] = ri[i][t];
-}
-
-void launch_chol_inv(const double *G, int b, double drop_rel, double *Rinv, int *flags,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(64), 0, st, G, b, drop_rel, Rinv, flags);
-}
-
-// ------------------------------------------------------------ small apply
-// Y[K x b] = X[K x b] * M[b x b] (M FP64, kMaxBlock x kMaxBlock), FP64 sums.
-__global__ __launch_bounds__(256) void apply_small_kernel(const float *__restrict__ X, int64_t ldx,
-                                                          int64_t K, int b,
-                                                          const double *__restrict__ Mg,
-                                                          float *__restrict__ Y, int64_t ldy) {
-  __shared__ double Ms[kMaxBlock][kMaxBlock];
-  __shared__ float xs[64][kMaxBlock + 1];
-  const int t = threadIdx.x;
-  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256) Ms[e / kMaxBlock][e % kMaxBlock] = Mg[e];
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
-  for (int e = t; e < 64 * kMaxBlock; e += 256) {
+  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256) {
     const int r = e / kMaxBlock, c = e % kMaxBlock;
-    const int64_t k = r0 + r;
-    xs[r][c] = (k < K && c < b) ? X[k * ldx + c] : 0.0f;
-  }
-  __syncthreads();
-  const int r = t >> 2, cq = (t & 3) * 16;
-  double acc[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) acc[c] = 0.0;
-  for (int k = 0; k < b; ++k) {
-    const double x = (double)xs[r][k];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) acc[c] = fma(x, Ms[k][cq + c], acc[c]);
-  }
-  const int64_t row = r0 + r;
-  if (row < K) {
-#pragma unroll
-    for (int c = 0; c < 16; ++c)
-      if (cq + c < b) Y[row * ldy + cq + c] = (float)acc[c];
+    double v = 0.0;
+    if (r < b && c < b) {
+      if (r < c) v = a[r][c];
+      else if (r == c) v = dropped[r] ? 0.0 : 1.0 / a[r][r];
+    }
+    F[e] = v;
   }
 }
 
-void launch_apply_small(const float *X, int64_t ldx, int64_t K, int b, const double *M,
-                        float *Y, int64_t ldy, hipStream_t st) {
-  hipLaunchKernelGGL(apply_small_kernel, dim3((unsigned)((K + 63) / 64)), dim3(256), 0, st, X, ldx,
-                     K, b, M, Y, ldy);
+void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags, hipStream_t st) {
+  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, st, G, b, drop_rel, F, flags);
+}
+
+// Rows of Y = X R^{-1}: q_j = (x_j - sum_{i<j} q_i R_ij) / R_jj, one row per
+// thread, FP64 sums (F from chol_kernel; in place allowed).
+__global__ __launch_bounds__(256) void trsm_rows_kernel(const float *__restrict__ X, int64_t ldx,
+                                                        int64_t K, int b, const double *__restrict__ F,
+                                                        float *__restrict__ Y, int64_t ldy) {
+  __shared__ double Fs[kMaxBlock * kMaxBlock];
+  const int t = threadIdx.x;
+  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256) Fs[e] = F[e];
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * 256 + t;
+  if (row >= K) return;
+  const float *x = X + row * ldx;
+  double q[kMaxBlock];
+#pragma unroll
+  for (int c = 0; c < kMaxBlock; ++c) {
+    if (c < b) {
+      double s = (double)x[c];
+#pragma unroll
+      for (int i = 0; i < c; ++i) s = fma(-q[i], Fs[i * kMaxBlock + c], s);
+      q[c] = s * Fs[c * kMaxBlock + c];
+    } else {
+      q[c] = 0.0;
+    }
+  }
+  float *y = Y + row * ldy;
+#pragma unroll
+  for (int c = 0; c < kMaxBlock; ++c)
+    if (c < b) y[c] = (float)q[c];
+}
+
+void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *F, float *Y,
+                      int64_t ldy, hipStream_t st) {
+  hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, X, ldx, K,
+                     b, F, Y, ldy);
 }
 
 // ------------------------------------------------------------ setup pass

@@ -4,7 +4,10 @@
 // (smallest singular value for the shift).
 //
 // Method: two-sided cyclic Jacobi.  Small matrices (<= 64) are solved by one
-// workgroup entirely in LDS.  Larger ones use block Jacobi: the index set is
+// workgroup entirely in LDS.  Larger ones are first rotated by the
+// eigenvectors of their 64 x 64 diagonal blocks (the method builds K = C C^T
+// block by block, and blocks of later power iterations couple weakly, so this
+// leaves little off-diagonal mass), then finished by block Jacobi: the index set is
 // cut into blocks of 16, blocks are paired by a round-robin tournament, every
 // pair's 32 x 32 principal submatrix is diagonalised in LDS (one workgroup per
 // pair), and the whole matrix is then rotated block-by-block,
@@ -17,7 +20,13 @@
 
 namespace farpca_int {
 
+// A pair (p, q) is left alone when |a_pq| <= 1e-14 sqrt(|a_pp a_qq|) (the
+// relative test that keeps Jacobi's small eigenvalues accurate) or when
+// |a_pq| <= 1e-13 max_i |a_ii|.  The absolute floor sits above the FP64
+// rounding that the block updates themselves leave behind (sums of 32 terms
+// of size max |a_ii|); with a floor at that level the sweeps never end.
 constexpr double kJacobiRel = 1e-14;
+constexpr double kJacobiAbs = 1e-13;
 constexpr int kInnerMaxSweeps = 30;
 
 __device__ __forceinline__ bool negligible(double apq, double app, double aqq, double floor_abs) {
@@ -51,7 +60,7 @@ __device__ void jacobi_lds(double *a, double *v, double floor_abs) {
         if (!negligible(apq, app, aqq, floor_abs)) {
           const double theta = (aqq - app) / (2.0 * apq);
           t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(fma(theta, theta, 1.0)));
-          c = 1.0 / sqrt(fma(t, t, 1.0));
+          c = rsqrt(fma(t, t, 1.0));
           s = t * c;
           on = 1;
           any_rot = 1;
@@ -120,7 +129,7 @@ __global__ __launch_bounds__(256) void eig_small_kernel(const double *__restrict
   if (tid == 0) {
     double mx = 0.0;
     for (int i = 0; i < s; ++i) mx = fmax(mx, fabs(a[i * kSmallLd + i]));
-    fl = mx * 1e-300;
+    fl = mx * kJacobiAbs;
   }
   __syncthreads();
   jacobi_lds<64, kSmallLd, 256>(a, v, fl);
@@ -158,23 +167,31 @@ __device__ __forceinline__ int sub_index(int u, int bi, int bj) {
 }
 
 // One workgroup per pair: diagonalise M[S, S], S = block(bi) U block(bj).
-__global__ __launch_bounds__(64) void bj_pair_kernel(const double *__restrict__ M, int64_t lp, int nb,
+__global__ __launch_bounds__(256) void bj_pair_kernel(const double *__restrict__ M, int64_t lp, int nb,
                                                      int step, double *__restrict__ R,
                                                      const double *__restrict__ floor_abs) {
   __shared__ double a[kSub * kSubLd];
   __shared__ double v[kSub * kSubLd];
   const int pair = blockIdx.x, tid = threadIdx.x;
   const int bi = rr_player(pair, step, nb), bj = rr_player(nb - 1 - pair, step, nb);
-  for (int e = tid; e < kSub * kSub; e += 64) {
+  for (int e = tid; e < kSub * kSub; e += 256) {
     const int u = e / kSub, x = e % kSub;
     a[u * kSubLd + x] = M[(int64_t)sub_index(u, bi, bj) * lp + sub_index(x, bi, bj)];
     v[u * kSubLd + x] = (u == x) ? 1.0 : 0.0;
   }
+  __shared__ int any_big;
+  if (tid == 0) any_big = 0;
   __syncthreads();
-  jacobi_lds<kSub, kSubLd, 64>(a, v, floor_abs[0]);
+  const double fl = floor_abs[0];
+  for (int e = tid; e < kSub * kSub; e += 256) {
+    const int u = e / kSub, x = e % kSub;
+    if (u < x && !negligible(a[u * kSubLd + x], a[u * kSubLd + u], a[x * kSubLd + x], fl)) any_big = 1;
+  }
+  __syncthreads();
+  if (any_big) jacobi_lds<kSub, kSubLd, 256>(a, v, fl);   // else R = I
   __syncthreads();
   double *Rp = R + (int64_t)pair * kSub * kSub;
-  for (int e = tid; e < kSub * kSub; e += 64) Rp[e] = v[(e / kSub) * kSubLd + (e % kSub)];
+  for (int e = tid; e < kSub * kSub; e += 256) Rp[e] = v[(e / kSub) * kSubLd + (e % kSub)];
 }
 
 // Rotate M (pair blocks) and V (row tiles x pair columns) in place.
@@ -237,28 +254,35 @@ __global__ __launch_bounds__(256) void bj_update_kernel(double *__restrict__ M, 
   }
 }
 
-// Count off-diagonal entries that are not negligible; also floor = max|diag| * 1e-300.
-__global__ __launch_bounds__(1024) void bj_check_kernel(const double *__restrict__ M, int64_t lp,
-                                                        int *__restrict__ count,
-                                                        double *__restrict__ floor_abs) {
-  __shared__ double mx[1024];
+// floor = kJacobiAbs * max |diag| (one workgroup over the diagonal).
+__global__ __launch_bounds__(256) void bj_floor_kernel(const double *__restrict__ M, int64_t lp,
+                                                       double abs_factor, int *__restrict__ count,
+                                                       double *__restrict__ floor_abs) {
+  __shared__ double mx[256];
   const int tid = threadIdx.x;
   double m = 0.0;
-  for (int64_t i = tid; i < lp; i += 1024) m = fmax(m, fabs(M[i * lp + i]));
+  for (int64_t i = tid; i < lp; i += 256) m = fmax(m, fabs(M[i * lp + i]));
   mx[tid] = m;
   __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
+  for (int s = 128; s > 0; s >>= 1) {
     if (tid < s) mx[tid] = fmax(mx[tid], mx[tid + s]);
     __syncthreads();
   }
-  const double fl = mx[0] * 1e-300;
+  if (tid == 0) { floor_abs[0] = mx[0] * abs_factor; count[0] = 0; }
+}
+
+// Count the off-diagonal pairs that are not negligible (one row per thread
+// block row; integer atomics, so the count is exact).
+__global__ __launch_bounds__(256) void bj_check_kernel(const double *__restrict__ M, int64_t lp,
+                                                       int *__restrict__ count,
+                                                       const double *__restrict__ floor_abs) {
+  const int64_t i = blockIdx.x;
+  const double fl = floor_abs[0];
+  const double aii = M[i * lp + i];
   int c = 0;
-  for (int64_t e = tid; e < lp * lp; e += 1024) {
-    const int64_t i = e / lp, j = e % lp;
-    if (i < j && !negligible(M[i * lp + j], M[i * lp + i], M[j * lp + j], fl)) ++c;
-  }
+  for (int64_t j = i + 1 + threadIdx.x; j < lp; j += 256)
+    if (!negligible(M[i * lp + j], aii, M[j * lp + j], fl)) ++c;
   if (c) atomicAdd(count, c);
-  if (tid == 0) floor_abs[0] = fl;
 }
 
 __global__ void bj_init_kernel(const double *__restrict__ K, int64_t l, int64_t lp,
@@ -267,7 +291,75 @@ __global__ void bj_init_kernel(const double *__restrict__ K, int64_t l, int64_t 
   if (e >= lp * lp) return;
   const int64_t i = e / lp, j = e % lp;
   M[e] = (i < l && j < l) ? K[i * l + j] : 0.0;
-  V[e] = (i == j) ? 1.0 : 0.0;
+  V[e] = 0.0;
+}
+
+// Preconditioning: diagonalise every 64 x 64 diagonal block M[I, I] (the
+// method's blocks make K nearly block-diagonal) and store its eigenvectors as
+// the diagonal block V[I, I] of the starting basis.
+constexpr int kPre = 64;
+__global__ __launch_bounds__(256) void bj_pre_eig_kernel(const double *__restrict__ M, int64_t lp,
+                                                         double *__restrict__ V) {
+  __shared__ double a[kPre * kSmallLd];
+  __shared__ double v[kPre * kSmallLd];
+  __shared__ double fl;
+  const int tid = threadIdx.x;
+  const int64_t o = (int64_t)blockIdx.x * kPre;
+  for (int e = tid; e < kPre * kPre; e += 256) {
+    const int i = e / kPre, j = e % kPre;
+    a[i * kSmallLd + j] = M[(o + i) * lp + o + j];
+    v[i * kSmallLd + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < kPre; ++i) mx = fmax(mx, fabs(a[i * kSmallLd + i]));
+    fl = mx * kJacobiAbs;
+  }
+  __syncthreads();
+  jacobi_lds<kPre, kSmallLd, 256>(a, v, fl);
+  __syncthreads();
+  for (int e = tid; e < kPre * kPre; e += 256) {
+    const int i = e / kPre, j = e % kPre;
+    V[(o + i) * lp + o + j] = v[i * kSmallLd + j];
+  }
+}
+
+// M[I, J] <- W_I^T M[I, J] W_J with W_I = V[I, I] (64 x 64 blocks, in place:
+// each workgroup reads and writes only its own block).
+__global__ __launch_bounds__(256) void bj_pre_rotate_kernel(double *__restrict__ M,
+                                                            const double *__restrict__ V, int64_t lp) {
+  __shared__ double blk[kPre * kSmallLd];
+  __shared__ double w[kPre * kSmallLd];
+  const int tid = threadIdx.x;
+  const int64_t oi = (int64_t)blockIdx.x * kPre, oj = (int64_t)blockIdx.y * kPre;
+  // tmp = M_IJ W_J  (into blk after the first pass)
+  for (int e = tid; e < kPre * kPre; e += 256) {
+    const int i = e / kPre, j = e % kPre;
+    blk[i * kSmallLd + j] = M[(oi + i) * lp + oj + j];
+    w[i * kSmallLd + j] = V[(oj + i) * lp + oj + j];
+  }
+  __syncthreads();
+  double t[16];
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q, i = e / kPre, j = e % kPre;
+    double s = 0.0;
+    for (int k = 0; k < kPre; ++k) s = fma(blk[i * kSmallLd + k], w[k * kSmallLd + j], s);
+    t[q] = s;
+  }
+  __syncthreads();
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q, i = e / kPre, j = e % kPre;
+    blk[i * kSmallLd + j] = t[q];
+    w[i * kSmallLd + j] = V[(oi + i) * lp + oi + j];
+  }
+  __syncthreads();
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q, i = e / kPre, j = e % kPre;
+    double s = 0.0;
+    for (int k = 0; k < kPre; ++k) s = fma(w[k * kSmallLd + i], blk[k * kSmallLd + j], s);
+    M[(oi + i) * lp + oj + j] = s;
+  }
 }
 
 __global__ void bj_rank_kernel(const double *__restrict__ M, int64_t l, int64_t lp,
@@ -294,7 +386,7 @@ __global__ void bj_gather_kernel(const double *__restrict__ M, const double *__r
   if (r == 0) w[k] = M[(int64_t)src * lp + src];
 }
 
-static int64_t padded(int64_t l) { return (l + kSub - 1) / kSub * kSub; }
+static int64_t padded(int64_t l) { return (l + kPre - 1) / kPre * kPre; }
 
 size_t eig_workspace_bytes(int64_t l) {
   const int64_t lp = padded(l);
@@ -325,18 +417,22 @@ int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, hip
   double *floor_abs = reinterpret_cast<double *>(p + 8);
 
   const int64_t tot = lp * lp;
+  const double abs_factor = kJacobiAbs;
   hipLaunchKernelGGL(bj_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, K, l, lp, M, V);
+  const int npre = (int)(lp / kPre);
+  hipLaunchKernelGGL(bj_pre_eig_kernel, dim3(npre), dim3(256), 0, st, M, lp, V);
+  hipLaunchKernelGGL(bj_pre_rotate_kernel, dim3(npre, npre), dim3(256), 0, st, M, V, lp);
   int sweeps = 0;
   const int max_sweeps = 40;
   for (; sweeps < max_sweeps; ++sweeps) {
-    hipMemsetAsync(count, 0, sizeof(int), st);
-    hipLaunchKernelGGL(bj_check_kernel, dim3(1), dim3(1024), 0, st, M, lp, count, floor_abs);
+    hipLaunchKernelGGL(bj_floor_kernel, dim3(1), dim3(256), 0, st, M, lp, abs_factor, count, floor_abs);
+    hipLaunchKernelGGL(bj_check_kernel, dim3((unsigned)lp), dim3(256), 0, st, M, lp, count, floor_abs);
     int h_count = 0;
     hipMemcpyAsync(&h_count, count, sizeof(int), hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
     if (h_count == 0) break;
     for (int step = 0; step < nb - 1; ++step) {
-      hipLaunchKernelGGL(bj_pair_kernel, dim3(npairs), dim3(64), 0, st, M, lp, nb, step, R, floor_abs);
+      hipLaunchKernelGGL(bj_pair_kernel, dim3(npairs), dim3(256), 0, st, M, lp, nb, step, R, floor_abs);
       const int64_t nwg = (int64_t)npairs * npairs + (lp / kSub) * npairs;
       hipLaunchKernelGGL(bj_update_kernel, dim3((unsigned)nwg), dim3(256), 0, st, M, V, lp, nb, step, R);
     }

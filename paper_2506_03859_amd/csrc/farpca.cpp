@@ -59,6 +59,9 @@ struct farpca_plan_s {
       off_v64, off_setup, off_sq, off_scal, off_ehist, off_kbig, off_eig, off_wfin, off_vfin,
       off_u32, off_gbig, total;
   size_t gbig_bytes;
+  int64_t part_floats;  // capacity of the K-split partial buffer
+  // K splits the partial buffer holds for an M-row product
+  int64_t part_splits(int64_t M) const { return M > 0 ? part_floats / (M * kBld) : 1; }
 };
 
 namespace {
@@ -171,12 +174,13 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   pl->off_mask = c.take((size_t)n * 8);
   pl->off_neg = c.take((size_t)n * 8);
   pl->off_colptr = c.take((size_t)pl->nchunks * (kMaxBlock + 1) * 4);
-  pl->off_ent = c.take((size_t)pl->nchunks * kChunk * kMaxBlock * sizeof(ChunkEntry));
+  pl->off_ent = c.take((size_t)pl->nchunks * kEntCap * sizeof(ChunkEntry));
   pl->off_z = c.take((size_t)m * 4);
   pl->off_rowsum = c.take((size_t)m * 8);
   pl->off_r = c.take((size_t)ldq * kBld * 4);
-  pl->off_part = c.take((size_t)16 * mnl * kBld * 4);
-  pl->off_gpart = c.take((size_t)256 * kMaxBlock * kMaxBlock * 8);   // <= 256 partials for any K
+  pl->part_floats = 16 * mnl * kBld;
+  pl->off_part = c.take((size_t)pl->part_floats * 4);
+  pl->off_gpart = c.take((size_t)64 * kMaxBlock * kMaxBlock * 8);    // <= 64 partials for any K
   pl->off_g64 = c.take((size_t)kMaxBlock * kMaxBlock * 8);
   pl->off_rinv = c.take((size_t)kMaxBlock * kMaxBlock * 8);
   pl->off_w64 = c.take((size_t)kMaxBlock * 8);
@@ -203,6 +207,49 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
 extern "C" void farpca_free(farpca_plan_t *plan) { delete plan; }
 
 namespace {
+
+// Opt-in event timing of the kernels that stream A (hipEvents recorded on the
+// caller's stream around each launch; resolved when farpca_run returns).
+struct ProfClass { double total_ms = 0.0; int64_t count = 0; };
+struct Prof {
+  bool on = false;
+  ProfClass cls[FARPCA_PROF_NCLASS];
+  struct Pending { hipEvent_t a, b; int c; };
+  Pending pend[4096];
+  int npend = 0;
+};
+Prof g_prof;
+
+struct ProfScope {
+  hipStream_t st;
+  int c;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(int cls, hipStream_t s) : st(s), c(cls) {
+    if (!g_prof.on || g_prof.npend >= 4096) return;
+    if (hipEventCreate(&a) != hipSuccess) { a = nullptr; return; }
+    if (hipEventCreate(&b) != hipSuccess) { hipEventDestroy(a); a = nullptr; return; }
+    hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEventRecord(b, st);
+    g_prof.pend[g_prof.npend++] = {a, b, c};
+  }
+};
+
+void prof_resolve() {
+  for (int i = 0; i < g_prof.npend; ++i) {
+    auto &p = g_prof.pend[i];
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      g_prof.cls[p.c].total_ms += ms;
+      g_prof.cls[p.c].count += 1;
+    }
+    hipEventDestroy(p.a);
+    hipEventDestroy(p.b);
+  }
+  g_prof.npend = 0;
+}
 
 OmegaSpec omega_spec(const farpca_plan_s *pl) {
   OmegaSpec s;
@@ -231,19 +278,28 @@ void sketch(const farpca_plan_s *pl, const Ws &w, const float *A, float *S, hipS
   const farpca_params &q = pl->prm;
   float *part = w.at<float>(pl->off_part);
   if (pl->kind == FARPCA_GAUSSIAN) {
-    launch_gemm_nn(A, q.lda, w.at<float>(pl->off_om), kBld, S, kBld, q.m, kBld, q.n, 1.f, 0.f,
-                   gemm_choose_ksplit(q.m, q.n, 0), part, st);
+    int nsp;
+    {
+      ProfScope ps(FARPCA_PROF_GEMM_NN, st);
+      nsp = launch_gemm_nn_main(A, q.lda, w.at<float>(pl->off_om), kBld, S, kBld, q.m, kBld, q.n, 1.f,
+                                0.f, gemm_choose_ksplit(q.m, q.n, 0, pl->part_splits(q.m)), part, st);
+    }
+    launch_gemm_finish(part, nsp, q.m, kBld, S, kBld, 1.f, 0.f, st);
     return;
   }
   const float *z = (pl->kind == FARPCA_STD_BERNOULLI) ? w.at<float>(pl->off_z) : nullptr;
   const float scale = pl->sketch_scale;
   const int ns = sketch_choose_split(q.m, q.n);
   if (ns <= 1) {
+    ProfScope ps(FARPCA_PROF_SKETCH, st);
     launch_sketch_full(A, q.lda, q.m, q.n, pl->b, w.at<uint32_t>(pl->off_colptr),
                        w.at<ChunkEntry>(pl->off_ent), S, 1, scale, z, -1.f, st);
   } else {
-    launch_sketch_full(A, q.lda, q.m, q.n, pl->b, w.at<uint32_t>(pl->off_colptr),
-                       w.at<ChunkEntry>(pl->off_ent), part, ns, scale, z, -1.f, st);
+    {
+      ProfScope ps(FARPCA_PROF_SKETCH, st);
+      launch_sketch_full(A, q.lda, q.m, q.n, pl->b, w.at<uint32_t>(pl->off_colptr),
+                         w.at<ChunkEntry>(pl->off_ent), part, ns, scale, z, -1.f, st);
+    }
     // number of splits actually launched
     const int64_t nchunks = pl->nchunks;
     const int64_t cps = (nchunks + ns - 1) / ns;
@@ -262,7 +318,7 @@ void project_out(const farpca_plan_s *pl, const Ws &w, int64_t l, float *T, hipS
   float *part = w.at<float>(pl->off_part);
   for (int pass = 0; pass < 2; ++pass) {
     launch_gemm_tn(Q, pl->ldq, T, kBld, r, kBld, l, pl->b, q.m, 1.f, 0.f,
-                   gemm_choose_ksplit(l, q.m, 1), part, st);
+                   gemm_choose_ksplit(l, q.m, 1, pl->part_splits(l)), part, st);
     launch_gemm_nn(Q, pl->ldq, r, kBld, T, kBld, q.m, pl->b, l, -1.f, 1.f, 1, part, st);
   }
 }
@@ -282,8 +338,8 @@ void cholqr(const farpca_plan_s *pl, const Ws &w, float *X, int64_t K, int passe
     if (pass == 0 && gram_eig)
       launch_eig_small(G, pl->b, kMaxBlock, w.at<double>(pl->off_w64), w.at<double>(pl->off_v64),
                        kMaxBlock, st);
-    launch_chol_inv(G, pl->b, kDropRel, Rinv, flags, st);
-    launch_apply_small(X, kBld, K, pl->b, Rinv, X, kBld, st);
+    launch_chol(G, pl->b, kDropRel, Rinv, flags, st);
+    launch_trsm_rows(X, kBld, K, pl->b, Rinv, X, kBld, st);
   }
 }
 
@@ -343,28 +399,48 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
       float *T = S;
       for (int k = 1; k <= pl->P; ++k) {
         project_out(pl, w, l, T, st);
-        launch_gemm_tn(A, q.lda, T, kBld, X, kBld, n, b, m, 1.f, 0.f,
-                       gemm_choose_ksplit(n, m, 1), part, st);
+        int nsp;
+        {
+          ProfScope ps(FARPCA_PROF_GEMM_TN, st);
+          nsp = launch_gemm_tn_main(A, q.lda, T, kBld, X, kBld, n, b, m, 1.f, 0.f,
+                                    gemm_choose_ksplit(n, m, 1, pl->part_splits(n)), part, st);
+        }
+        launch_gemm_finish(part, nsp, n, b, X, kBld, 1.f, 0.f, st);
         if (k >= 2 && pl->P > 2) launch_axpy_block(X, kBld, G, kBld, n, b, alpha, st);
         cholqr(pl, w, X, n, 3, pl->P > 2, st);
         if (k >= 2 && pl->P > 2) launch_alpha_update(w.at<double>(pl->off_w64), b, alpha, st);
         launch_copy_block(X, kBld, n, b, G, kBld, st);
         if (k < pl->P) {
-          launch_gemm_nn(A, q.lda, G, kBld, S, kBld, m, b, n, 1.f, 0.f,
-                         gemm_choose_ksplit(m, n, 0), part, st);
+          int nsp2;
+          {
+            ProfScope ps(FARPCA_PROF_GEMM_NN, st);
+            nsp2 = launch_gemm_nn_main(A, q.lda, G, kBld, S, kBld, m, b, n, 1.f, 0.f,
+                                       gemm_choose_ksplit(m, n, 0, pl->part_splits(m)), part, st);
+          }
+          launch_gemm_finish(part, nsp2, m, b, S, kBld, 1.f, 0.f, st);
           T = S;
         }
       }
-      launch_gemm_nn(A, q.lda, G, kBld, Yb, kBld, m, b, n, 1.f, 0.f, gemm_choose_ksplit(m, n, 0),
-                     part, st);
+      int nsp3;
+      {
+        ProfScope ps(FARPCA_PROF_GEMM_NN, st);
+        nsp3 = launch_gemm_nn_main(A, q.lda, G, kBld, Yb, kBld, m, b, n, 1.f, 0.f,
+                                   gemm_choose_ksplit(m, n, 0, pl->part_splits(m)), part, st);
+      }
+      launch_gemm_finish(part, nsp3, m, b, Yb, kBld, 1.f, 0.f, st);
       Ysrc = Yb;
     }
     // Basis extension: Y_j against Q, orthonormalise, append; C_j^T = A^T Q_j.
     project_out(pl, w, l, Ysrc, st);
     cholqr(pl, w, Ysrc, m, 3, false, st);
     launch_copy_block(Ysrc, kBld, m, b, Q + l, pl->ldq, st);
-    launch_gemm_tn(A, q.lda, Ysrc, kBld, Ct + l, pl->ldq, n, b, m, 1.f, 0.f,
-                   gemm_choose_ksplit(n, m, 1), part, st);
+    int nsp4;
+    {
+      ProfScope ps(FARPCA_PROF_GEMM_TN, st);
+      nsp4 = launch_gemm_tn_main(A, q.lda, Ysrc, kBld, Ct + l, pl->ldq, n, b, m, 1.f, 0.f,
+                                 gemm_choose_ksplit(n, m, 1, pl->part_splits(n)), part, st);
+    }
+    launch_gemm_finish(part, nsp4, n, b, Ct + l, pl->ldq, 1.f, 0.f, st);
     launch_sqnorm(Ct + l, pl->ldq, n, b, w.at<double>(pl->off_sq), st);
     launch_indicator_update(w.at<double>(pl->off_sq), sqnorm_num_partials(n), E, ehist, j, st);
     l += b;
@@ -386,7 +462,11 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
   double *vfin = w.at<double>(pl->off_vfin);
   float *u32 = w.at<float>(pl->off_u32);
   launch_gram_big(Ct, pl->ldq, n, l, Kbig, w.at<void>(pl->off_gbig), pl->gbig_bytes, st);
-  const int sweeps = eig_sym(Kbig, l, wfin, vfin, w.at<void>(pl->off_eig), st);
+  int sweeps;
+  {
+    ProfScope ps(FARPCA_PROF_EIG, st);
+    sweeps = eig_sym(Kbig, l, wfin, vfin, w.at<void>(pl->off_eig), st);
+  }
   launch_sqrt_clip(wfin, rout, dS, st);
   // U = Q U~ (first rout columns)
   launch_convert_f64_f32(vfin, l, rout, l, nullptr, u32, rout, st);
@@ -406,6 +486,7 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
   HIP_OK(hipMemcpyAsync(h_tail, scal, 32, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   HIP_OK(hipGetLastError());
+  if (g_prof.on) prof_resolve();
   if (info) {
     info->rank_l = l;
     info->rank_out = rout;
@@ -459,7 +540,7 @@ extern "C" int farpca_gemm_nn(const float *dA, int64_t lda, const float *dX, int
                               void *stream) {
   if (!dA || !dX || !dC || M < 1 || K < 1 || N < 1 || N > kBld || lda < K || ldx < N || ldc < N)
     return FARPCA_E_INVALID;
-  const int ks = gemm_choose_ksplit(M, K, 0);
+  const int ks = gemm_choose_ksplit(M, K, 0, 16);
   if (ks > 1 && !dPart) return FARPCA_E_INVALID;
   launch_gemm_nn(dA, lda, dX, ldx, dC, ldc, M, N, K, 1.f, 0.f, ks, dPart,
                  static_cast<hipStream_t>(stream));
@@ -472,7 +553,7 @@ extern "C" int farpca_gemm_tn(const float *dA, int64_t lda, const float *dY, int
                               void *stream) {
   if (!dA || !dY || !dC || M < 1 || K < 1 || N < 1 || N > kBld || lda < M || ldy < N || ldc < N)
     return FARPCA_E_INVALID;
-  const int ks = gemm_choose_ksplit(M, K, 1);
+  const int ks = gemm_choose_ksplit(M, K, 1, 16);
   if (ks > 1 && !dPart) return FARPCA_E_INVALID;
   launch_gemm_tn(dA, lda, dY, ldy, dC, ldc, M, N, K, 1.f, 0.f, ks, dPart,
                  static_cast<hipStream_t>(stream));
@@ -488,4 +569,19 @@ extern "C" int farpca_eig(const double *dK, int64_t l, double *dW, double *dV, v
   const int sweeps = eig_sym(dK, l, dW, dV, dWork, static_cast<hipStream_t>(stream));
   HIP_OK(hipGetLastError());
   return sweeps;
+}
+
+extern "C" void farpca_profile_enable(int on) {
+  if (!on && g_prof.npend) prof_resolve();
+  g_prof.on = on != 0;
+  if (on) {
+    for (auto &c : g_prof.cls) c = ProfClass();
+  }
+}
+
+extern "C" int farpca_profile_get(int cls, double *total_ms, int64_t *count) {
+  if (cls < 0 || cls >= FARPCA_PROF_NCLASS || !total_ms || !count) return FARPCA_E_INVALID;
+  *total_ms = g_prof.cls[cls].total_ms;
+  *count = g_prof.cls[cls].count;
+  return FARPCA_OK;
 }

@@ -4,199 +4,326 @@
 //
 //   NN: C[M x N] = A[M x K] X[K x N]        (A row-major, reduce along a row)
 //   TN: C[M x N] = A^T Y, A is K x M        (A row-major, reduce over rows)
-// N <= 64 (one block of the method).  A workgroup = 4 waves owns a 64 x 64
-// output tile; the 4 waves take interleaved 16-deep slices of K and their
-// accumulators are summed through LDS in a fixed order.  Grid dimension y
-// splits K further (partial tiles + reduce_partials) when the output alone
-// has too few tiles to fill 256 CUs.
+// N <= 64 (one block of the method); X / Y is the "skinny" operand.
 //
-// Operand trick: a dot product may visit K in any order as long as both
-// operands use the same order.  In NN each lane loads 4 consecutive K values
-// of one A row with one 16-byte load and feeds them to 4 successive MFMAs
-// (K slot l/16 of MFMA t <-> k = k0 + 4 (l/16) + t); X is read with the same
-// mapping.  In TN each lane loads 4 consecutive columns of one A row (16
-// bytes); component t feeds MFMA t, whose 16 output rows are then the
-// columns c0 + 4 i + t (an interleaved output tile).
+// A workgroup has 4 waves.  Each wave accumulates one 64 x 64 output tile in
+// registers.  Two layouts (template WM = waves along the output dimension):
+//   WM = 4  the 4 waves own 4 consecutive output tiles (256 rows) and walk
+//           the same K range: every staged skinny chunk feeds 4 tiles, so the
+//           skinny operand costs a quarter of A's bytes (large M);
+//   WM = 1  the 4 waves share one output tile and take interleaved 16-deep
+//           K slices; their accumulators are summed through LDS in a fixed
+//           order at the end (small M: more workgroups per output tile).
+// Grid: tiles x K splits, flattened and remapped so that the workgroups of
+// one K split run on the same XCD (consecutive logical ids share an L2 there
+// and with it the skinny chunk).  With more than one split the kernel writes
+// partial tiles and reduce_partials sums them in split order.
+//
+// Per 16-deep K slice a lane issues 4 16-byte loads of A (registers, fetched
+// one chunk ahead), reads 16 skinny values from LDS and issues 64 MFMAs.  The
+// skinny chunk is staged in LDS row-major (stride 68 floats: the 16-byte
+// stores and the 4-byte reads are bank-conflict free), double buffered, one
+// barrier per chunk.
+//
+// K order: a dot product may visit K in any order as long as both operands
+// use the same one.  NN: lane (li = l%16, lk = l/16) loads 4 consecutive K
+// values of A row 16 rt + li; component t feeds MFMA t, whose K slot lk is
+// k = k0 + 4 lk + t.  TN: lane loads 4 consecutive A columns c0 + 4 li .. +3
+// of A rows k0 + 4 lk + q; component t feeds MFMA (q, t), whose 16 output
+// rows are then the columns c0 + 4 i + t (an interleaved output tile).  In
+// both the skinny operand is read at chunk row 16 wk + 4 lk + u, column
+// 16 ct + li.
 //
 // MFMA 16x16x4 f32 operand layout (wave64): A lane l = (row l%16, k l/16),
 // B lane l = (k l/16, col l%16), D lane l element v = (row 4 (l/16) + v, col l%16).
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "internal.h"
 
 namespace farpca_int {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+constexpr int kXs = 68;   // floats per staged skinny row (64 + 4 pad)
+
 __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-template <bool VEC>
-__device__ __forceinline__ float4 load4_guard(const float *__restrict__ p, int64_t idx, int64_t lim) {
-  // p points at element idx of a row with `lim` valid entries.
-  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (VEC && idx + 3 < lim) {
-    v = *reinterpret_cast<const float4 *>(p);
-  } else {
-    if (idx + 0 < lim) v.x = p[0];
-    if (idx + 1 < lim) v.y = p[1];
-    if (idx + 2 < lim) v.z = p[2];
-    if (idx + 3 < lim) v.w = p[3];
-  }
-  return v;
 }
 
 __device__ __forceinline__ float comp(const float4 &v, int t) {
   return t == 0 ? v.x : (t == 1 ? v.y : (t == 2 ? v.z : v.w));
 }
 
-// Sum the 4 waves' 64x64 accumulators (acc[16] floatx4 per lane) into wave 0.
-__device__ __forceinline__ void wave_reduce(floatx4 (&acc)[16], float *red, int wave, int lane) {
-  if (wave > 0) {
-    float *dst = red + (wave - 1) * (16 * 4 * 64);
+__device__ __forceinline__ int64_t clampi(int64_t v, int64_t hi) { return v < hi ? v : hi; }
+
+// Logical workgroup id: physical ids g = 8 j + x run on XCD x; the first
+// 8 floor(T/8) ids are regrouped so that XCD x gets a contiguous logical range.
+__device__ __forceinline__ int64_t xcd_remap(int64_t g, int64_t T) {
+  const int64_t T8 = T & ~int64_t(7);
+  if (g >= T8) return g;
+  return (g & 7) * (T8 >> 3) + (g >> 3);
+}
+
+// Per-lane A base pointer (the part of the address fixed for the whole K
+// range).  Rows (NN) / columns (TN) outside M are clamped into the matrix:
+// they only feed outputs that are never stored.
+template <bool TN, bool AVEC>
+__device__ __forceinline__ const float *a_base(const float *__restrict__ A, int64_t lda,
+                                               int64_t M, int64_t t0, int li, int lk) {
+  if (!TN) return A + 4 * lk;                       // + row * lda + k0 per load
+  int64_t col = t0 + 4 * li;
+  if (AVEC) col = col < M - 4 ? col : M - 4;        // AVEC: M % 4 == 0, M >= 4
+  return A + 4 * lk * lda + col;                    // + (k0 + q) * lda per load
+}
+
+// A-operand loads of one full 16-deep slice at k0 (inside K): 4 float4 per lane.
+template <bool TN, bool AVEC>
+__device__ __forceinline__ void load_a_full(const float *__restrict__ ab, int64_t lda, int64_t M,
+                                            int64_t t0, int li, int64_t k0, float4 (&a)[4]) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
+  for (int q = 0; q < 4; ++q) {
+    const float *p;
+    if (!TN) {
+      const int64_t row = clampi(t0 + 16 * q + li, M - 1);
+      p = ab + row * lda + k0;
+    } else {
+      p = ab + (k0 + q) * lda;
+    }
+    if (AVEC) {
+      a[q] = *reinterpret_cast<const float4 *>(p);
+    } else if (!TN) {
+      a[q] = make_float4(p[0], p[1], p[2], p[3]);
+    } else {
+      // scalar columns, each clamped into M (p is at column t0 + 4 li)
+      const int64_t col = t0 + 4 * li;
+      float v[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) dst[(q * 4 + v) * 64 + lane] = acc[q][v];
-  }
-  __syncthreads();
-  if (wave == 0) {
-#pragma unroll
-    for (int w = 0; w < 3; ++w) {
-      const float *src = red + w * (16 * 4 * 64);
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[q][v] += src[(q * 4 + v) * 64 + lane];
+      for (int t = 0; t < 4; ++t) v[t] = p[clampi(col + t, M - 1) - col];
+      a[q] = make_float4(v[0], v[1], v[2], v[3]);
     }
   }
 }
 
-// ---------------------------------------------------------------- NN
-template <bool VEC>
-__global__ __launch_bounds__(256) void gemm_nn_kernel(const float *__restrict__ A, int64_t lda,
+// The same for the last, partial slice: addresses clamped into [.., ke) and
+// values beyond K zeroed (scalar loads).
+template <bool TN>
+__device__ __forceinline__ void load_a_tail(const float *__restrict__ A, int64_t lda, int64_t M,
+                                            int64_t ke, int64_t t0, int li, int lk, int64_t k0,
+                                            float4 (&a)[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float v[4];
+    if (!TN) {
+      const float *p = A + clampi(t0 + 16 * q + li, M - 1) * lda;
+      const int64_t kk = k0 + 4 * lk;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float u = p[clampi(kk + t, ke - 1)];
+        v[t] = (kk + t < ke) ? u : 0.0f;
+      }
+    } else {
+      const int64_t k = k0 + 4 * lk + q;
+      const float *p = A + clampi(k, ke - 1) * lda;
+      const int64_t col = t0 + 4 * li;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float u = p[clampi(col + t, M - 1)];
+        v[t] = (k < ke) ? u : 0.0f;
+      }
+    }
+    a[q] = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// Skinny chunk rows [kc, kc + 16 NX) into registers: thread tid holds float4
+// number f = tid + 256 j (chunk row f / 16, columns 4 (f % 16) .. +3).
+// XVEC (N == 64, rows 16-byte aligned) and rows inside K: one 16-byte load;
+// otherwise clamped scalar loads, zero outside K x N.
+template <int NX, bool XVEC>
+__device__ __forceinline__ void load_x(const float *__restrict__ X, int64_t ldx, int64_t N,
+                                       int64_t ke, int64_t kc, int tid, bool full,
+                                       float4 (&xr)[NX]) {
+#pragma unroll
+  for (int j = 0; j < NX; ++j) {
+    const int f = tid + 256 * j;
+    const int64_t k = kc + (f >> 4);
+    const int col = 4 * (f & 15);
+    if (XVEC && full) {
+      xr[j] = *reinterpret_cast<const float4 *>(X + k * ldx + col);
+    } else {
+      const float *p = X + clampi(k, ke - 1) * ldx;
+      float v[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float u = p[clampi(col + t, N - 1)];
+        v[t] = (k < ke && col + t < N) ? u : 0.0f;
+      }
+      xr[j] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+}
+
+template <int NX>
+__device__ __forceinline__ void store_x(float *xs, int tid, const float4 (&xr)[NX]) {
+#pragma unroll
+  for (int j = 0; j < NX; ++j) {
+    const int f = tid + 256 * j;
+    *reinterpret_cast<float4 *>(xs + (f >> 4) * kXs + 4 * (f & 15)) = xr[j];
+  }
+}
+
+// 64 MFMAs of one 16-deep slice: skinny values from LDS rows 4 lk + u of
+// the slice.
+template <bool TN>
+__device__ __forceinline__ void mma_slice(floatx4 (&acc)[16], const float4 (&a)[4],
+                                          const float *xslice, int li, int lk) {
+  const float *xb = xslice + 4 * lk * kXs + li;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    float xv[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) xv[ct] = xb[u * kXs + 16 * ct];
+    if (!TN) {
+      // NN: MFMA u takes component u of every row group rt
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+          acc[rt * 4 + ct] = mfma4(comp(a[rt], u), xv[ct], acc[rt * 4 + ct]);
+    } else {
+      // TN: load u (A row k0 + 4 lk + u) feeds the 4 interleaved column groups t
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+          acc[t * 4 + ct] = mfma4(comp(a[u], t), xv[ct], acc[t * 4 + ct]);
+    }
+  }
+}
+
+template <bool TN, int WM, bool AVEC, bool XVEC>
+__global__ __launch_bounds__(256, AVEC ? 3 : 2) void gemm_kernel(const float *__restrict__ A, int64_t lda,
                                                       const float *__restrict__ X, int64_t ldx,
                                                       float *__restrict__ C, int64_t ldc,
                                                       int64_t M, int64_t N, int64_t K,
-                                                      int64_t k_per_split, float alpha, float beta,
+                                                      int64_t kps, int64_t tiles, int64_t total,
+                                                      float alpha, float beta,
                                                       float *__restrict__ part) {
-  __shared__ float red[3 * 16 * 4 * 64];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * 64;
-  const int64_t kb = (int64_t)blockIdx.y * k_per_split;
-  int64_t ke = kb + k_per_split;
-  if (ke > K) ke = K;
+  constexpr int WK = 4 / WM;
+  constexpr int SL = (WM == 4) ? 2 : 1;   // 16-deep slices per wave per chunk
+  constexpr int KW = 16 * SL;             // K rows per wave per chunk
+  constexpr int KC = KW * WK;             // skinny rows per staged chunk
+  constexpr int NX = KC / 16;             // skinny float4 loads per thread per chunk
+  __shared__ float xs[2][KC * kXs];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wk = wave / WM;
   const int li = lane & 15, lk = lane >> 4;
+
+  const int64_t L = xcd_remap(blockIdx.x, total);
+  const int64_t tile = L % tiles, split = L / tiles;
+  const int64_t t0 = (tile * WM + wm) * 64;        // first output row of this wave's tile
+  const int64_t kb = split * kps;
+  const int64_t ke = (kb + kps < K) ? kb + kps : K;
+  const int64_t nfull = (ke - kb) / KC;            // chunks entirely inside [kb, ke)
+  const float *ab = a_base<TN, AVEC>(A, lda, M, t0, li, lk);
 
   floatx4 acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t k0 = kb + 16 * wave; k0 < ke; k0 += 64) {
-    const int64_t kk = k0 + 4 * lk;
-    float4 a[4];
+  // Chunk c: A slices in `cur`, skinny rows in xs[c & 1].  Chunk c + 1 is
+  // fetched (A into `nxt`, skinny rows into `xr`) before the MFMAs of chunk
+  // c; the scheduling barriers keep the compiler from sinking those loads
+  // below the MFMAs, which would serialise memory latency and compute.
+  float4 cur[SL][4], nxt[SL][4], xr[NX];
+  auto fetch = [&](int64_t c, float4 (&a)[SL][4]) {
+    const int64_t kc = kb + c * KC;
+    load_x<NX, XVEC>(X, ldx, N, ke, kc, tid, true, xr);
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      const int64_t row = row0 + 16 * rt + li;
-      a[rt] = (row < M) ? load4_guard<VEC>(A + row * lda + kk, kk, ke) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int s = 0; s < SL; ++s)
+      load_a_full<TN, AVEC>(ab, lda, M, t0, li, kc + KW * wk + 16 * s, a[s]);
+  };
+  auto mma_chunk = [&](int64_t c) {
+#pragma unroll
+    for (int s = 0; s < SL; ++s) mma_slice<TN>(acc, cur[s], xs[c & 1] + (KW * wk + 16 * s) * kXs, li, lk);
+  };
+
+  if (nfull > 0) {
+    fetch(0, cur);
+    store_x<NX>(xs[0], tid, xr);
+    __syncthreads();
+    for (int64_t c = 0; c + 1 < nfull; ++c) {
+      fetch(c + 1, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_chunk(c);
+      __builtin_amdgcn_sched_barrier(0);
+      store_x<NX>(xs[(c + 1) & 1], tid, xr);
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < SL; ++s)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cur[s][q] = nxt[s][q];
     }
-    float x[4][4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        const int64_t k = kk + t;
-        const int64_t col = 16 * ct + li;
-        x[t][ct] = (k < ke && col < N) ? X[k * ldx + col] : 0.0f;
-      }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[rt * 4 + ct] = mfma4(comp(a[rt], t), x[t][ct], acc[rt * 4 + ct]);
+    mma_chunk(nfull - 1);
+    __syncthreads();
   }
-  wave_reduce(acc, red, wave, lane);
-  if (wave != 0) return;
-  // acc[rt*4+ct] element v: row = row0 + 16 rt + 4 lk + v, col = 16 ct + li
-  float *dst = part ? part + (int64_t)blockIdx.y * M * kBld : C;
+  if (kb + nfull * KC < ke) {
+    // the partial last chunk (every reader of xs has passed the last barrier)
+    const int64_t kc = kb + nfull * KC;
+    load_x<NX, false>(X, ldx, N, ke, kc, tid, false, xr);
+#pragma unroll
+    for (int s = 0; s < SL; ++s)
+      load_a_tail<TN>(A, lda, M, ke, t0, li, lk, kc + KW * wk + 16 * s, cur[s]);
+    store_x<NX>(xs[0], tid, xr);
+    __syncthreads();
+    mma_chunk(0);
+    __syncthreads();
+  }
+
+  if (WK > 1) {
+    // fixed-order sum of the 4 K-interleaved accumulators into wave 0:
+    // (w0 + w2) + (w1 + w3), staged through the (now free) skinny buffers
+    // (2 KC kXs >= 2 x 4096 floats)
+    float *red = &xs[0][0];
+    auto put = [&](int slot) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[slot * 4096 + (q * 4 + v) * 64 + lane] = acc[q][v];
+    };
+    auto add = [&](int slot) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[q][v] += red[slot * 4096 + (q * 4 + v) * 64 + lane];
+    };
+    if (wave >= 2) put(wave - 2);
+    __syncthreads();
+    if (wave < 2) add(wave);
+    __syncthreads();
+    if (wave == 1) put(0);
+    __syncthreads();
+    if (wave != 0) return;
+    add(0);
+  }
+
+  float *dst = part ? part + split * M * kBld : C;
   const int64_t ld = part ? kBld : ldc;
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
+  for (int g = 0; g < 4; ++g)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = row0 + 16 * rt + 4 * lk + v;
+        // NN: acc[rt*4+ct][v] -> row t0 + 16 rt + 4 lk + v
+        // TN: acc[t*4+ct][v]  -> row t0 + 4 (4 lk + v) + t
+        const int64_t row = TN ? t0 + 4 * (4 * lk + v) + g : t0 + 16 * g + 4 * lk + v;
         const int64_t col = 16 * ct + li;
         if (row < M && col < N) {
-          float r = acc[rt * 4 + ct][v];
-          if (!part) {
-            r *= alpha;
-            if (beta != 0.0f) r += beta * dst[row * ld + col];
-          }
-          dst[row * ld + col] = r;
-        }
-      }
-}
-
-// ---------------------------------------------------------------- TN
-template <bool VEC>
-__global__ __launch_bounds__(256) void gemm_tn_kernel(const float *__restrict__ A, int64_t lda,
-                                                      const float *__restrict__ Y, int64_t ldy,
-                                                      float *__restrict__ C, int64_t ldc,
-                                                      int64_t M, int64_t N, int64_t K,
-                                                      int64_t k_per_split, float alpha, float beta,
-                                                      float *__restrict__ part) {
-  __shared__ float red[3 * 16 * 4 * 64];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t c0 = (int64_t)blockIdx.x * 64;
-  const int64_t kb = (int64_t)blockIdx.y * k_per_split;
-  int64_t ke = kb + k_per_split;
-  if (ke > K) ke = K;
-  const int li = lane & 15, lk = lane >> 4;
-  const int64_t col_a = c0 + 4 * li;   // first of the 4 A columns this lane loads
-
-  floatx4 acc[16];   // acc[t*4+ct]
-#pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  for (int64_t k0 = kb + 16 * wave; k0 < ke; k0 += 64) {
-    float4 a[4];
-    float y[4][4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t k = k0 + 4 * q + lk;
-      a[q] = (k < ke) ? load4_guard<VEC>(A + k * lda + col_a, col_a, M) : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        const int64_t col = 16 * ct + li;
-        y[q][ct] = (k < ke && col < N) ? Y[k * ldy + col] : 0.0f;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[t * 4 + ct] = mfma4(comp(a[q], t), y[q][ct], acc[t * 4 + ct]);
-  }
-  wave_reduce(acc, red, wave, lane);
-  if (wave != 0) return;
-  // acc[t*4+ct] element v: MFMA row i = 4 lk + v <-> output row c0 + 4 i + t, col 16 ct + li
-  float *dst = part ? part + (int64_t)blockIdx.y * M * kBld : C;
-  const int64_t ld = part ? kBld : ldc;
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = c0 + 4 * (4 * lk + v) + t;
-        const int64_t col = 16 * ct + li;
-        if (row < M && col < N) {
-          float r = acc[t * 4 + ct][v];
+          float r = acc[g * 4 + ct][v];
           if (!part) {
             r *= alpha;
             if (beta != 0.0f) r += beta * dst[row * ld + col];
@@ -231,52 +358,128 @@ void launch_reduce_partials(const float *part, int nsplit, int64_t M, int64_t N,
                      part, nsplit, M, N, C, ldc, alpha, beta, D, ldd, gamma, z, zc);
 }
 
-int gemm_choose_ksplit(int64_t M, int64_t K, int /*is_tn*/) {
-  const int64_t tiles = (M + 63) / 64;
-  int64_t s = (1024 + tiles - 1) / tiles;       // about 1024 workgroups (4 waves each)
-  const int64_t maxs = K / 256;                 // keep >= 256 K per split
-  if (s > maxs) s = maxs;
-  if (s > 8) s = 8;
-  if (s < 1) s = 1;
-  return (int)s;
+void launch_gemm_finish(const float *part, int nsp, int64_t M, int64_t N, float *C, int64_t ldc,
+                        float alpha, float beta, hipStream_t st) {
+  if (nsp > 1) launch_reduce_partials(part, nsp, M, N, C, ldc, alpha, beta, nullptr, 0, 0.f,
+                                      nullptr, 0.f, st);
+}
+
+// Waves along the output dimension: 4 once there are enough 256-row tiles.
+static int gemm_wm(int64_t M) { return M >= 8192 ? 4 : 1; }
+
+// Workgroups of the aligned kernel for (TN, WM) that are resident on the
+// current device at once (compute units x occupancy); queried once per device.
+static int64_t gemm_slots(int is_tn, int wm) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int>, int64_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_tuple(dev, is_tn, wm);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  const void *fn = is_tn ? (wm == 4 ? reinterpret_cast<const void *>(&gemm_kernel<true, 4, true, true>)
+                                    : reinterpret_cast<const void *>(&gemm_kernel<true, 1, true, true>))
+                         : (wm == 4 ? reinterpret_cast<const void *>(&gemm_kernel<false, 4, true, true>)
+                                    : reinterpret_cast<const void *>(&gemm_kernel<false, 1, true, true>));
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1)
+    per_cu = 2;
+  const int64_t slots = (int64_t)cus * per_cu;
+  cache[key] = slots;
+  return slots;
+}
+
+// Number of K splits: all workgroups should run in as few rounds of resident
+// workgroups as possible, each split long enough (>= 256 K rows), and the
+// partial tiles (written and read once more) cheap next to A.  Time is
+// modelled as rounds x (K / s) x (1 + 128 s / K).
+int gemm_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split) {
+  if (M < 1 || K < 1) return 1;
+  const int wm = gemm_wm(M);
+  const int64_t tiles = (M + 64 * wm - 1) / (64 * wm);
+  const int64_t slots = gemm_slots(is_tn, wm);
+  int64_t smax = K / 256;
+  if (smax > max_split) smax = max_split;
+  if (smax > 64) smax = 64;
+  int best = 1;
+  double best_cost = 0.0;
+  for (int64_t sp = 1; sp <= (smax < 1 ? 1 : smax); ++sp) {
+    const int64_t rounds = (tiles * sp + slots - 1) / slots;
+    const double cost = (double)rounds / (double)sp * (1.0 + 128.0 * (double)sp / (double)K);
+    if (sp == 1 || cost < best_cost * (1.0 - 1e-9)) {
+      best = (int)sp;
+      best_cost = cost;
+    }
+  }
+  return best;
 }
 
 static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+template <bool TN>
+static int launch_main(const float *A, int64_t lda, const float *X, int64_t ldx, float *C,
+                       int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
+                       int ksplit, float *part, hipStream_t st) {
+  if (M <= 0 || N <= 0) return 1;
+  if (ksplit < 1) ksplit = 1;
+  const int wm = gemm_wm(M);
+  const int64_t kc = (wm == 4) ? 32 : 64;        // K rows per chunk (KC)
+  int64_t kps = (K + ksplit - 1) / ksplit;
+  kps = (kps + 63) / 64 * 64;                    // whole chunks per split
+  if (kps < kc) kps = kc;
+  const int nsp = K > 0 ? (int)((K + kps - 1) / kps) : 1;
+  float *p = (nsp > 1) ? part : nullptr;
+  const int64_t tiles = (M + 64 * wm - 1) / (64 * wm);
+  const int64_t total = tiles * nsp;
+  const bool avec = (lda % 4 == 0) && aligned16(A) && (!TN || (M % 4 == 0 && M >= 4));
+  const bool xvec = (ldx % 4 == 0) && aligned16(X) && N == 64;
+  dim3 grid((unsigned)total), blk(256);
+#define FARPCA_GEMM_LAUNCH(WMV, AV, XV)                                                            \
+  hipLaunchKernelGGL((gemm_kernel<TN, WMV, AV, XV>), grid, blk, 0, st, A, lda, X, ldx, C, ldc, M, \
+                     N, K, kps, tiles, total, alpha, beta, p)
+#define FARPCA_GEMM_LAUNCH_WM(WMV)                  \
+  do {                                              \
+    if (avec && xvec) FARPCA_GEMM_LAUNCH(WMV, true, true);          \
+    else if (avec) FARPCA_GEMM_LAUNCH(WMV, true, false);            \
+    else if (xvec) FARPCA_GEMM_LAUNCH(WMV, false, true);            \
+    else FARPCA_GEMM_LAUNCH(WMV, false, false);                     \
+  } while (0)
+  if (wm == 4) FARPCA_GEMM_LAUNCH_WM(4);
+  else FARPCA_GEMM_LAUNCH_WM(1);
+#undef FARPCA_GEMM_LAUNCH_WM
+#undef FARPCA_GEMM_LAUNCH
+  return nsp;
+}
+
+int launch_gemm_nn_main(const float *A, int64_t lda, const float *X, int64_t ldx, float *C,
+                        int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
+                        int ksplit, float *part, hipStream_t st) {
+  return launch_main<false>(A, lda, X, ldx, C, ldc, M, N, K, alpha, beta, ksplit, part, st);
+}
+
+int launch_gemm_tn_main(const float *A, int64_t lda, const float *Y, int64_t ldy, float *C,
+                        int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
+                        int ksplit, float *part, hipStream_t st) {
+  return launch_main<true>(A, lda, Y, ldy, C, ldc, M, N, K, alpha, beta, ksplit, part, st);
+}
+
 void launch_gemm_nn(const float *A, int64_t lda, const float *X, int64_t ldx, float *C,
                     int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
                     int ksplit, float *part, hipStream_t st) {
-  if (ksplit < 1) ksplit = 1;
-  int64_t kps = (K + ksplit - 1) / ksplit;
-  kps = (kps + 63) / 64 * 64;
-  const int nsp = (int)((K + kps - 1) / kps);
-  float *p = (nsp > 1) ? part : nullptr;
-  dim3 grid((unsigned)((M + 63) / 64), (unsigned)nsp);
-  const bool vec = (lda % 4 == 0) && aligned16(A);
-  if (vec) hipLaunchKernelGGL((gemm_nn_kernel<true>), grid, dim3(256), 0, st, A, lda, X, ldx, C, ldc,
-                              M, N, K, kps, alpha, beta, p);
-  else hipLaunchKernelGGL((gemm_nn_kernel<false>), grid, dim3(256), 0, st, A, lda, X, ldx, C, ldc,
-                          M, N, K, kps, alpha, beta, p);
-  if (nsp > 1) launch_reduce_partials(part, nsp, M, N, C, ldc, alpha, beta, nullptr, 0, 0.f,
-                                      nullptr, 0.f, st);
+  const int nsp = launch_gemm_nn_main(A, lda, X, ldx, C, ldc, M, N, K, alpha, beta, ksplit,
+                                      part, st);
+  launch_gemm_finish(part, nsp, M, N, C, ldc, alpha, beta, st);
 }
 
 void launch_gemm_tn(const float *A, int64_t lda, const float *Y, int64_t ldy, float *C,
                     int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
                     int ksplit, float *part, hipStream_t st) {
-  if (ksplit < 1) ksplit = 1;
-  int64_t kps = (K + ksplit - 1) / ksplit;
-  kps = (kps + 63) / 64 * 64;
-  const int nsp = (int)((K + kps - 1) / kps);
-  float *p = (nsp > 1) ? part : nullptr;
-  dim3 grid((unsigned)((M + 63) / 64), (unsigned)nsp);
-  const bool vec = (lda % 4 == 0) && aligned16(A);
-  if (vec) hipLaunchKernelGGL((gemm_tn_kernel<true>), grid, dim3(256), 0, st, A, lda, Y, ldy, C, ldc,
-                              M, N, K, kps, alpha, beta, p);
-  else hipLaunchKernelGGL((gemm_tn_kernel<false>), grid, dim3(256), 0, st, A, lda, Y, ldy, C, ldc,
-                          M, N, K, kps, alpha, beta, p);
-  if (nsp > 1) launch_reduce_partials(part, nsp, M, N, C, ldc, alpha, beta, nullptr, 0, 0.f,
-                                      nullptr, 0.f, st);
+  const int nsp = launch_gemm_tn_main(A, lda, Y, ldy, C, ldc, M, N, K, alpha, beta, ksplit,
+                                      part, st);
+  launch_gemm_finish(part, nsp, M, N, C, ldc, alpha, beta, st);
 }
 
 }  // namespace farpca_int

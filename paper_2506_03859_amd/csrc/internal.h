@@ -25,13 +25,17 @@ struct OmegaSpec {
 };
 
 // One entry of a chunk's column list: byte offset of the Omega row inside the
-// staged A tile, and the unscaled value (+-1, 1 or a Gaussian draw).
+// staged A tile, and the unscaled value (+-1, 1 or a Gaussian draw).  Every
+// column's list is padded with zero-valued entries to a multiple of
+// kListPad, so the sketch consumes whole groups; kEntCap entries per chunk.
 struct ChunkEntry { uint32_t lds_off; float val; };
+constexpr int kListPad = 4;
+constexpr int kEntCap = kChunk * kMaxBlock + kListPad * kMaxBlock;
 
 // ---- omega.hip
 // Generates Omega_j for rows [0, n): mask/sign words (n each), the dense copy
 // (n x kBld, columns >= b zero) and, if `entries` is non-null, the per-chunk
-// column lists: colptr[(chunk)*(kMaxBlock+1) + c], entries[chunk*kChunk*kMaxBlock + e].
+// column lists: colptr[(chunk)*(kMaxBlock+1) + c], entries[chunk*kEntCap + e].
 void launch_omega(const OmegaSpec &s, int64_t n, int64_t block_j,
                   uint64_t *mask_out, uint64_t *sign_out, float *dense_out,
                   uint32_t *colptr, ChunkEntry *entries, int lds_row_stride_bytes,
@@ -66,7 +70,19 @@ void launch_reduce_partials(const float *part, int nsplit, int64_t M, int64_t N,
                             float *C, int64_t ldc, float alpha, float beta,
                             const float *D, int64_t ldd, float gamma,
                             const float *z, float zc, hipStream_t st);
-int gemm_choose_ksplit(int64_t M, int64_t K, int is_tn);
+// K splits for an M-row product over K; the partial buffer holds at least
+// max_split x M x kBld floats.
+int gemm_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split);
+// The same products split in two launches: the main kernel (returns the number
+// of K splits it wrote) and the fixed-order reduction of the partials.
+int launch_gemm_nn_main(const float *A, int64_t lda, const float *X, int64_t ldx, float *C,
+                        int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
+                        int ksplit, float *part, hipStream_t st);
+int launch_gemm_tn_main(const float *A, int64_t lda, const float *Y, int64_t ldy, float *C,
+                        int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
+                        int ksplit, float *part, hipStream_t st);
+void launch_gemm_finish(const float *part, int nsp, int64_t M, int64_t N, float *C, int64_t ldc,
+                        float alpha, float beta, hipStream_t st);
 
 // ---- dense64.hip (FP64 small-matrix work)
 // Gram G[b x b] (FP64) = X^T X for X (K x b, FP32, ldx); partials in `part`
@@ -74,14 +90,12 @@ int gemm_choose_ksplit(int64_t M, int64_t K, int is_tn);
 int gram_num_partials(int64_t K);
 void launch_gram(const float *X, int64_t ldx, int64_t K, int b, double *part, double *G,
                  hipStream_t st);
-// Cholesky of G and inverse of the factor: Rinv (b x b, upper, FP64).  Columns
-// whose pivot is <= drop_rel * diagonal are dropped (zero column of Rinv);
-// flags[0] |= 1 then.
-void launch_chol_inv(const double *G, int b, double drop_rel, double *Rinv, int *flags,
-                     hipStream_t st);
-// Y[K x b] = X[K x b] * M[b x b] with FP64 accumulation (in place allowed).
-void launch_apply_small(const float *X, int64_t ldx, int64_t K, int b, const double *M,
-                        float *Y, int64_t ldy, hipStream_t st);
+// Cholesky factor of G in the form F (strict upper R, diagonal 1/R_jj); columns
+// whose pivot is <= drop_rel * diagonal are dropped (F_jj = 0); flags[0] |= 1 then.
+void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags, hipStream_t st);
+// Y = X R^{-1} row by row (forward substitution with F; in place allowed).
+void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *F, float *Y,
+                      int64_t ldy, hipStream_t st);
 // Setup pass over A: partial sums of squares (FP64, per row block) and the
 // row sums (FP64, rowsum[i]); nonfinite flag.
 int setup_num_partials(int64_t m);

@@ -100,6 +100,7 @@ __global__ __launch_bounds__(64) void omega_kernel(OmegaSpec s, int64_t n, int64
   uint32_t cnt = 0;
   if (c < b) {
     for (int k = 0; k < kChunk; ++k) cnt += (uint32_t)((rmask[k] >> c) & 1ull);
+    cnt = (cnt + kListPad - 1) / kListPad * kListPad;     // padded to whole groups
   }
   if (t == 0) cstart[0] = 0;
   __syncthreads();
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(64) void omega_kernel(OmegaSpec s, int64_t n, int64
   cp[c] = cstart[c];
   if (t == 0) cp[kMaxBlock] = cstart[kMaxBlock];
   if (c < b) {
-    ChunkEntry *ent = entries + chunk * (int64_t)(kChunk * kMaxBlock);
+    ChunkEntry *ent = entries + chunk * (int64_t)kEntCap;
     uint32_t pos = cstart[c];
     for (int k = 0; k < kChunk; ++k) {
       if ((rmask[k] >> c) & 1ull) {
@@ -127,6 +128,8 @@ __global__ __launch_bounds__(64) void omega_kernel(OmegaSpec s, int64_t n, int64
         ent[pos++] = e;
       }
     }
+    const ChunkEntry pad = {0u, 0.0f};      // adds 0 * A[i, first column]: exact no-op
+    while (pos < cstart[c + 1]) ent[pos++] = pad;
   }
 }
 

@@ -25,7 +25,8 @@ STATUS_NOT_CONVERGED = 1
 
 EXPORTED = ["farpca_plan", "farpca_run", "farpca_free", "farpca_status_str", "farpca_omega",
             "farpca_sketch", "farpca_gemm_scratch_bytes", "farpca_gemm_nn", "farpca_gemm_tn",
-            "farpca_eig_scratch_bytes", "farpca_eig"]
+            "farpca_eig_scratch_bytes", "farpca_eig", "farpca_profile_enable", "farpca_profile_get"]
+PROF_CLASSES = {"sketch": 0, "gemm_tn": 1, "gemm_nn": 2, "eig": 3}
 
 
 class FarpcaParams(ctypes.Structure):
@@ -84,6 +85,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.farpca_eig_scratch_bytes.restype = sz
     lib.farpca_eig.argtypes = [vp, i64, vp, vp, vp, vp]
     lib.farpca_eig.restype = ctypes.c_int
+    lib.farpca_profile_enable.argtypes = [ctypes.c_int]
+    lib.farpca_profile_enable.restype = None
+    lib.farpca_profile_get.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]
+    lib.farpca_profile_get.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -188,6 +194,19 @@ def farpca_eig(K, W, V, work, stream=None) -> int:
     lib = load_library()
     return _check(lib.farpca_eig(_ptr(K), K.shape[0], _ptr(W), _ptr(V), _ptr(work), _stream(stream)),
                   "farpca_eig")
+
+
+def farpca_profile_enable(on: bool) -> None:
+    load_library().farpca_profile_enable(1 if on else 0)
+
+
+def farpca_profile_get(cls: str):
+    """(total_ms, launches) of a kernel class since profiling was enabled."""
+    t = ctypes.c_double()
+    c = ctypes.c_int64()
+    _check(load_library().farpca_profile_get(PROF_CLASSES[cls], ctypes.byref(t), ctypes.byref(c)),
+           "farpca_profile_get")
+    return t.value, c.value
 
 
 @dataclass

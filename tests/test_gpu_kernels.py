@@ -96,6 +96,8 @@ SKETCH_CASES = [
     ("std_bernoulli", 0.5, 0, 64, 2000, 777),
     ("bernoulli", 0.125, 0, 33, 1500, 1000),
     ("sparse_sign", 0.0, 1, 8, 100, 12),
+    # about 3600 list entries per chunk: four LDS pieces of 1024
+    ("bernoulli", 0.875, 0, 64, 600, 300),
 ]
 
 
@@ -154,8 +156,11 @@ def test_sketch_real_A(fp, sketch, p, zeta, b):
         plan.free()
 
 
+# small-M layout (one output tile per workgroup, K interleaved over its waves)
+# and large-M layout (M >= 8192: 4 tiles per workgroup), aligned and ragged
 GEMM_SHAPES = [(1000, 777, 50), (130, 3000, 64), (64, 64, 1), (5000, 20000, 64), (1, 300, 7),
-               (257, 1500, 33), (3000, 64, 64)]
+               (257, 1500, 33), (3000, 64, 64), (9001, 3001, 64), (20000, 1000, 64),
+               (8192, 4000, 50), (12000, 2048, 64), (8200, 40, 64)]
 
 
 @pytest.mark.parametrize("M,K,N", GEMM_SHAPES)
@@ -172,12 +177,14 @@ def test_gemm_integer_exact(fp, M, K, N, kind):
     C = torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")
     part = torch.empty(fp.farpca_gemm_scratch_bytes(M) // 4 + 1, dtype=torch.float32, device="cuda")
     print(f"gemm {kind} M={M} K={K} N={N}", flush=True)
+    # |entries| <= amax^2 K < 2^24: every partial sum is exact in FP32, and
+    # the FP64 reference is exact in any order
     if kind == "nn":
         fp.farpca_gemm_nn(dev(a), dev(x), C, M, N, K, part)
-        ref = a.astype(np.int64) @ x.astype(np.int64)
+        ref = a.astype(np.float64) @ x.astype(np.float64)
     else:
         fp.farpca_gemm_tn(dev(a), dev(x), C, M, N, K, part)
-        ref = a.astype(np.int64).T @ x.astype(np.int64)
+        ref = a.astype(np.float64).T @ x.astype(np.float64)
     assert np.array_equal(host(C), ref.astype(np.float32))
 
 
