@@ -16,15 +16,22 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ------------------------------------------------------------------ Gram
-// part[blk][i][j] = sum over rows k of block blk of X[k][i] X[k][j] (FP64).
-constexpr int kGramRows = 32;
+// part[blk][i][j] = sum over the rows of block blk of X[k][i] X[k][j] (FP64;
+// columns >= b read as zero), then G = sum of the partials in block order.
+// Up to kGramParts workgroups, each over a contiguous row range in chunks of
+// 64 rows staged in LDS; thread t owns the 4 x 4 sub-block
+// (4 (t / 16) .., 4 (t % 16) ..).
+constexpr int kGramParts = 256;
+constexpr int kGramChunk = 64;
+
+int gram_max_partials() { return kGramParts; }
 
 __global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ X, int64_t ldx,
                                                    int64_t K, int b, int64_t rows_per_blk,
-                                                   double *__restrict__ part) {
-  __shared__ float xs[kGramRows][kMaxBlock + 1];
+                                                   bool vec, double *__restrict__ part) {
+  __shared__ float xs[kGramChunk][kMaxBlock + 1];
   const int t = threadIdx.x;
-  const int ti = (t >> 4) * 4, tj = (t & 15) * 4;   // 4x4 output sub-block
+  const int ti = (t >> 4) * 4, tj = (t & 15) * 4;
   double acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -33,15 +40,26 @@ __global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ X, 
   const int64_t k_begin = (int64_t)blockIdx.x * rows_per_blk;
   int64_t k_end = k_begin + rows_per_blk;
   if (k_end > K) k_end = K;
-  for (int64_t k0 = k_begin; k0 < k_end; k0 += kGramRows) {
+  for (int64_t k0 = k_begin; k0 < k_end; k0 += kGramChunk) {
+    const int nr = (int)((k_end - k0 < kGramChunk) ? k_end - k0 : kGramChunk);
     __syncthreads();
-    for (int e = t; e < kGramRows * kMaxBlock; e += 256) {
-      const int r = e / kMaxBlock, c = e % kMaxBlock;
-      const int64_t k = k0 + r;
-      xs[r][c] = (k < k_end && c < b) ? X[k * ldx + c] : 0.0f;
+#pragma unroll
+    for (int q = 0; q < kGramChunk * kMaxBlock / 4 / 256; ++q) {
+      const int f = t + 256 * q;
+      const int r = f >> 4, c4 = (f & 15) * 4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (r < nr) {
+        const float *p = X + (k0 + r) * ldx + c4;
+        if (vec) v = *reinterpret_cast<const float4 *>(p);
+        else v = make_float4(p[0], p[1], p[2], p[3]);
+      }
+      xs[r][c4 + 0] = (c4 + 0 < b) ? v.x : 0.0f;
+      xs[r][c4 + 1] = (c4 + 1 < b) ? v.y : 0.0f;
+      xs[r][c4 + 2] = (c4 + 2 < b) ? v.z : 0.0f;
+      xs[r][c4 + 3] = (c4 + 3 < b) ? v.w : 0.0f;
     }
     __syncthreads();
-    for (int r = 0; r < kGramRows; ++r) {
+    for (int r = 0; r < nr; ++r) {
       double xi[4], xj[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) { xi[a] = (double)xs[r][ti + a]; xj[a] = (double)xs[r][tj + a]; }
@@ -68,115 +86,143 @@ __global__ void gram_reduce_kernel(const double *__restrict__ part, int nblk, in
   G[e] = (i < b && j < b) ? s : 0.0;
 }
 
+static int64_t gram_rows_per_blk(int64_t K) {
+  int64_t rows = (K + kGramParts - 1) / kGramParts;
+  if (rows < 16) rows = 16;
+  return rows;
+}
+
 int gram_num_partials(int64_t K) {
-  int64_t rows = (K + 63) / 64;
-  rows = ((rows + kGramRows - 1) / kGramRows) * kGramRows;
-  if (rows < kGramRows) rows = kGramRows;
+  const int64_t rows = gram_rows_per_blk(K);
   return (int)((K + rows - 1) / rows);
 }
 
 void launch_gram(const float *X, int64_t ldx, int64_t K, int b, double *part, double *G,
                  hipStream_t st) {
-  int64_t rows = (K + 63) / 64;   // at most 64 partials
-  rows = ((rows + kGramRows - 1) / kGramRows) * kGramRows;
-  if (rows < kGramRows) rows = kGramRows;
-  const int nblk = (int)((K + rows - 1) / rows);
-  hipLaunchKernelGGL(gram_kernel, dim3(nblk), dim3(256), 0, st, X, ldx, K, b, rows, part);
+  const int64_t rows = gram_rows_per_blk(K);
+  const int nblk = K > 0 ? (int)((K + rows - 1) / rows) : 0;
+  const bool vec = (ldx % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  if (nblk > 0)
+    hipLaunchKernelGGL(gram_kernel, dim3(nblk), dim3(256), 0, st, X, ldx, K, b, rows, vec, part);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(kMaxBlock * kMaxBlock / 256), dim3(256), 0, st, part,
                      nblk, b, G);
 }
 
-// --------------------------------------------------------- Cholesky factor
-// G (kMaxBlock x kMaxBlock, FP64, valid b x b) = R^T R.  The output F holds
-// R strictly above the diagonal and 1 / R_jj on the diagonal, so that the
-// rows of X R^{-1} (orthonormal columns spanning X) follow by forward
-// substitution (trsm_rows).  A column whose pivot after elimination falls to
-// drop_rel * (its own diagonal) or below is numerically dependent on the
-// previous ones (for FP32 data the residual is rounding noise): it is dropped
-// - F's diagonal entry is 0, so that output column is exactly zero - and it is
-// not used to eliminate later columns.  flags[0] |= 1 when a column is
-// dropped.  (The method's Z^{-1} is read as the pseudo-inverse there.)
-__global__ __launch_bounds__(256) void chol_kernel(const double *__restrict__ G, int b,
-                                                   double drop_rel, double *__restrict__ F,
-                                                   int *__restrict__ flags) {
-  __shared__ double a[kMaxBlock][kMaxBlock + 1];
-  __shared__ double dg[kMaxBlock];
-  __shared__ int dropped[kMaxBlock];
-  const int t = threadIdx.x;
-  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256) a[e / kMaxBlock][e % kMaxBlock] = G[e];
-  __syncthreads();
-  if (t < kMaxBlock) { dg[t] = a[t][t]; dropped[t] = 0; }
-  __syncthreads();
-  const int j = t & 63, i_off = t >> 6;
-  for (int k = 0; k < b; ++k) {
-    if (t == 0) {
-      const double piv = a[k][k];
-      if (!(piv > drop_rel * dg[k]) || !(piv > 0.0)) {   // also catches NaN
-        dropped[k] = 1;
-        a[k][k] = 1.0;
-        atomicOr(flags, 1);
+// ------------------------------------------- Cholesky factor and its inverse
+// G (kMaxBlock x kMaxBlock, FP64, valid b x b) = R^T R; the output is the
+// upper triangular W with X W = X R^{-1}: the orthonormal columns spanning X.
+// A column whose pivot after elimination falls to drop_rel * (its own
+// diagonal) or below is numerically dependent on the previous ones (for FP32
+// data the residual is rounding noise): it is dropped - its row of R is zero,
+// so it eliminates nothing later, and its column of W is zero, so that output
+// column is exactly zero.  flags[0] |= 1 when a column is dropped.  (The
+// method's Z^{-1} is read as the pseudo-inverse there.)
+//
+// One wave.  Factorisation: lane j holds column j of the working matrix in
+// registers; step k broadcasts the pivot and row k of R through LDS and
+// updates the trailing columns.  Inverse: with F = R off the diagonal and
+// F_jj = 1 / R_jj (0 for a dropped column), row r of W follows from
+// W[r][j] = F_jj (delta_rj - sum_{i<j} W[r][i] R[i][j]), lane r per row.
+__device__ __forceinline__ double bcast_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__global__ __launch_bounds__(64) void chol_inv_kernel(const double *__restrict__ G, int b,
+                                                      double drop_rel, double *__restrict__ W,
+                                                      int *__restrict__ flags) {
+  __shared__ double rk[kMaxBlock];
+  __shared__ double Rs[kMaxBlock * (kMaxBlock + 1)];
+  const int j = threadIdx.x;
+  double c[kMaxBlock];
+#pragma unroll
+  for (int i = 0; i < kMaxBlock; ++i) c[i] = G[i * kMaxBlock + j];
+  const double dg = G[j * kMaxBlock + j];
+  bool any_drop = false;
+#pragma unroll
+  for (int k = 0; k < kMaxBlock; ++k) {
+    if (k < b) {
+      const double piv = bcast_f64(c[k], k);
+      const double dgk = bcast_f64(dg, k);
+      double r = 0.0;                               // R[k][j] for j > k
+      if (piv > drop_rel * dgk && piv > 0.0) {     // false for NaN too
+        const double inv = 1.0 / sqrt(piv);
+        r = (j > k) ? c[k] * inv : 0.0;
+        c[k] = (j == k) ? inv : ((j > k) ? r : c[k]);
       } else {
-        a[k][k] = sqrt(piv);
+        any_drop = true;
+        c[k] = (j >= k) ? 0.0 : c[k];
       }
+      rk[j] = r;
+      __syncthreads();
+#pragma unroll
+      for (int i = k + 1; i < kMaxBlock; ++i) c[i] = fma(-rk[i], r, c[i]);
+      __syncthreads();
     }
-    __syncthreads();
-    if (t > k && t < b) a[k][t] = dropped[k] ? 0.0 : a[k][t] / a[k][k];
-    __syncthreads();
-    if (!dropped[k] && j > k && j < b) {
-      const double rkj = a[k][j];
-      for (int i = k + 1 + i_off; i <= j; i += 4) a[i][j] -= a[k][i] * rkj;
-    }
-    __syncthreads();
   }
-  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256) {
-    const int r = e / kMaxBlock, c = e % kMaxBlock;
-    double v = 0.0;
-    if (r < b && c < b) {
-      if (r < c) v = a[r][c];
-      else if (r == c) v = dropped[r] ? 0.0 : 1.0 / a[r][r];
-    }
-    F[e] = v;
-  }
-}
-
-void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags, hipStream_t st) {
-  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, st, G, b, drop_rel, F, flags);
-}
-
-// Rows of Y = X R^{-1}: q_j = (x_j - sum_{i<j} q_i R_ij) / R_jj, one row per
-// thread, FP64 sums (F from chol_kernel; in place allowed).
-__global__ __launch_bounds__(256) void trsm_rows_kernel(const float *__restrict__ X, int64_t ldx,
-                                                        int64_t K, int b, const double *__restrict__ F,
-                                                        float *__restrict__ Y, int64_t ldy) {
-  __shared__ double Fs[kMaxBlock * kMaxBlock];
-  const int t = threadIdx.x;
-  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256) Fs[e] = F[e];
+  if (any_drop && j == 0) atomicOr(flags, 1);
+  // F into LDS: rows i <= j of column j (c[i] for i < j is R[i][j], c[j] is F_jj)
+#pragma unroll
+  for (int i = 0; i < kMaxBlock; ++i) Rs[i * (kMaxBlock + 1) + j] = (i <= j && j < b) ? c[i] : 0.0;
   __syncthreads();
-  const int64_t row = (int64_t)blockIdx.x * 256 + t;
-  if (row >= K) return;
-  const float *x = X + row * ldx;
-  double q[kMaxBlock];
+  const int r = j;
+  double w[kMaxBlock];
 #pragma unroll
-  for (int c = 0; c < kMaxBlock; ++c) {
-    if (c < b) {
-      double s = (double)x[c];
+  for (int jj = 0; jj < kMaxBlock; ++jj) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int i = 0; i < c; ++i) s = fma(-q[i], Fs[i * kMaxBlock + c], s);
-      q[c] = s * Fs[c * kMaxBlock + c];
-    } else {
-      q[c] = 0.0;
-    }
+    for (int i = 0; i < jj; ++i) s[i & 3] = fma(Rs[i * (kMaxBlock + 1) + jj], w[i], s[i & 3]);
+    const double d = ((r == jj) ? 1.0 : 0.0) - ((s[0] + s[1]) + (s[2] + s[3]));
+    w[jj] = Rs[jj * (kMaxBlock + 1) + jj] * d;
   }
-  float *y = Y + row * ldy;
+  __syncthreads();
 #pragma unroll
-  for (int c = 0; c < kMaxBlock; ++c)
-    if (c < b) y[c] = (float)q[c];
+  for (int jj = 0; jj < kMaxBlock; ++jj) Rs[r * (kMaxBlock + 1) + jj] = w[jj];
+  __syncthreads();
+  for (int e = j; e < kMaxBlock * kMaxBlock; e += 64)
+    W[e] = Rs[(e / kMaxBlock) * (kMaxBlock + 1) + (e % kMaxBlock)];
 }
 
-void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *F, float *Y,
+void launch_chol(const double *G, int b, double drop_rel, double *W, int *flags, hipStream_t st) {
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(64), 0, st, G, b, drop_rel, W, flags);
+}
+
+// Y = X W for upper triangular W (kMaxBlock x kMaxBlock, FP64): FP64 sums of
+// the FP32 data, rounded once.  A workgroup owns 64 rows (lane = row); wave h
+// computes the output columns c = h (mod 4) (balanced over the triangle).
+// All four waves read their rows before any writes, so Y may alias X.
+__global__ __launch_bounds__(256) void trsm_rows_kernel(const float *__restrict__ X, int64_t ldx,
+                                                        int64_t K, int b, const double *__restrict__ Wg,
+                                                        float *__restrict__ Y, int64_t ldy) {
+  __shared__ double Ws[kMaxBlock * kMaxBlock];
+  const int t = threadIdx.x;
+  const int lane = t & 63, h = t >> 6;
+  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256) Ws[e] = Wg[e];
+  const int64_t row = (int64_t)blockIdx.x * 64 + lane;
+  const bool valid = row < K;
+  double x[kMaxBlock];
+  const float *xr = X + (valid ? row : 0) * ldx;
+#pragma unroll
+  for (int i = 0; i < kMaxBlock; ++i) x[i] = (valid && i < b) ? (double)xr[i] : 0.0;
+  __syncthreads();   // every wave has read its rows (in-place use) and Ws is staged
+  float *yr = Y + (valid ? row : 0) * ldy;
+#pragma unroll
+  for (int c0 = 0; c0 < kMaxBlock; c0 += 4) {
+    const int c = c0 + h;                 // wave-uniform
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i <= c0 + 3; ++i)
+      if (i <= c) s[i & 3] = fma(x[i], Ws[i * kMaxBlock + c], s[i & 3]);
+    if (valid && c < b) yr[c] = (float)((s[0] + s[1]) + (s[2] + s[3]));
+  }
+}
+
+void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *W, float *Y,
                       int64_t ldy, hipStream_t st) {
-  hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, X, ldx, K,
-                     b, F, Y, ldy);
+  if (K <= 0) return;
+  hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((K + 63) / 64)), dim3(256), 0, st, X, ldx, K,
+                     b, W, Y, ldy);
 }
 
 // ------------------------------------------------------------ setup pass
@@ -370,6 +416,8 @@ void launch_alpha_update(const double *w, int b, double *alpha, hipStream_t st) 
 }  // namespace farpca_int
 
 namespace farpca_int {
+
+constexpr int kGramRows = 32;   // rows staged per step of the big Gram
 
 // ------------------------------------------------ final Gram K = X^T X (l x l)
 // X is n x l FP32 (ldx).  Upper 64 x 64 tiles only; grid z splits the rows of

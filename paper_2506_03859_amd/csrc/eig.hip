@@ -4,13 +4,14 @@
 // (smallest singular value for the shift).
 //
 // Method: two-sided cyclic Jacobi.  Small matrices (<= 64) are solved by one
-// workgroup entirely in LDS.  Larger ones are first rotated by the
-// eigenvectors of their 64 x 64 diagonal blocks (the method builds K = C C^T
-// block by block, and blocks of later power iterations couple weakly, so this
-// leaves little off-diagonal mass), then finished by block Jacobi: the index set is
-// cut into blocks of 16, blocks are paired by a round-robin tournament, every
-// pair's 32 x 32 principal submatrix is diagonalised in LDS (one workgroup per
-// pair), and the whole matrix is then rotated block-by-block,
+// workgroup entirely in LDS.  Larger ones are first rotated by (approximate,
+// three Jacobi sweeps) eigenvectors of their 64 x 64 diagonal blocks (the
+// method builds K = C C^T block by block, and blocks of later power iterations
+// couple weakly, so this leaves little off-diagonal mass), then finished by
+// block Jacobi: the index set is cut into blocks of 16, blocks are paired by a
+// round-robin tournament, every pair's 32 x 32 principal submatrix gets one
+// Jacobi sweep in LDS (one workgroup per pair), and the whole matrix is then
+// rotated block-by-block,
 // M[S_p, S_q] <- R_p^T M[S_p, S_q] R_q, V[:, S_q] <- V[:, S_q] R_q - every
 // output block depends only on the same input block, so the update runs in
 // place with one workgroup per block.  Sweeps repeat until every off-diagonal
@@ -27,7 +28,13 @@ namespace farpca_int {
 // of size max |a_ii|); with a floor at that level the sweeps never end.
 constexpr double kJacobiRel = 1e-14;
 constexpr double kJacobiAbs = 1e-13;
-constexpr int kInnerMaxSweeps = 30;
+constexpr int kInnerMaxSweeps = 30;   // a small matrix solved on its own
+// Inside the block method a diagonal-block pre-rotation and a pair subproblem
+// need not be converged: each is one step of the outer iteration, whose own
+// test decides convergence.  (One inner sweep per pair costs about one more
+// outer sweep than solving every pair exactly, at a small fraction of the work.)
+constexpr int kPreSweeps = 3;
+constexpr int kPairSweeps = 1;
 
 __device__ __forceinline__ bool negligible(double apq, double app, double aqq, double floor_abs) {
   const double x = fabs(apq);
@@ -42,13 +49,13 @@ __device__ __forceinline__ int rr_player(int pos, int step, int n) {
 // Cyclic Jacobi on an S x S symmetric matrix a (LDS, stride LD) accumulating
 // rotations into v (LDS, stride LD, holds the starting orthogonal matrix).
 template <int S, int LD, int NT>
-__device__ void jacobi_lds(double *a, double *v, double floor_abs) {
+__device__ void jacobi_lds(double *a, double *v, double floor_abs, int max_sweeps) {
   constexpr int H = S / 2;
   __shared__ double cs_c[H], cs_s[H], cs_t[H];
   __shared__ int cs_p[H], cs_q[H], cs_on[H];
   __shared__ int any_rot;
   const int tid = threadIdx.x;
-  for (int sweep = 0; sweep < kInnerMaxSweeps; ++sweep) {
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (tid == 0) any_rot = 0;
     __syncthreads();
     for (int step = 0; step < S - 1; ++step) {
@@ -132,7 +139,7 @@ __global__ __launch_bounds__(256) void eig_small_kernel(const double *__restrict
     fl = mx * kJacobiAbs;
   }
   __syncthreads();
-  jacobi_lds<64, kSmallLd, 256>(a, v, fl);
+  jacobi_lds<64, kSmallLd, 256>(a, v, fl, kInnerMaxSweeps);
   __syncthreads();
   // descending order among the first s positions (ties by index)
   if (tid < s) {
@@ -188,7 +195,7 @@ __global__ __launch_bounds__(256) void bj_pair_kernel(const double *__restrict__
     if (u < x && !negligible(a[u * kSubLd + x], a[u * kSubLd + u], a[x * kSubLd + x], fl)) any_big = 1;
   }
   __syncthreads();
-  if (any_big) jacobi_lds<kSub, kSubLd, 256>(a, v, fl);   // else R = I
+  if (any_big) jacobi_lds<kSub, kSubLd, 256>(a, v, fl, kPairSweeps);   // else R = I
   __syncthreads();
   double *Rp = R + (int64_t)pair * kSub * kSub;
   for (int e = tid; e < kSub * kSub; e += 256) Rp[e] = v[(e / kSub) * kSubLd + (e % kSub)];
@@ -317,7 +324,7 @@ __global__ __launch_bounds__(256) void bj_pre_eig_kernel(const double *__restric
     fl = mx * kJacobiAbs;
   }
   __syncthreads();
-  jacobi_lds<kPre, kSmallLd, 256>(a, v, fl);
+  jacobi_lds<kPre, kSmallLd, 256>(a, v, fl, kPreSweeps);
   __syncthreads();
   for (int e = tid; e < kPre * kPre; e += 256) {
     const int i = e / kPre, j = e % kPre;

@@ -180,7 +180,7 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   pl->off_r = c.take((size_t)ldq * kBld * 4);
   pl->part_floats = 16 * mnl * kBld;
   pl->off_part = c.take((size_t)pl->part_floats * 4);
-  pl->off_gpart = c.take((size_t)64 * kMaxBlock * kMaxBlock * 8);    // <= 64 partials for any K
+  pl->off_gpart = c.take((size_t)gram_max_partials() * kMaxBlock * kMaxBlock * 8);
   pl->off_g64 = c.take((size_t)kMaxBlock * kMaxBlock * 8);
   pl->off_rinv = c.take((size_t)kMaxBlock * kMaxBlock * 8);
   pl->off_w64 = c.take((size_t)kMaxBlock * 8);

@@ -28,9 +28,14 @@ struct OmegaSpec {
 // staged A tile, and the unscaled value (+-1, 1 or a Gaussian draw).  Every
 // column's list is padded with zero-valued entries to a multiple of
 // kListPad, so the sketch consumes whole groups; kEntCap entries per chunk.
+// The last kListPad slots of every chunk's region (kZeroEnt ..) hold zero
+// entries, a group the sketch may read in place of a real one; the lists
+// themselves use at most kChunk * kMaxBlock + (kListPad - 1) * kMaxBlock slots.
 struct ChunkEntry { uint32_t lds_off; float val; };
 constexpr int kListPad = 4;
 constexpr int kEntCap = kChunk * kMaxBlock + kListPad * kMaxBlock;
+constexpr int kZeroEnt = kEntCap - kListPad;
+static_assert(kChunk * kMaxBlock + (kListPad - 1) * kMaxBlock <= kZeroEnt, "zero group overlaps lists");
 
 // ---- omega.hip
 // Generates Omega_j for rows [0, n): mask/sign words (n each), the dense copy
@@ -85,16 +90,19 @@ void launch_gemm_finish(const float *part, int nsp, int64_t M, int64_t N, float 
                         float alpha, float beta, hipStream_t st);
 
 // ---- dense64.hip (FP64 small-matrix work)
-// Gram G[b x b] (FP64) = X^T X for X (K x b, FP32, ldx); partials in `part`
-// (nblk x b x b doubles), nblk = gram_num_partials(K).
+// Gram G[b x b] (FP64) = X^T X for X (K x b, FP32, ldx; columns >= b ignored);
+// partials in `part` (nblk x 64 x 64 doubles), nblk = gram_num_partials(K) <=
+// gram_max_partials().
 int gram_num_partials(int64_t K);
+int gram_max_partials();
 void launch_gram(const float *X, int64_t ldx, int64_t K, int b, double *part, double *G,
                  hipStream_t st);
-// Cholesky factor of G in the form F (strict upper R, diagonal 1/R_jj); columns
-// whose pivot is <= drop_rel * diagonal are dropped (F_jj = 0); flags[0] |= 1 then.
-void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags, hipStream_t st);
-// Y = X R^{-1} row by row (forward substitution with F; in place allowed).
-void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *F, float *Y,
+// Cholesky factor G = R^T R and W = R^{-1} (upper triangular, 64 x 64 FP64);
+// columns whose pivot is <= drop_rel * diagonal are dropped (zero row of R,
+// zero column of W); flags[0] |= 1 then.
+void launch_chol(const double *G, int b, double drop_rel, double *W, int *flags, hipStream_t st);
+// Y = X W row by row (FP64 sums; in place allowed).
+void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *W, float *Y,
                       int64_t ldy, hipStream_t st);
 // Setup pass over A: partial sums of squares (FP64, per row block) and the
 // row sums (FP64, rowsum[i]); nonfinite flag.
