@@ -113,6 +113,36 @@ def cpu_baseline(a_dev, wl, blocks_gpu):
             "ms_per_solve": per_solve * 1e3}
 
 
+def kernel_probe(wl, dev, reps=3):
+    """The kernels that stream A, each launched `reps` times on a random matrix
+    of the workload's shape, then a 1 GiB device-to-device copy (a plain read +
+    write of known size for scaling FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    from paper_2506_03859_amd import farpca as fp
+    m, n, _, _, tol, b, P, sketch, zeta, p = WORKLOADS[wl]
+    A = torch.randn(m, n, device=dev)
+    skinny_n = torch.randn(n, 64, device=dev)
+    skinny_m = torch.randn(m, 64, device=dev)
+    Cm = torch.zeros(m, 64, device=dev)
+    Cn = torch.zeros(n, 64, device=dev)
+    part = torch.empty(fp.farpca_gemm_scratch_bytes(max(m, n)) // 4, device=dev)
+    plan = fp.farpca_plan(fp.make_params(m, n, tol=tol, rank=(200 if tol == 0.0 else 0), block=b,
+                                         power=P, sketch=sketch, p=p, zeta=zeta, seed=1000))
+    work, _, _, _, _ = fp.alloc_outputs(plan, dev)
+    for r in range(reps):
+        fp.farpca_gemm_tn(A, skinny_m, Cn, n, b, m, part)
+        fp.farpca_gemm_nn(A, skinny_n, Cm, m, b, n, part)
+        fp.farpca_sketch(plan, A, r, work, Cm)
+    torch.cuda.synchronize()
+    plan.free()
+    del A
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)      # an elementwise kernel: reads 1 GiB, writes 1 GiB
+    torch.cuda.synchronize()
+    log(f"kernel probe done ({reps} launches each, then a {src.numel() * 4 >> 20} MiB copy)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +152,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--kernel-probe", action="store_true",
+                    help="only launch the kernels that stream A (A-pass products, sparse sketch) "
+                         "on a random matrix of the workload's shape, plus a 1 GiB copy: the "
+                         "input of the hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
@@ -134,6 +168,9 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     wl = args.workload
+    if args.kernel_probe:
+        kernel_probe(wl, dev)
+        return
     m, n, _, _, tol, b, P, sketch, zeta, p = WORKLOADS[wl]
     rank = 200 if tol == 0.0 else 0
     log(f"generating {wl}")
@@ -147,7 +184,7 @@ def main():
     if args.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     for r in range(args.warmup):

@@ -76,14 +76,26 @@ __global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ X, 
     for (int c = 0; c < 4; ++c) o[(ti + a) * kMaxBlock + tj + c] = acc[a][c];
 }
 
-__global__ void gram_reduce_kernel(const double *__restrict__ part, int nblk, int b,
-                                   double *__restrict__ G) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= kMaxBlock * kMaxBlock) return;
-  const int i = e / kMaxBlock, j = e % kMaxBlock;
+// G[e] = sum_q part[q][e] in a fixed order: workgroup g owns 16 entries; its
+// 16 thread groups sum the partials q = grp, grp + 16, ... and the group sums
+// are added in group order.
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double *__restrict__ part, int nblk,
+                                                          int b, double *__restrict__ G) {
+  __shared__ double red[16][16];
+  const int t = threadIdx.x;
+  const int grp = t >> 4, o = t & 15;
+  const int e = blockIdx.x * 16 + o;
   double s = 0.0;
-  for (int q = 0; q < nblk; ++q) s += part[(int64_t)q * kMaxBlock * kMaxBlock + e];
-  G[e] = (i < b && j < b) ? s : 0.0;
+  for (int q = grp; q < nblk; q += 16) s += part[(int64_t)q * kMaxBlock * kMaxBlock + e];
+  red[grp][o] = s;
+  __syncthreads();
+  if (grp == 0) {
+    double tot = 0.0;
+#pragma unroll
+    for (int g = 0; g < 16; ++g) tot += red[g][o];
+    const int i = e / kMaxBlock, j = e % kMaxBlock;
+    G[e] = (i < b && j < b) ? tot : 0.0;
+  }
 }
 
 static int64_t gram_rows_per_blk(int64_t K) {
@@ -104,7 +116,7 @@ void launch_gram(const float *X, int64_t ldx, int64_t K, int b, double *part, do
   const bool vec = (ldx % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
   if (nblk > 0)
     hipLaunchKernelGGL(gram_kernel, dim3(nblk), dim3(256), 0, st, X, ldx, K, b, rows, vec, part);
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(kMaxBlock * kMaxBlock / 256), dim3(256), 0, st, part,
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(kMaxBlock * kMaxBlock / 16), dim3(256), 0, st, part,
                      nblk, b, G);
 }
 
@@ -189,31 +201,28 @@ void launch_chol(const double *G, int b, double drop_rel, double *W, int *flags,
 }
 
 // Y = X W for upper triangular W (kMaxBlock x kMaxBlock, FP64): FP64 sums of
-// the FP32 data, rounded once.  A workgroup owns 64 rows (lane = row); wave h
-// computes the output columns c = h (mod 4) (balanced over the triangle).
-// All four waves read their rows before any writes, so Y may alias X.
+// the FP32 data, rounded once.  One row per thread (256 rows per workgroup);
+// W is staged transposed in LDS so that W[0..c][c] is contiguous.  Each thread
+// reads its whole row before writing it, so Y may alias X.
 __global__ __launch_bounds__(256) void trsm_rows_kernel(const float *__restrict__ X, int64_t ldx,
                                                         int64_t K, int b, const double *__restrict__ Wg,
                                                         float *__restrict__ Y, int64_t ldy) {
-  __shared__ double Ws[kMaxBlock * kMaxBlock];
+  __shared__ double Wt[kMaxBlock * kMaxBlock];     // Wt[c][i] = W[i][c]
   const int t = threadIdx.x;
-  const int lane = t & 63, h = t >> 6;
-  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256) Ws[e] = Wg[e];
-  const int64_t row = (int64_t)blockIdx.x * 64 + lane;
+  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256) Wt[(e % kMaxBlock) * kMaxBlock + e / kMaxBlock] = Wg[e];
+  const int64_t row = (int64_t)blockIdx.x * 256 + t;
   const bool valid = row < K;
   double x[kMaxBlock];
   const float *xr = X + (valid ? row : 0) * ldx;
 #pragma unroll
   for (int i = 0; i < kMaxBlock; ++i) x[i] = (valid && i < b) ? (double)xr[i] : 0.0;
-  __syncthreads();   // every wave has read its rows (in-place use) and Ws is staged
+  __syncthreads();
   float *yr = Y + (valid ? row : 0) * ldy;
 #pragma unroll
-  for (int c0 = 0; c0 < kMaxBlock; c0 += 4) {
-    const int c = c0 + h;                 // wave-uniform
+  for (int c = 0; c < kMaxBlock; ++c) {
     double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i <= c0 + 3; ++i)
-      if (i <= c) s[i & 3] = fma(x[i], Ws[i * kMaxBlock + c], s[i & 3]);
+    for (int i = 0; i <= c; ++i) s[i & 3] = fma(x[i], Wt[c * kMaxBlock + i], s[i & 3]);
     if (valid && c < b) yr[c] = (float)((s[0] + s[1]) + (s[2] + s[3]));
   }
 }
@@ -221,7 +230,7 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(const float *__restrict_
 void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *W, float *Y,
                       int64_t ldy, hipStream_t st) {
   if (K <= 0) return;
-  hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((K + 63) / 64)), dim3(256), 0, st, X, ldx, K,
+  hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, X, ldx, K,
                      b, W, Y, ldy);
 }
 
