@@ -96,8 +96,12 @@ SKETCH_CASES = [
     ("std_bernoulli", 0.5, 0, 64, 2000, 777),
     ("bernoulli", 0.125, 0, 33, 1500, 1000),
     ("sparse_sign", 0.0, 1, 8, 100, 12),
-    # about 3600 list entries per chunk: four LDS pieces of 1024
+    # about 3600 list entries per chunk: several LDS pieces
     ("bernoulli", 0.875, 0, 64, 600, 300),
+    # second row block of a workgroup mostly past m; three chunks (prefetch clamps)
+    ("sparse_sign", 0.0, 4, 64, 130, 192),
+    # many row tiles and K splits
+    ("sparse_sign", 0.0, 16, 64, 12000, 4096),
 ]
 
 
