@@ -5,7 +5,7 @@
 //
 // Method: two-sided cyclic Jacobi.  Small matrices (<= 64) are solved by one
 // workgroup entirely in LDS.  Larger ones are first rotated by (approximate,
-// three Jacobi sweeps) eigenvectors of their 64 x 64 diagonal blocks (the
+// two Jacobi sweeps) eigenvectors of their 64 x 64 diagonal blocks (the
 // method builds K = C C^T block by block, and blocks of later power iterations
 // couple weakly, so this leaves little off-diagonal mass), then finished by
 // block Jacobi: the index set is cut into blocks of 16, blocks are paired by a
@@ -33,7 +33,7 @@ constexpr int kInnerMaxSweeps = 30;   // a small matrix solved on its own
 // need not be converged: each is one step of the outer iteration, whose own
 // test decides convergence.  (One inner sweep per pair costs about one more
 // outer sweep than solving every pair exactly, at a small fraction of the work.)
-constexpr int kPreSweeps = 3;
+constexpr int kPreSweeps = 2;
 constexpr int kPairSweeps = 1;
 
 __device__ __forceinline__ bool negligible(double apq, double app, double aqq, double floor_abs) {
@@ -173,15 +173,16 @@ __device__ __forceinline__ int sub_index(int u, int bi, int bj) {
   return u < kBlk ? bi * kBlk + u : bj * kBlk + (u - kBlk);
 }
 
-// One workgroup per pair: diagonalise M[S, S], S = block(bi) U block(bj).
-__global__ __launch_bounds__(256) void bj_pair_kernel(const double *__restrict__ M, int64_t lp, int nb,
+// One workgroup per pair: one Jacobi sweep of M[S, S], S = block(bi) U block(bj).
+constexpr int kPairThreads = 256;
+__global__ __launch_bounds__(kPairThreads) void bj_pair_kernel(const double *__restrict__ M, int64_t lp, int nb,
                                                      int step, double *__restrict__ R,
                                                      const double *__restrict__ floor_abs) {
   __shared__ double a[kSub * kSubLd];
   __shared__ double v[kSub * kSubLd];
   const int pair = blockIdx.x, tid = threadIdx.x;
   const int bi = rr_player(pair, step, nb), bj = rr_player(nb - 1 - pair, step, nb);
-  for (int e = tid; e < kSub * kSub; e += 256) {
+  for (int e = tid; e < kSub * kSub; e += kPairThreads) {
     const int u = e / kSub, x = e % kSub;
     a[u * kSubLd + x] = M[(int64_t)sub_index(u, bi, bj) * lp + sub_index(x, bi, bj)];
     v[u * kSubLd + x] = (u == x) ? 1.0 : 0.0;
@@ -190,15 +191,15 @@ __global__ __launch_bounds__(256) void bj_pair_kernel(const double *__restrict__
   if (tid == 0) any_big = 0;
   __syncthreads();
   const double fl = floor_abs[0];
-  for (int e = tid; e < kSub * kSub; e += 256) {
+  for (int e = tid; e < kSub * kSub; e += kPairThreads) {
     const int u = e / kSub, x = e % kSub;
     if (u < x && !negligible(a[u * kSubLd + x], a[u * kSubLd + u], a[x * kSubLd + x], fl)) any_big = 1;
   }
   __syncthreads();
-  if (any_big) jacobi_lds<kSub, kSubLd, 256>(a, v, fl, kPairSweeps);   // else R = I
+  if (any_big) jacobi_lds<kSub, kSubLd, kPairThreads>(a, v, fl, kPairSweeps);   // else R = I
   __syncthreads();
   double *Rp = R + (int64_t)pair * kSub * kSub;
-  for (int e = tid; e < kSub * kSub; e += 256) Rp[e] = v[(e / kSub) * kSubLd + (e % kSub)];
+  for (int e = tid; e < kSub * kSub; e += kPairThreads) Rp[e] = v[(e / kSub) * kSubLd + (e % kSub)];
 }
 
 // Rotate M (pair blocks) and V (row tiles x pair columns) in place.
@@ -439,7 +440,7 @@ int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, hip
     hipStreamSynchronize(st);
     if (h_count == 0) break;
     for (int step = 0; step < nb - 1; ++step) {
-      hipLaunchKernelGGL(bj_pair_kernel, dim3(npairs), dim3(256), 0, st, M, lp, nb, step, R, floor_abs);
+      hipLaunchKernelGGL(bj_pair_kernel, dim3(npairs), dim3(kPairThreads), 0, st, M, lp, nb, step, R, floor_abs);
       const int64_t nwg = (int64_t)npairs * npairs + (lp / kSub) * npairs;
       hipLaunchKernelGGL(bj_update_kernel, dim3((unsigned)nwg), dim3(256), 0, st, M, V, lp, nb, step, R);
     }
