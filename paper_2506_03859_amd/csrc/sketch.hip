@@ -1,21 +1,22 @@
 // Sparse sketch S = A * Omega_j for the sparse test matrices (Section 3: the
 // cost of A B_j is nnz(B_j) m instead of a dense product).
 //
-// A is streamed in chunks of 64 columns.  A workgroup has four waves: two row
-// blocks of 64 rows (lane = row) times two halves of the 64 output columns.
-// Per chunk and row block
-//   1. the two waves of the block each hold half of the block's 64 x 64 tile
-//      of A in registers (16-byte loads, 4 rows x 256 contiguous bytes per
-//      instruction) and store it transposed into the block's LDS tile
-//      (stride 65 floats: conflict-free stores and loads).  Tiles are fetched
-//      two chunks ahead, so that every wave keeps two half tiles (16 KB) in
+// A is streamed in chunks of 64 columns.  A workgroup has four waves over one
+// block of 128 rows; lane l of every wave owns rows 2 l and 2 l + 1 of the
+// block, wave w owns output columns 16 w .. 16 w + 15.  Per chunk
+//   1. each wave holds a quarter of the block's 128 x 64 tile of A in
+//      registers (16-byte loads, 4 rows x 256 contiguous bytes per
+//      instruction) and stores it transposed into the LDS tile (column-major,
+//      130 floats per column: rows 2 l, 2 l + 1 form one aligned 8-byte pair).
+//      Tiles are fetched two chunks ahead, so that every wave keeps 16 KB in
 //      flight while it works: HBM needs a few hundred KB in flight per CU;
-//   2. each wave walks the chunk's column lists of Omega for its 32 output
+//   2. each wave walks the chunk's column lists of Omega for its 16 output
 //      columns (lists staged in LDS once for the workgroup, padded per column
 //      to groups of four; every lane reads the same entry: an LDS broadcast),
-//      two columns per step (8 independent tile reads in flight), accumulating
-//      acc[c] += val * tile[r][lane]: each A element is read from HBM once and
-//      from LDS once per nonzero of its Omega row.
+//      two columns per step, accumulating acc[r][c] += val * tile[j][2 l + r]
+//      with one 8-byte tile read per entry for two rows: each A element is
+//      read from HBM once and from LDS once per nonzero of its Omega row, and
+//      each list entry is read once per 128 rows.
 // A column whose list is exhausted inside a step reads a group of zero
 // entries (0 * finite = +0, an exact no-op).  Each column's sum runs in list
 // order, so results are bitwise repeatable; the +-1 values of the sign
@@ -29,10 +30,10 @@
 
 namespace farpca_int {
 
-constexpr int kTileStride = kChunk + 1;   // floats per LDS row of the staged tile
-constexpr int kBlocksPerWg = 2;           // row blocks of 64 rows per workgroup
-constexpr int kHalf = kMaxBlock / 2;      // output columns per wave
-constexpr int kThreads = 64 * 2 * kBlocksPerWg;
+constexpr int kRowsWg = 128;              // rows of A per workgroup (2 per lane)
+constexpr int kTileStride = kRowsWg + 2;  // floats per LDS column of the staged tile
+constexpr int kHalf = kMaxBlock / 4;      // output columns per wave
+constexpr int kThreads = 256;
 constexpr int kPiece = 768;               // column-list entries staged in LDS at a time
 constexpr int kPieceLoads = kPiece / kThreads;   // entries per thread per piece
 constexpr int kPair = 2;                  // output columns walked together
@@ -40,9 +41,9 @@ static_assert(kPiece % kThreads == 0, "piece must split evenly over the threads"
 static_assert(kPiece % kListPad == 0, "pieces hold whole groups");
 
 int sketch_lds_row_stride_bytes() { return kTileStride * 4; }
-int sketch_rows_per_wg() { return 64 * kBlocksPerWg; }
+int sketch_rows_per_wg() { return kRowsWg; }
 
-// Half tile (rows 32 h .. 32 h + 31 of the block) into registers: instruction
+// A quarter tile (rows r0 .. r0 + 31) into registers: instruction
 // q covers rows r0 + 4 q + lane/16, columns col0 + 4 (lane%16) .. +3.  Rows
 // beyond m are clamped to m - 1 (they feed outputs that are never stored) and
 // columns beyond n read as zero.  VEC (lda % 4 == 0, A 16-byte aligned,
@@ -80,13 +81,13 @@ __device__ __forceinline__ void load_half(const float *__restrict__ A, int64_t l
   }
 }
 
-// Store a half tile transposed: tile[col][row] with row = 32 h + 4 q + lane/16.
-__device__ __forceinline__ void store_half(float *tile, int h, int lane, const float4 (&reg)[8]) {
+// Store a quarter tile transposed: tile[col][row] with row = 32 w + 4 q + lane/16.
+__device__ __forceinline__ void store_half(float *tile, int w, int lane, const float4 (&reg)[8]) {
   const int rsub = lane >> 4;
   const int c4 = (lane & 15) * 4;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const int row = 32 * h + 4 * q + rsub;
+    const int row = 32 * w + 4 * q + rsub;
     tile[(c4 + 0) * kTileStride + row] = reg[q].x;
     tile[(c4 + 1) * kTileStride + row] = reg[q].y;
     tile[(c4 + 2) * kTileStride + row] = reg[q].z;
@@ -103,10 +104,10 @@ __device__ __forceinline__ int64_t sketch_xcd_remap(int64_t g, int64_t T) {
 }
 
 // Entries [p0, p1) of one chunk staged in E (relative index), E[kPiece ..
-// kPiece + 3] zero.  Adds the lists of output columns c_base .. c_base + 31
-// into acc, kPair columns per step.  cp0 / cp1 (lane c): start / end of
+// kPiece + 3] zero.  Adds the lists of output columns c_base .. c_base + 15
+// into acc (the lane's two rows), kPair columns per step.  cp0 / cp1 (lane c): start / end of
 // column c.
-__device__ __forceinline__ void sketch_piece(float (&acc)[kHalf], const uint2 *E,
+__device__ __forceinline__ void sketch_piece(float (&acc)[2][kHalf], const uint2 *E,
                                              const char *tile_bytes, uint32_t cp0, uint32_t cp1,
                                              int c_base, uint32_t p0, uint32_t p1, int b) {
 #pragma unroll
@@ -126,9 +127,9 @@ __device__ __forceinline__ void sketch_piece(float (&acc)[kHalf], const uint2 *E
         kmax = len[i] > kmax ? len[i] : kmax;
       }
       if (kmax == 0) continue;
-      float a[kPair];
+      float a0[kPair], a1[kPair];
 #pragma unroll
-      for (int i = 0; i < kPair; ++i) a[i] = acc[cq + i];
+      for (int i = 0; i < kPair; ++i) { a0[i] = acc[0][cq + i]; a1[i] = acc[1][cq + i]; }
       // entries of step k (past a column's end: the zero group)
       auto read_entries = [&](uint32_t k, uint2 (&q)[kPair][kListPad]) {
 #pragma unroll
@@ -139,16 +140,20 @@ __device__ __forceinline__ void sketch_piece(float (&acc)[kHalf], const uint2 *E
         }
       };
       auto accumulate = [&](const uint2 (&q)[kPair][kListPad]) {
-        float x[kPair][kListPad];
+        float2 x[kPair][kListPad];
 #pragma unroll
         for (int i = 0; i < kPair; ++i)
 #pragma unroll
           for (int u = 0; u < kListPad; ++u)
-            x[i][u] = *reinterpret_cast<const float *>(tile_bytes + q[i][u].x);
+            x[i][u] = *reinterpret_cast<const float2 *>(tile_bytes + q[i][u].x);
 #pragma unroll
         for (int i = 0; i < kPair; ++i)
 #pragma unroll
-          for (int u = 0; u < kListPad; ++u) a[i] = fmaf(__uint_as_float(q[i][u].y), x[i][u], a[i]);
+          for (int u = 0; u < kListPad; ++u) {
+            const float v = __uint_as_float(q[i][u].y);
+            a0[i] = fmaf(v, x[i][u].x, a0[i]);
+            a1[i] = fmaf(v, x[i][u].y, a1[i]);
+          }
       };
       for (uint32_t k = 0; k < kmax; k += kListPad) {
         uint2 qa[kPair][kListPad];
@@ -156,7 +161,7 @@ __device__ __forceinline__ void sketch_piece(float (&acc)[kHalf], const uint2 *E
         accumulate(qa);
       }
 #pragma unroll
-      for (int i = 0; i < kPair; ++i) acc[cq + i] = a[i];
+      for (int i = 0; i < kPair; ++i) { acc[0][cq + i] = a0[i]; acc[1][cq + i] = a1[i]; }
     }
   }
 }
@@ -167,32 +172,30 @@ __global__ __launch_bounds__(kThreads) void sketch_kernel(
     const uint32_t *__restrict__ colptr, const ChunkEntry *__restrict__ entries,
     float *__restrict__ out, int64_t chunks_per_split, int64_t tiles, int64_t total_wg,
     float scale, const float *__restrict__ z, float zc) {
-  __shared__ float tiles_lds[kBlocksPerWg][kChunk * kTileStride];
+  __shared__ float tile_lds[kChunk * kTileStride];
   __shared__ uint2 ents[2][kPiece + kListPad];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int rb = wave >> 1, h = wave & 1;
   const int64_t L = sketch_xcd_remap(blockIdx.x, total_wg);
   const int64_t tile = L % tiles, split = L / tiles;
-  const int64_t i0 = (tile * kBlocksPerWg + rb) * 64;
+  const int64_t i0 = tile * kRowsWg;
   const int64_t nchunks = (n + kChunk - 1) / kChunk;
   const int64_t ch_begin = split * chunks_per_split;
   int64_t ch_end = ch_begin + chunks_per_split;
   if (ch_end > nchunks) ch_end = nchunks;
-  float *tile_lds = tiles_lds[rb];
-  const char *tile_bytes = reinterpret_cast<const char *>(tile_lds) + lane * 4;
-  const int c_base = kHalf * h;
+  const char *tile_bytes = reinterpret_cast<const char *>(tile_lds) + lane * 8;
+  const int c_base = kHalf * wave;
 
   if (tid < 2 * kListPad) ents[tid / kListPad][kPiece + tid % kListPad] = make_uint2(0u, 0u);
 
-  float acc[kHalf];
+  float acc[2][kHalf];
 #pragma unroll
-  for (int c = 0; c < kHalf; ++c) acc[c] = 0.0f;
+  for (int c = 0; c < kHalf; ++c) { acc[0][c] = 0.0f; acc[1][c] = 0.0f; }
 
-  // half tiles of chunks ch + 1 (one set) and ch + 2 (the other) in flight
+  // quarter tiles of chunks ch + 1 (one set) and ch + 2 (the other) in flight
   float4 s0[8], s1[8];
   auto fetch_tile = [&](int64_t ch, float4 (&reg)[8]) {
-    load_half<VEC>(A, lda, m, n, i0 + 32 * h, ch * kChunk, lane, reg);
+    load_half<VEC>(A, lda, m, n, i0 + 32 * wave, ch * kChunk, lane, reg);
   };
   // first piece of a chunk's entries and its column bounds (one chunk ahead)
   uint2 ereg[kPieceLoads];
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(kThreads) void sketch_kernel(
     __builtin_amdgcn_sched_barrier(0);
     __syncthreads();                 // every wave is done with this chunk's tile and lists
     if (ch + 1 < ch_end) {
-      store_half(tile_lds, h, lane, nxt);
+      store_half(tile_lds, wave, lane, nxt);
       stage_lists(buf ^ 1);
     }
     __syncthreads();
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(kThreads) void sketch_kernel(
     fetch_lists(ch_begin);
     fetch_tile(ch_begin, s0);
     fetch_tile(ch_begin + 1 < ch_end ? ch_begin + 1 : ch_begin, s1);
-    store_half(tile_lds, h, lane, s0);
+    store_half(tile_lds, wave, lane, s0);
     stage_lists(0);
     __syncthreads();
     uint32_t cp0 = cp0_next, cp1 = cp1_next;
@@ -265,17 +268,20 @@ __global__ __launch_bounds__(kThreads) void sketch_kernel(
     }
   }
 
-  const int64_t row = i0 + lane;
-  if (row >= m) return;
-  if (DIRECT) {
-    float *o = out + row * (int64_t)kBld + c_base;
-    const float zr = z ? zc * z[row] : 0.0f;
 #pragma unroll
-    for (int c = 0; c < kHalf; ++c) o[c] = (c_base + c < b) ? fmaf(scale, acc[c], zr) : 0.0f;
-  } else {
-    float *o = out + (split * m + row) * (int64_t)kBld + c_base;
+  for (int r = 0; r < 2; ++r) {
+    const int64_t row = i0 + 2 * lane + r;
+    if (row >= m) continue;
+    if (DIRECT) {
+      float *o = out + row * (int64_t)kBld + c_base;
+      const float zr = z ? zc * z[row] : 0.0f;
 #pragma unroll
-    for (int c = 0; c < kHalf; ++c) o[c] = (c_base + c < b) ? acc[c] : 0.0f;
+      for (int c = 0; c < kHalf; ++c) o[c] = (c_base + c < b) ? fmaf(scale, acc[r][c], zr) : 0.0f;
+    } else {
+      float *o = out + (split * m + row) * (int64_t)kBld + c_base;
+#pragma unroll
+      for (int c = 0; c < kHalf; ++c) o[c] = (c_base + c < b) ? acc[r][c] : 0.0f;
+    }
   }
 }
 
@@ -291,8 +297,7 @@ void launch_sketch_full(const float *A, int64_t lda, int64_t m, int64_t n, int b
   nsplit = (int)((nchunks + cps - 1) / cps);
   const bool vec = (lda % 4 == 0) && (lda < (int64_t(1) << 28)) &&
                    ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-  const int64_t rows_wg = 64 * kBlocksPerWg;
-  const int64_t tiles = (m + rows_wg - 1) / rows_wg;
+  const int64_t tiles = (m + kRowsWg - 1) / kRowsWg;
   const int64_t total = tiles * nsplit;
   dim3 grid((unsigned)total), blk(kThreads);
 #define FARPCA_SKETCH_LAUNCH(V, D)                                                              \
@@ -334,7 +339,7 @@ static int64_t sketch_slots() {
 // workgroups as possible, each split >= 4 chunks, partial traffic small next
 // to A (time modelled as rounds x (chunks / s) x (1 + 2 s / chunks)).
 int sketch_choose_split(int64_t m, int64_t n) {
-  const int64_t tiles = (m + 64 * kBlocksPerWg - 1) / (64 * kBlocksPerWg);
+  const int64_t tiles = (m + kRowsWg - 1) / kRowsWg;
   const int64_t nchunks = (n + kChunk - 1) / kChunk;
   const int64_t slots = sketch_slots();
   int64_t smax = nchunks / 4;
