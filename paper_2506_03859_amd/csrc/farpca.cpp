@@ -38,6 +38,7 @@ using namespace farpca_int;
 
 // squared relative pivot below which a block direction counts as dependent
 static constexpr double kDropRel = 1e-10;
+static constexpr int kCholqrPasses = 2;
 
 struct farpca_plan_s {
   farpca_params prm;
@@ -324,9 +325,12 @@ void project_out(const farpca_plan_s *pl, const Ws &w, int64_t l, float *T, hipS
 }
 
 // X (K x b) <- orthonormal basis of its range, CholeskyQR with `passes`
-// passes; numerically dependent columns (residual below 1e-5 of the column,
-// i.e. rounding noise of the FP32 data) become exactly zero.  If gram_eig,
-// the eigenvalues of the first Gram go to w64 (descending).
+// passes (FP64 Gram and factor, FP32 storage); numerically dependent columns
+// (residual below 1e-5 of the column, i.e. rounding noise of the FP32 data)
+// become exactly zero.  Two passes suffice: the first leaves an orthogonality
+// error of about u64 cond(X)^2, the second brings it to the FP32 rounding of
+// the stored result, which further passes cannot go below.  If gram_eig, the
+// eigenvalues of the first Gram go to w64 (descending).
 void cholqr(const farpca_plan_s *pl, const Ws &w, float *X, int64_t K, int passes, bool gram_eig,
             hipStream_t st) {
   double *gpart = w.at<double>(pl->off_gpart);
@@ -407,7 +411,7 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
         }
         launch_gemm_finish(part, nsp, n, b, X, kBld, 1.f, 0.f, st);
         if (k >= 2 && pl->P > 2) launch_axpy_block(X, kBld, G, kBld, n, b, alpha, st);
-        cholqr(pl, w, X, n, 3, pl->P > 2, st);
+        cholqr(pl, w, X, n, kCholqrPasses, pl->P > 2, st);
         if (k >= 2 && pl->P > 2) launch_alpha_update(w.at<double>(pl->off_w64), b, alpha, st);
         launch_copy_block(X, kBld, n, b, G, kBld, st);
         if (k < pl->P) {
@@ -432,7 +436,7 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
     }
     // Basis extension: Y_j against Q, orthonormalise, append; C_j^T = A^T Q_j.
     project_out(pl, w, l, Ysrc, st);
-    cholqr(pl, w, Ysrc, m, 3, false, st);
+    cholqr(pl, w, Ysrc, m, kCholqrPasses, false, st);
     launch_copy_block(Ysrc, kBld, m, b, Q + l, pl->ldq, st);
     int nsp4;
     {
