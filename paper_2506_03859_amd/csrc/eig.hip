@@ -174,7 +174,7 @@ __device__ __forceinline__ int sub_index(int u, int bi, int bj) {
 }
 
 // One workgroup per pair: one Jacobi sweep of M[S, S], S = block(bi) U block(bj).
-constexpr int kPairThreads = 256;
+constexpr int kPairThreads = 512;
 __global__ __launch_bounds__(kPairThreads) void bj_pair_kernel(const double *__restrict__ M, int64_t lp, int nb,
                                                      int step, double *__restrict__ R,
                                                      const double *__restrict__ floor_abs) {
