@@ -75,12 +75,17 @@ def default_maxit(m: int, n: int, b: int) -> int:
 
 def eig_svd(x: np.ndarray):
     """Economy SVD of a tall matrix through the eigendecomposition of its Gram
-    matrix (the eigSVD step of Algorithms 1 and 2).  Ascending order."""
+    matrix (the eigSVD step of Algorithms 1 and 2).  Ascending order.
+    Eigenvalues of the Gram at or below lambda_max * b * eps belong to
+    numerically dependent columns (e.g. two equal test-matrix columns): as in
+    the pseudo-inverse reading of Z^{-1}, their singular values are set to 0
+    and their columns of U to zero instead of amplifying rounding noise."""
     c = x.T @ x
     d, v = np.linalg.eigh(c)
     d = np.clip(d, 0.0, None)
-    s = np.sqrt(d)
-    inv = np.where(s > 0, 1.0 / np.where(s > 0, s, 1.0), 0.0)
+    keep = d > (d[-1] if d.size else 0.0) * c.shape[0] * np.finfo(np.float64).eps
+    s = np.where(keep, np.sqrt(d), 0.0)
+    inv = np.where(keep, 1.0 / np.where(keep, s, 1.0), 0.0)
     u = (x @ v) * inv[None, :]
     return u, s, v
 
@@ -205,8 +210,15 @@ def farpca(a: np.ndarray, params: FarpcaParams, keep_bases: bool = False,
 
 def projection_svd(a: np.ndarray, y: np.ndarray) -> np.ndarray:
     """Singular values (descending) of C = Q^T A with Q an orthonormal basis of
-    range(Y): the direct SVD of Section 2.1 written out plainly (Householder QR
-    and LAPACK SVD), without the Gram matrices Z and T.  Used as the
-    definition the final step reaches for a given basis."""
-    q, _ = np.linalg.qr(np.asarray(y, dtype=np.float64))
+    range(Y): the direct SVD of Section 2.1 written out plainly (LAPACK SVDs),
+    without the Gram matrices Z and T.  Used as the definition the final step
+    reaches for a given basis.  Q is the left singular vectors of Y whose
+    squared singular values pass the dependence threshold of the pseudo-inverse
+    reading of Z^{-1} (lambda > lambda_max * l * eps for the eigenvalues
+    lambda = sigma^2 of Z = Y^T Y): numerically dependent columns of Y (e.g.
+    two equal test-matrix columns) span no extra direction."""
+    y = np.asarray(y, dtype=np.float64)
+    u, sv, _ = np.linalg.svd(y, full_matrices=False)
+    keep = sv * sv > sv[0] * sv[0] * y.shape[1] * np.finfo(np.float64).eps
+    q = u[:, keep]
     return np.linalg.svd(q.T @ np.asarray(a, dtype=np.float64), compute_uv=False)

@@ -80,6 +80,21 @@ def test_eig_svd_matches_lapack():
     assert np.linalg.norm(u * s @ v.T - x) < 1e-10 * np.linalg.norm(x)
 
 
+def test_eig_svd_dependent_columns():
+    # two equal columns (an empty test-matrix column twice gives this): one
+    # singular value is exactly 0 with a zero column of U (LAPACK finds it at
+    # rounding level); the others are LAPACK's
+    x = synth.gaussian_matrix(200, 10, seed=2)
+    x[:, 7] = x[:, 3]
+    u, s, v = eig_svd(x)
+    assert s[0] == 0.0 and np.all(u[:, 0] == 0.0)
+    ref = np.linalg.svd(x, compute_uv=False)[::-1]
+    assert ref[0] < 1e-13 * ref[-1]
+    assert np.allclose(s[1:], ref[1:], rtol=1e-9)
+    assert np.abs(u[:, 1:].T @ u[:, 1:] - np.eye(9)).max() < 1e-9
+    assert np.linalg.norm(u * s @ v.T - x) < 1e-10 * np.linalg.norm(x)
+
+
 @pytest.mark.parametrize("sketch,p,zeta", SKETCHES)
 def test_power0_is_textbook_randqb(a_fast, sketch, p, zeta):
     # With P = 0 the basis after j blocks spans A [Omega_0 ... Omega_{j-1}]
