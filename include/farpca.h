@@ -47,10 +47,19 @@ extern "C" {
 #define FARPCA_BERNOULLI 4        /* plain 0/1 Bernoulli (Def. 2.1, farPCAB of Section 5)        */
 
 #define FARPCA_DTYPE_F32 0
+/* Precision form: A stored as BF16 (uint16 bit patterns, the caller's rounding,
+ * normally round-to-nearest-even from FP32).  The A-passes run on the BF16
+ * matrix cores with FP32 accumulation; the FP32 vectors they multiply are
+ * split exactly into three BF16 terms, so every product A_ij x_j is exact and
+ * the results equal those of the FP32 path on the BF16-valued matrix up to
+ * FP32 accumulation order.  Everything else (sketch sums, Grams, Cholesky,
+ * indicator, eigensolver) is unchanged.  The method's accuracy is then bounded
+ * by the storage error ||A - A_bf16||_F / ||A||_F (unit roundoff 2^-8; about 2e-3 for generic data). */
+#define FARPCA_DTYPE_BF16 1
 
 typedef struct farpca_params {
   int64_t m, n, lda;   /* A is m x n, row-major, leading dimension lda >= n                  */
-  int32_t a_dtype;     /* FARPCA_DTYPE_F32                                                   */
+  int32_t a_dtype;     /* FARPCA_DTYPE_F32 or FARPCA_DTYPE_BF16                              */
   int32_t sketch;      /* FARPCA_GAUSSIAN ... FARPCA_BERNOULLI                               */
   double tol;          /* relative Frobenius tolerance eps > 0 (fixed precision, Section 5.2):
                           stop once E < eps^2 ||A||_F^2 (strict); ignored when rank > 0     */
@@ -88,7 +97,7 @@ int farpca_plan(const farpca_params *params, farpca_plan_t **out, int64_t *l_max
                 size_t *workspace_bytes);
 
 /* Run the method (Algorithms 1/2 with the steps of the plan).
- *  dA     device, m x n FP32 (lda), read only
+ *  dA     device, m x n FP32 or BF16 (a_dtype; lda elements), read only
  *  dWork  device workspace, >= workspace_bytes, 256-byte aligned, contents ignored
  *  dU     device, m x l_max FP32 (leading dimension l_max): left singular vectors
  *  dS     device, l_max FP64: singular values, descending
@@ -127,6 +136,16 @@ int farpca_gemm_nn(const float *dA, int64_t lda, const float *dX, int64_t ldx, f
                    int64_t ldc, int64_t M, int64_t N, int64_t K, float *dPart, void *stream);
 int farpca_gemm_tn(const float *dA, int64_t lda, const float *dY, int64_t ldy, float *dC,
                    int64_t ldc, int64_t M, int64_t N, int64_t K, float *dPart, void *stream);
+
+/* The same two products with A in BF16 (bit patterns, as for FARPCA_DTYPE_BF16):
+ * BF16 matrix cores, the FP32 operand X / Y split exactly into three BF16
+ * terms, FP32 accumulation.  dScratch: device, farpca_gemm_bf16_scratch_bytes(M, K)
+ * bytes, 256-byte aligned (split-K partials and the transposed operand). */
+size_t farpca_gemm_bf16_scratch_bytes(int64_t M, int64_t K);
+int farpca_gemm_bf16_nn(const uint16_t *dA, int64_t lda, const float *dX, int64_t ldx, float *dC,
+                        int64_t ldc, int64_t M, int64_t N, int64_t K, void *dScratch, void *stream);
+int farpca_gemm_bf16_tn(const uint16_t *dA, int64_t lda, const float *dY, int64_t ldy, float *dC,
+                        int64_t ldc, int64_t M, int64_t N, int64_t K, void *dScratch, void *stream);
 
 /* FP64 symmetric eigendecomposition (block Jacobi) of K (l x l, row-major):
  * dW (l) descending, dV (l x l) eigenvectors in columns.  dWork holds

@@ -238,8 +238,22 @@ void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const doubl
 // One wave per row at a time; each workgroup (4 waves) owns a fixed row range.
 constexpr int kSetupWgs = 1024;
 
-template <bool VEC>
-__global__ __launch_bounds__(256) void setup_kernel(const float *__restrict__ A, int64_t lda,
+// Element loads: FP32, or BF16 bit patterns widened exactly.
+__device__ __forceinline__ float elem(const float *p, int64_t c) { return p[c]; }
+__device__ __forceinline__ float elem(const uint16_t *p, int64_t c) {
+  return __uint_as_float((uint32_t)p[c] << 16);
+}
+__device__ __forceinline__ float4 elem4(const float *p, int64_t c4) {
+  return reinterpret_cast<const float4 *>(p)[c4];
+}
+__device__ __forceinline__ float4 elem4(const uint16_t *p, int64_t c4) {
+  const uint2 u = reinterpret_cast<const uint2 *>(p)[c4];
+  return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xFFFF0000u),
+                     __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xFFFF0000u));
+}
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void setup_kernel(const T *__restrict__ A, int64_t lda,
                                                     int64_t m, int64_t n, int64_t rows_per_wg,
                                                     double *__restrict__ part_sq,
                                                     double *__restrict__ rowsum,
@@ -252,28 +266,25 @@ __global__ __launch_bounds__(256) void setup_kernel(const float *__restrict__ A,
   double sq = 0.0;
   bool bad = false;
   for (int64_t row = rb + wave; row < re; row += 4) {
-    const float *p = A + row * lda;
+    const T *p = A + row * lda;
     double s = 0.0, q = 0.0;
+    int64_t c0 = 0;
     if (VEC) {
       const int64_t n4 = n / 4;
       for (int64_t c = lane; c < n4; c += 64) {
-        const float4 v = reinterpret_cast<const float4 *>(p)[c];
+        const float4 v = elem4(p, c);
         const double x0 = v.x, x1 = v.y, x2 = v.z, x3 = v.w;
         s += (x0 + x1) + (x2 + x3);
         q = fma(x0, x0, q); q = fma(x1, x1, q); q = fma(x2, x2, q); q = fma(x3, x3, q);
         bad |= !isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w);
       }
-      for (int64_t c = n4 * 4 + lane; c < n; c += 64) {
-        const double x = p[c];
-        s += x; q = fma(x, x, q);
-        bad |= !isfinite(p[c]);
-      }
-    } else {
-      for (int64_t c = lane; c < n; c += 64) {
-        const double x = p[c];
-        s += x; q = fma(x, x, q);
-        bad |= !isfinite(p[c]);
-      }
+      c0 = n4 * 4;
+    }
+    for (int64_t c = c0 + lane; c < n; c += 64) {
+      const float f = elem(p, c);
+      const double x = f;
+      s += x; q = fma(x, x, q);
+      bad |= !isfinite(f);
     }
     s = wave_sum(s);
     q = wave_sum(q);
@@ -291,15 +302,24 @@ int setup_num_partials(int64_t m) {
   return (int)((m + rows - 1) / rows);
 }
 
-void launch_setup(const float *A, int64_t lda, int64_t m, int64_t n, double *part_sq,
-                  double *rowsum, int *flags, hipStream_t st) {
+template <typename T>
+static void launch_setup_t(const T *A, int64_t lda, int64_t m, int64_t n, double *part_sq,
+                           double *rowsum, int *flags, hipStream_t st) {
   const int64_t rows = (m + kSetupWgs - 1) / kSetupWgs;
   const int nwg = (int)((m + rows - 1) / rows);
-  const bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-  if (vec) hipLaunchKernelGGL((setup_kernel<true>), dim3(nwg), dim3(256), 0, st, A, lda, m, n, rows,
-                              part_sq, rowsum, flags);
-  else hipLaunchKernelGGL((setup_kernel<false>), dim3(nwg), dim3(256), 0, st, A, lda, m, n, rows,
-                          part_sq, rowsum, flags);
+  const bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & (4 * sizeof(T) - 1)) == 0);
+  if (vec) hipLaunchKernelGGL((setup_kernel<T, true>), dim3(nwg), dim3(256), 0, st, A, lda, m, n,
+                              rows, part_sq, rowsum, flags);
+  else hipLaunchKernelGGL((setup_kernel<T, false>), dim3(nwg), dim3(256), 0, st, A, lda, m, n,
+                          rows, part_sq, rowsum, flags);
+}
+
+void launch_setup(const void *A, bool bf16, int64_t lda, int64_t m, int64_t n, double *part_sq,
+                  double *rowsum, int *flags, hipStream_t st) {
+  if (bf16)
+    launch_setup_t(static_cast<const uint16_t *>(A), lda, m, n, part_sq, rowsum, flags, st);
+  else
+    launch_setup_t(static_cast<const float *>(A), lda, m, n, part_sq, rowsum, flags, st);
 }
 
 // ------------------------------------------------------ fixed-order sums

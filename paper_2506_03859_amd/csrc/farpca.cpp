@@ -42,6 +42,7 @@ static constexpr int kCholqrPasses = 2;
 
 struct farpca_plan_s {
   farpca_params prm;
+  bool bf16;            // A holds BF16 bit patterns (precision form)
   int b;
   int P;
   int kind;
@@ -58,7 +59,7 @@ struct farpca_plan_s {
   size_t off_q, off_ct, off_s, off_y, off_x, off_g, off_om, off_mask, off_neg, off_colptr,
       off_ent, off_z, off_rowsum, off_r, off_part, off_gpart, off_g64, off_rinv, off_w64,
       off_v64, off_setup, off_sq, off_scal, off_ehist, off_kbig, off_eig, off_wfin, off_vfin,
-      off_u32, off_gbig, total;
+      off_u32, off_gbig, off_xt, total;
   size_t gbig_bytes;
   int64_t part_floats;  // capacity of the K-split partial buffer
   // K splits the partial buffer holds for an M-row product
@@ -113,7 +114,7 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   *out = nullptr;
   const farpca_params &q = *prm;
   if (q.m < 1 || q.n < 1 || q.lda < q.n) return FARPCA_E_INVALID;
-  if (q.a_dtype != FARPCA_DTYPE_F32) return FARPCA_E_INVALID;
+  if (q.a_dtype != FARPCA_DTYPE_F32 && q.a_dtype != FARPCA_DTYPE_BF16) return FARPCA_E_INVALID;
   if (q.sketch < FARPCA_GAUSSIAN || q.sketch > FARPCA_BERNOULLI) return FARPCA_E_INVALID;
   if (q.block < 0 || q.block > kMaxBlock || q.power < 0 || q.power > 64) return FARPCA_E_INVALID;
   if (q.rank < 0 || q.max_blocks < 0) return FARPCA_E_INVALID;
@@ -130,6 +131,7 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   farpca_plan_s *pl = new (std::nothrow) farpca_plan_s();
   if (!pl) return FARPCA_E_INVALID;
   pl->prm = q;
+  pl->bf16 = q.a_dtype == FARPCA_DTYPE_BF16;
   pl->b = b;
   pl->P = q.power;
   pl->kind = q.sketch;
@@ -198,6 +200,7 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   const size_t gbig = gram_big_workspace_bytes(n, lmax);
   pl->off_gbig = c.take(gbig);
   pl->gbig_bytes = gbig;
+  pl->off_xt = pl->bf16 ? c.take(bf16_pack_bytes(imax(m, n))) : 0;
   pl->total = c.cur;
   *out = pl;
   if (l_max) *l_max = lmax;
@@ -274,16 +277,40 @@ void gen_omega(const farpca_plan_s *pl, const Ws &w, int64_t j, hipStream_t st,
                lists ? w.at<ChunkEntry>(pl->off_ent) : nullptr, sketch_lds_row_stride_bytes(), st);
 }
 
+// One A-pass with the plan's storage type of A, split over K:
+//   NN (tn false): C (m x ncols) = A X, X n x ncols (ld kBld)
+//   TN (tn true):  C (n x ncols) = A^T T, T m x ncols (ld kBld)
+// Returns the number of partial products left in the partial buffer (1: C
+// was written directly); launch_gemm_finish completes the product.
+int a_pass(const farpca_plan_s *pl, const Ws &w, bool tn, const void *A, const float *X, int ncols,
+           float *C, int64_t ldc, hipStream_t st) {
+  const farpca_params &q = pl->prm;
+  float *part = w.at<float>(pl->off_part);
+  const int64_t M = tn ? q.n : q.m, K = tn ? q.m : q.n;
+  if (pl->bf16) {
+    const uint16_t *Ab = static_cast<const uint16_t *>(A);
+    float *xt = w.at<float>(pl->off_xt);
+    const int ks = gemm_bf16_choose_ksplit(M, K, tn, pl->part_splits(M));
+    return tn ? launch_gemm_bf16_tn_main(Ab, q.lda, X, kBld, C, ldc, M, ncols, K, 1.f, 0.f, ks,
+                                         part, xt, st)
+              : launch_gemm_bf16_nn_main(Ab, q.lda, X, kBld, C, ldc, M, ncols, K, 1.f, 0.f, ks,
+                                         part, xt, st);
+  }
+  const float *Af = static_cast<const float *>(A);
+  const int ks = gemm_choose_ksplit(M, K, tn, pl->part_splits(M));
+  return tn ? launch_gemm_tn_main(Af, q.lda, X, kBld, C, ldc, M, ncols, K, 1.f, 0.f, ks, part, st)
+            : launch_gemm_nn_main(Af, q.lda, X, kBld, C, ldc, M, ncols, K, 1.f, 0.f, ks, part, st);
+}
+
 // S = A Omega_j (standardized Bernoulli: A B_j - z), m x kBld.
-void sketch(const farpca_plan_s *pl, const Ws &w, const float *A, float *S, hipStream_t st) {
+void sketch(const farpca_plan_s *pl, const Ws &w, const void *A, float *S, hipStream_t st) {
   const farpca_params &q = pl->prm;
   float *part = w.at<float>(pl->off_part);
   if (pl->kind == FARPCA_GAUSSIAN) {
     int nsp;
     {
       ProfScope ps(FARPCA_PROF_GEMM_NN, st);
-      nsp = launch_gemm_nn_main(A, q.lda, w.at<float>(pl->off_om), kBld, S, kBld, q.m, kBld, q.n, 1.f,
-                                0.f, gemm_choose_ksplit(q.m, q.n, 0, pl->part_splits(q.m)), part, st);
+      nsp = a_pass(pl, w, false, A, w.at<float>(pl->off_om), kBld, S, kBld, st);
     }
     launch_gemm_finish(part, nsp, q.m, kBld, S, kBld, 1.f, 0.f, st);
     return;
@@ -293,12 +320,12 @@ void sketch(const farpca_plan_s *pl, const Ws &w, const float *A, float *S, hipS
   const int ns = sketch_choose_split(q.m, q.n);
   if (ns <= 1) {
     ProfScope ps(FARPCA_PROF_SKETCH, st);
-    launch_sketch_full(A, q.lda, q.m, q.n, pl->b, w.at<uint32_t>(pl->off_colptr),
+    launch_sketch_full(A, pl->bf16, q.lda, q.m, q.n, pl->b, w.at<uint32_t>(pl->off_colptr),
                        w.at<ChunkEntry>(pl->off_ent), S, 1, scale, z, -1.f, st);
   } else {
     {
       ProfScope ps(FARPCA_PROF_SKETCH, st);
-      launch_sketch_full(A, q.lda, q.m, q.n, pl->b, w.at<uint32_t>(pl->off_colptr),
+      launch_sketch_full(A, pl->bf16, q.lda, q.m, q.n, pl->b, w.at<uint32_t>(pl->off_colptr),
                          w.at<ChunkEntry>(pl->off_ent), part, ns, scale, z, -1.f, st);
     }
     // number of splits actually launched
@@ -360,7 +387,7 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
   const farpca_params &q = pl->prm;
   const int64_t m = q.m, n = q.n;
   const int b = pl->b;
-  const float *A = static_cast<const float *>(dA);
+  const void *A = dA;
   Ws w{static_cast<char *>(dWork)};
   double *scal = w.at<double>(pl->off_scal);
   double *nA2 = scal + 0, *E = scal + 1, *alpha = scal + 2;
@@ -375,7 +402,8 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
 
   HIP_OK(hipMemsetAsync(scal, 0, 64, st));
   // a0: ||A||_F^2 in FP64, row sums (z for the standardized Bernoulli matrix), finiteness.
-  launch_setup(A, q.lda, m, n, w.at<double>(pl->off_setup), w.at<double>(pl->off_rowsum), flags, st);
+  launch_setup(A, pl->bf16, q.lda, m, n, w.at<double>(pl->off_setup), w.at<double>(pl->off_rowsum),
+               flags, st);
   launch_sum_partials(w.at<double>(pl->off_setup), setup_num_partials(m), nA2, st);
   double h_scal[4];
   HIP_OK(hipMemcpyAsync(h_scal, scal, 32, hipMemcpyDeviceToHost, st));
@@ -406,8 +434,7 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
         int nsp;
         {
           ProfScope ps(FARPCA_PROF_GEMM_TN, st);
-          nsp = launch_gemm_tn_main(A, q.lda, T, kBld, X, kBld, n, b, m, 1.f, 0.f,
-                                    gemm_choose_ksplit(n, m, 1, pl->part_splits(n)), part, st);
+          nsp = a_pass(pl, w, true, A, T, b, X, kBld, st);
         }
         launch_gemm_finish(part, nsp, n, b, X, kBld, 1.f, 0.f, st);
         if (k >= 2 && pl->P > 2) launch_axpy_block(X, kBld, G, kBld, n, b, alpha, st);
@@ -418,8 +445,7 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
           int nsp2;
           {
             ProfScope ps(FARPCA_PROF_GEMM_NN, st);
-            nsp2 = launch_gemm_nn_main(A, q.lda, G, kBld, S, kBld, m, b, n, 1.f, 0.f,
-                                       gemm_choose_ksplit(m, n, 0, pl->part_splits(m)), part, st);
+            nsp2 = a_pass(pl, w, false, A, G, b, S, kBld, st);
           }
           launch_gemm_finish(part, nsp2, m, b, S, kBld, 1.f, 0.f, st);
           T = S;
@@ -428,8 +454,7 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
       int nsp3;
       {
         ProfScope ps(FARPCA_PROF_GEMM_NN, st);
-        nsp3 = launch_gemm_nn_main(A, q.lda, G, kBld, Yb, kBld, m, b, n, 1.f, 0.f,
-                                   gemm_choose_ksplit(m, n, 0, pl->part_splits(m)), part, st);
+        nsp3 = a_pass(pl, w, false, A, G, b, Yb, kBld, st);
       }
       launch_gemm_finish(part, nsp3, m, b, Yb, kBld, 1.f, 0.f, st);
       Ysrc = Yb;
@@ -441,8 +466,7 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
     int nsp4;
     {
       ProfScope ps(FARPCA_PROF_GEMM_TN, st);
-      nsp4 = launch_gemm_tn_main(A, q.lda, Ysrc, kBld, Ct + l, pl->ldq, n, b, m, 1.f, 0.f,
-                                 gemm_choose_ksplit(n, m, 1, pl->part_splits(n)), part, st);
+      nsp4 = a_pass(pl, w, true, A, Ysrc, b, Ct + l, pl->ldq, st);
     }
     launch_gemm_finish(part, nsp4, n, b, Ct + l, pl->ldq, 1.f, 0.f, st);
     launch_sqnorm(Ct + l, pl->ldq, n, b, w.at<double>(pl->off_sq), st);
@@ -527,12 +551,12 @@ extern "C" int farpca_sketch(farpca_plan_t *plan, const void *dA, int64_t block_
   const farpca_params &q = pl->prm;
   if (pl->kind == FARPCA_STD_BERNOULLI) {
     int *flags = reinterpret_cast<int *>(w.at<double>(pl->off_scal) + 3);
-    launch_setup(static_cast<const float *>(dA), q.lda, q.m, q.n, w.at<double>(pl->off_setup),
+    launch_setup(dA, pl->bf16, q.lda, q.m, q.n, w.at<double>(pl->off_setup),
                  w.at<double>(pl->off_rowsum), flags, st);
     launch_scale_rowsum(w.at<double>(pl->off_rowsum), q.m, pl->p, w.at<float>(pl->off_z), st);
   }
   gen_omega(pl, w, block_j, st);
-  sketch(pl, w, static_cast<const float *>(dA), dS, st);
+  sketch(pl, w, dA, dS, st);
   HIP_OK(hipGetLastError());
   return FARPCA_OK;
 }
@@ -561,6 +585,49 @@ extern "C" int farpca_gemm_tn(const float *dA, int64_t lda, const float *dY, int
   if (ks > 1 && !dPart) return FARPCA_E_INVALID;
   launch_gemm_tn(dA, lda, dY, ldy, dC, ldc, M, N, K, 1.f, 0.f, ks, dPart,
                  static_cast<hipStream_t>(stream));
+  HIP_OK(hipGetLastError());
+  return FARPCA_OK;
+}
+
+extern "C" size_t farpca_gemm_bf16_scratch_bytes(int64_t M, int64_t K) {
+  if (M < 1 || K < 1) return 0;
+  return align_up((size_t)16 * M * kBld * 4) + bf16_pack_bytes(K);
+}
+
+extern "C" int farpca_gemm_bf16_nn(const uint16_t *dA, int64_t lda, const float *dX, int64_t ldx,
+                                   float *dC, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                                   void *dScratch, void *stream) {
+  if (!dA || !dX || !dC || !dScratch || M < 1 || K < 1 || N < 1 || N > kBld || lda < K ||
+      ldx < N || ldc < N)
+    return FARPCA_E_INVALID;
+  if ((reinterpret_cast<uintptr_t>(dScratch) & 255) != 0) return FARPCA_E_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float *part = static_cast<float *>(dScratch);
+  float *xt = reinterpret_cast<float *>(static_cast<char *>(dScratch) +
+                                        align_up((size_t)16 * M * kBld * 4));
+  const int ks = gemm_bf16_choose_ksplit(M, K, 0, 16);
+  const int nsp = launch_gemm_bf16_nn_main(dA, lda, dX, ldx, dC, ldc, M, N, K, 1.f, 0.f, ks, part,
+                                           xt, st);
+  launch_gemm_finish(part, nsp, M, N, dC, ldc, 1.f, 0.f, st);
+  HIP_OK(hipGetLastError());
+  return FARPCA_OK;
+}
+
+extern "C" int farpca_gemm_bf16_tn(const uint16_t *dA, int64_t lda, const float *dY, int64_t ldy,
+                                   float *dC, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                                   void *dScratch, void *stream) {
+  if (!dA || !dY || !dC || !dScratch || M < 1 || K < 1 || N < 1 || N > kBld || lda < M ||
+      ldy < N || ldc < N)
+    return FARPCA_E_INVALID;
+  if ((reinterpret_cast<uintptr_t>(dScratch) & 255) != 0) return FARPCA_E_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float *part = static_cast<float *>(dScratch);
+  float *xt = reinterpret_cast<float *>(static_cast<char *>(dScratch) +
+                                        align_up((size_t)16 * M * kBld * 4));
+  const int ks = gemm_bf16_choose_ksplit(M, K, 1, 16);
+  const int nsp = launch_gemm_bf16_tn_main(dA, lda, dY, ldy, dC, ldc, M, N, K, 1.f, 0.f, ks, part,
+                                           xt, st);
+  launch_gemm_finish(part, nsp, M, N, dC, ldc, 1.f, 0.f, st);
   HIP_OK(hipGetLastError());
   return FARPCA_OK;
 }

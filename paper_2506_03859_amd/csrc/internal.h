@@ -50,7 +50,8 @@ void launch_omega(const OmegaSpec &s, int64_t n, int64_t block_j,
 // nsplit == 1: out (m x kBld) = scale * (A Omega) + zc * z (z may be null).
 // nsplit > 1: out = partials (nsplit x m x kBld) of the unscaled sums over
 // consecutive chunk groups; finish with launch_reduce_partials.
-void launch_sketch_full(const float *A, int64_t lda, int64_t m, int64_t n, int b,
+// A is FP32 or (bf16) BF16 bit patterns.
+void launch_sketch_full(const void *A, bool bf16, int64_t lda, int64_t m, int64_t n, int b,
                         const uint32_t *colptr, const ChunkEntry *entries, float *out,
                         int nsplit, float scale, const float *z, float zc, hipStream_t st);
 int sketch_choose_split(int64_t m, int64_t n);
@@ -89,6 +90,20 @@ int launch_gemm_tn_main(const float *A, int64_t lda, const float *Y, int64_t ldy
 void launch_gemm_finish(const float *part, int nsp, int64_t M, int64_t N, float *C, int64_t ldc,
                         float alpha, float beta, hipStream_t st);
 
+// ---- gemm_bf16.hip (A stored as BF16 bit patterns; the FP32 skinny operand
+// is split exactly into three BF16 terms; FP32 accumulation).  Same NN / TN
+// conventions and partial handling as the FP32 kernels.  `xt` is scratch of
+// bf16_pack_bytes(K) bytes (the transposed, zero-padded skinny operand).
+int64_t bf16_padded_k(int64_t K);
+size_t bf16_pack_bytes(int64_t K);
+int gemm_bf16_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split);
+int launch_gemm_bf16_nn_main(const uint16_t *A, int64_t lda, const float *X, int64_t ldx, float *C,
+                             int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
+                             int ksplit, float *part, float *xt, hipStream_t st);
+int launch_gemm_bf16_tn_main(const uint16_t *A, int64_t lda, const float *Y, int64_t ldy, float *C,
+                             int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
+                             int ksplit, float *part, float *xt, hipStream_t st);
+
 // ---- dense64.hip (FP64 small-matrix work)
 // Gram G[b x b] (FP64) = X^T X for X (K x b, FP32, ldx; columns >= b ignored);
 // partials in `part` (nblk x 64 x 64 doubles), nblk = gram_num_partials(K) <=
@@ -107,7 +122,7 @@ void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const doubl
 // Setup pass over A: partial sums of squares (FP64, per row block) and the
 // row sums (FP64, rowsum[i]); nonfinite flag.
 int setup_num_partials(int64_t m);
-void launch_setup(const float *A, int64_t lda, int64_t m, int64_t n, double *part_sq,
+void launch_setup(const void *A, bool bf16, int64_t lda, int64_t m, int64_t n, double *part_sq,
                   double *rowsum, int *flags, hipStream_t st);
 // out[0] = sum of partials (fixed order).
 void launch_sum_partials(const double *part, int count, double *out, hipStream_t st);

@@ -1,12 +1,14 @@
 // Sparse sketch S = A * Omega_j for the sparse test matrices (Section 3: the
 // cost of A B_j is nnz(B_j) m instead of a dense product).
 //
-// A is streamed in chunks of 64 columns.  A workgroup has four waves over one
+// A (FP32, or BF16 for the precision form: widened exactly to FP32 when the
+// tile is stored in LDS, so everything after the load is shared) is streamed
+// in chunks of 64 columns.  A workgroup has four waves over one
 // block of 128 rows; lane l of every wave owns rows 2 l and 2 l + 1 of the
 // block, wave w owns output columns 16 w .. 16 w + 15.  Per chunk
 //   1. each wave holds a quarter of the block's 128 x 64 tile of A in
 //      registers (16-byte loads, 4 rows x 256 contiguous bytes per
-//      instruction) and stores it transposed into the LDS tile (column-major,
+//      instruction; BF16: 8-byte loads, 4 rows x 128 bytes) and stores it transposed into the LDS tile (column-major,
 //      130 floats per column: rows 2 l, 2 l + 1 form one aligned 8-byte pair).
 //      Tiles are fetched two chunks ahead, so that every wave keeps 16 KB in
 //      flight while it works: HBM needs a few hundred KB in flight per CU;
@@ -43,55 +45,85 @@ static_assert(kPiece % kListPad == 0, "pieces hold whole groups");
 int sketch_lds_row_stride_bytes() { return kTileStride * 4; }
 int sketch_rows_per_wg() { return kRowsWg; }
 
+// Registers of a quarter tile: 4 consecutive columns of A per row and
+// instruction, as loaded (FP32: 16 bytes; BF16: 8 bytes, widened to FP32 only
+// when the tile is stored, so the loads stay in flight until then).
+template <typename T> struct TileRaw;
+template <> struct TileRaw<float> { using type = float4; };
+template <> struct TileRaw<uint16_t> { using type = uint2; };
+
 // A quarter tile (rows r0 .. r0 + 31) into registers: instruction
 // q covers rows r0 + 4 q + lane/16, columns col0 + 4 (lane%16) .. +3.  Rows
 // beyond m are clamped to m - 1 (they feed outputs that are never stored) and
-// columns beyond n read as zero.  VEC (lda % 4 == 0, A 16-byte aligned,
-// lda < 2^28): one 16-byte load per instruction from a uniform row base plus a
+// columns beyond n read as zero.  VEC (lda % 4 == 0, A aligned to 4 elements,
+// lda < 2^28): one vector load per instruction from a uniform row base plus a
 // 32-bit lane offset; a column group that crosses n is read at a clamped
 // column inside the row (lda >= n) and then masked.  Otherwise scalar loads.
-template <bool VEC>
-__device__ __forceinline__ void load_half(const float *__restrict__ A, int64_t lda, int64_t m,
+template <typename T, bool VEC>
+__device__ __forceinline__ void load_half(const T *__restrict__ A, int64_t lda, int64_t m,
                                           int64_t n, int64_t r0, int64_t col0, int lane,
-                                          float4 (&reg)[8]) {
+                                          typename TileRaw<T>::type (&reg)[8]) {
   const int rsub = lane >> 4;
   const int64_t col = col0 + (lane & 15) * 4;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int64_t rq = (r0 + 4 * q < m) ? r0 + 4 * q : m - 1;
     const int64_t row = (r0 + 4 * q + rsub < m) ? r0 + 4 * q + rsub : m - 1;
-    const float *base = A + rq * lda;
+    const T *base = A + rq * lda;
     const int32_t roff = (int32_t)(row - rq) * (int32_t)lda;
-    float v[4];
     if (VEC) {
       const int64_t cc = col < lda - 4 ? col : lda - 4;
-      const float4 u = *reinterpret_cast<const float4 *>(base + (roff + (int32_t)cc));
-      v[0] = u.x; v[1] = u.y; v[2] = u.z; v[3] = u.w;
+      bool ok[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) v[t] = (col + t < n && cc == col) ? v[t] : 0.0f;
+      for (int t = 0; t < 4; ++t) ok[t] = col + t < n && cc == col;
+      if constexpr (sizeof(T) == 4) {
+        const float4 u = *reinterpret_cast<const float4 *>(base + (roff + (int32_t)cc));
+        reg[q] = make_float4(ok[0] ? u.x : 0.0f, ok[1] ? u.y : 0.0f, ok[2] ? u.z : 0.0f,
+                             ok[3] ? u.w : 0.0f);
+      } else {
+        const uint2 u = *reinterpret_cast<const uint2 *>(base + (roff + (int32_t)cc));
+        const uint32_t m0 = (ok[0] ? 0x0000FFFFu : 0u) | (ok[1] ? 0xFFFF0000u : 0u);
+        const uint32_t m1 = (ok[2] ? 0x0000FFFFu : 0u) | (ok[3] ? 0xFFFF0000u : 0u);
+        reg[q] = make_uint2(u.x & m0, u.y & m1);
+      }
     } else {
+      T v[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int64_t c = col + t < n ? col + t : n - 1;
-        const float u = base[roff + (int32_t)c];
-        v[t] = (col + t < n) ? u : 0.0f;
+        const T u = base[roff + (int32_t)c];
+        v[t] = (col + t < n) ? u : T(0);
+      }
+      if constexpr (sizeof(T) == 4) {
+        reg[q] = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+        reg[q] = make_uint2((uint32_t)v[0] | ((uint32_t)v[1] << 16),
+                            (uint32_t)v[2] | ((uint32_t)v[3] << 16));
       }
     }
-    reg[q] = make_float4(v[0], v[1], v[2], v[3]);
   }
 }
 
+__device__ __forceinline__ float4 widen(const float4 &v) { return v; }
+// BF16 bit patterns (low half first) to FP32: exact.
+__device__ __forceinline__ float4 widen(const uint2 &v) {
+  return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xFFFF0000u),
+                     __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xFFFF0000u));
+}
+
 // Store a quarter tile transposed: tile[col][row] with row = 32 w + 4 q + lane/16.
-__device__ __forceinline__ void store_half(float *tile, int w, int lane, const float4 (&reg)[8]) {
+template <typename R>
+__device__ __forceinline__ void store_half(float *tile, int w, int lane, const R (&reg)[8]) {
   const int rsub = lane >> 4;
   const int c4 = (lane & 15) * 4;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int row = 32 * w + 4 * q + rsub;
-    tile[(c4 + 0) * kTileStride + row] = reg[q].x;
-    tile[(c4 + 1) * kTileStride + row] = reg[q].y;
-    tile[(c4 + 2) * kTileStride + row] = reg[q].z;
-    tile[(c4 + 3) * kTileStride + row] = reg[q].w;
+    const float4 v = widen(reg[q]);
+    tile[(c4 + 0) * kTileStride + row] = v.x;
+    tile[(c4 + 1) * kTileStride + row] = v.y;
+    tile[(c4 + 2) * kTileStride + row] = v.z;
+    tile[(c4 + 3) * kTileStride + row] = v.w;
   }
 }
 
@@ -166,9 +198,9 @@ __device__ __forceinline__ void sketch_piece(float (&acc)[2][kHalf], const uint2
   }
 }
 
-template <bool VEC, bool DIRECT>
+template <typename T, bool VEC, bool DIRECT>
 __global__ __launch_bounds__(kThreads) void sketch_kernel(
-    const float *__restrict__ A, int64_t lda, int64_t m, int64_t n, int b,
+    const T *__restrict__ A, int64_t lda, int64_t m, int64_t n, int b,
     const uint32_t *__restrict__ colptr, const ChunkEntry *__restrict__ entries,
     float *__restrict__ out, int64_t chunks_per_split, int64_t tiles, int64_t total_wg,
     float scale, const float *__restrict__ z, float zc) {
@@ -193,9 +225,10 @@ __global__ __launch_bounds__(kThreads) void sketch_kernel(
   for (int c = 0; c < kHalf; ++c) { acc[0][c] = 0.0f; acc[1][c] = 0.0f; }
 
   // quarter tiles of chunks ch + 1 (one set) and ch + 2 (the other) in flight
-  float4 s0[8], s1[8];
-  auto fetch_tile = [&](int64_t ch, float4 (&reg)[8]) {
-    load_half<VEC>(A, lda, m, n, i0 + 32 * wave, ch * kChunk, lane, reg);
+  using Raw = typename TileRaw<T>::type;
+  Raw s0[8], s1[8];
+  auto fetch_tile = [&](int64_t ch, Raw (&reg)[8]) {
+    load_half<T, VEC>(A, lda, m, n, i0 + 32 * wave, ch * kChunk, lane, reg);
   };
   // first piece of a chunk's entries and its column bounds (one chunk ahead)
   uint2 ereg[kPieceLoads];
@@ -231,8 +264,8 @@ __global__ __launch_bounds__(kThreads) void sketch_kernel(
   // one chunk: fetch ahead (lists of ch + 1 first, then the tile of ch + 2, so
   // the wait before staging ch + 1 leaves the newest tile loads in flight),
   // walk ch, stage ch + 1 from `nxt`; `far` receives ch + 2
-  auto iterate = [&](int64_t ch, int buf, uint32_t &cp0, uint32_t &cp1, float4 (&nxt)[8],
-                     float4 (&far)[8]) {
+  auto iterate = [&](int64_t ch, int buf, uint32_t &cp0, uint32_t &cp1, Raw (&nxt)[8],
+                     Raw (&far)[8]) {
     const int64_t c1 = ch + 1 < ch_end ? ch + 1 : ch;      // clamped: in bounds, unused
     const int64_t c2 = ch + 2 < ch_end ? ch + 2 : ch;
     fetch_lists(c1);
@@ -285,23 +318,22 @@ __global__ __launch_bounds__(kThreads) void sketch_kernel(
   }
 }
 
-// part: nsplit == 1 -> final S (scale, z applied); else partials (nsplit x m x kBld).
-void launch_sketch_full(const float *A, int64_t lda, int64_t m, int64_t n, int b,
-                        const uint32_t *colptr, const ChunkEntry *entries, float *out,
-                        int nsplit, float scale, const float *z, float zc, hipStream_t st) {
-  if (m <= 0 || n <= 0) return;
+template <typename T>
+static void launch_sketch_t(const T *A, int64_t lda, int64_t m, int64_t n, int b,
+                            const uint32_t *colptr, const ChunkEntry *entries, float *out,
+                            int nsplit, float scale, const float *z, float zc, hipStream_t st) {
   const int64_t nchunks = (n + kChunk - 1) / kChunk;
   if (nsplit < 1) nsplit = 1;
   if (nsplit > nchunks) nsplit = (int)nchunks;
   const int64_t cps = (nchunks + nsplit - 1) / nsplit;
   nsplit = (int)((nchunks + cps - 1) / cps);
   const bool vec = (lda % 4 == 0) && (lda < (int64_t(1) << 28)) &&
-                   ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+                   ((reinterpret_cast<uintptr_t>(A) & (4 * sizeof(T) - 1)) == 0);
   const int64_t tiles = (m + kRowsWg - 1) / kRowsWg;
   const int64_t total = tiles * nsplit;
   dim3 grid((unsigned)total), blk(kThreads);
-#define FARPCA_SKETCH_LAUNCH(V, D)                                                              \
-  hipLaunchKernelGGL((sketch_kernel<V, D>), grid, blk, 0, st, A, lda, m, n, b, colptr, entries, \
+#define FARPCA_SKETCH_LAUNCH(V, D)                                                                 \
+  hipLaunchKernelGGL((sketch_kernel<T, V, D>), grid, blk, 0, st, A, lda, m, n, b, colptr, entries, \
                      out, cps, tiles, total, scale, z, zc)
   if (nsplit == 1) {
     if (vec) FARPCA_SKETCH_LAUNCH(true, true);
@@ -311,6 +343,19 @@ void launch_sketch_full(const float *A, int64_t lda, int64_t m, int64_t n, int b
     else FARPCA_SKETCH_LAUNCH(false, false);
   }
 #undef FARPCA_SKETCH_LAUNCH
+}
+
+// part: nsplit == 1 -> final S (scale, z applied); else partials (nsplit x m x kBld).
+void launch_sketch_full(const void *A, bool bf16, int64_t lda, int64_t m, int64_t n, int b,
+                        const uint32_t *colptr, const ChunkEntry *entries, float *out,
+                        int nsplit, float scale, const float *z, float zc, hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  if (bf16)
+    launch_sketch_t(static_cast<const uint16_t *>(A), lda, m, n, b, colptr, entries, out, nsplit,
+                    scale, z, zc, st);
+  else
+    launch_sketch_t(static_cast<const float *>(A), lda, m, n, b, colptr, entries, out, nsplit,
+                    scale, z, zc, st);
 }
 
 // Workgroups of the sketch kernel resident on the current device at once.
@@ -326,7 +371,7 @@ static int64_t sketch_slots() {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
     cus = 256;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void *>(&sketch_kernel<true, false>), kThreads, 0) !=
+          &per_cu, reinterpret_cast<const void *>(&sketch_kernel<float, true, false>), kThreads, 0) !=
           hipSuccess ||
       per_cu < 1)
     per_cu = 2;

@@ -2,7 +2,7 @@
 
 The names follow the C-ABI in include/farpca.h: farpca_plan, farpca_run,
 farpca_free, farpca_omega, farpca_sketch, farpca_gemm_nn, farpca_gemm_tn,
-farpca_eig.  Device buffers are torch tensors on the current HIP device;
+farpca_gemm_bf16_nn, farpca_gemm_bf16_tn, farpca_eig.  Device buffers are torch tensors on the current HIP device;
 every step of the method runs in the library's kernels.  ``solve`` is a
 convenience wrapper that allocates the caller-owned buffers the C-ABI asks for.
 
@@ -20,11 +20,13 @@ LIB_PATH = os.path.join(HERE, "libfarpca.so")
 
 SKETCH_IDS = {"gaussian": 0, "std_bernoulli": 1, "sparse_sign": 2, "sparse_gaussian": 3,
               "bernoulli": 4}
+DTYPE_IDS = {"f32": 0, "bf16": 1}
 STATUS_OK = 0
 STATUS_NOT_CONVERGED = 1
 
 EXPORTED = ["farpca_plan", "farpca_run", "farpca_free", "farpca_status_str", "farpca_omega",
             "farpca_sketch", "farpca_gemm_scratch_bytes", "farpca_gemm_nn", "farpca_gemm_tn",
+            "farpca_gemm_bf16_scratch_bytes", "farpca_gemm_bf16_nn", "farpca_gemm_bf16_tn",
             "farpca_eig_scratch_bytes", "farpca_eig", "farpca_profile_enable", "farpca_profile_get"]
 PROF_CLASSES = {"sketch": 0, "gemm_tn": 1, "gemm_nn": 2, "eig": 3}
 
@@ -77,7 +79,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.farpca_sketch.restype = ctypes.c_int
     lib.farpca_gemm_scratch_bytes.argtypes = [i64]
     lib.farpca_gemm_scratch_bytes.restype = sz
-    for name in ("farpca_gemm_nn", "farpca_gemm_tn"):
+    lib.farpca_gemm_bf16_scratch_bytes.argtypes = [i64, i64]
+    lib.farpca_gemm_bf16_scratch_bytes.restype = sz
+    for name in ("farpca_gemm_nn", "farpca_gemm_tn", "farpca_gemm_bf16_nn", "farpca_gemm_bf16_tn"):
         f = getattr(lib, name)
         f.argtypes = [vp, i64, vp, i64, vp, i64, i64, i64, i64, vp, vp]
         f.restype = ctypes.c_int
@@ -112,8 +116,8 @@ def _check(rc: int, what: str) -> int:
 
 
 def make_params(m, n, lda=None, *, tol=0.0, rank=0, block=0, power=1, sketch="sparse_sign",
-                p=0.0, zeta=0, seed=0, max_blocks=0) -> FarpcaParams:
-    return FarpcaParams(m=m, n=n, lda=lda if lda is not None else n, a_dtype=0,
+                p=0.0, zeta=0, seed=0, max_blocks=0, a_dtype="f32") -> FarpcaParams:
+    return FarpcaParams(m=m, n=n, lda=lda if lda is not None else n, a_dtype=DTYPE_IDS[a_dtype],
                         sketch=SKETCH_IDS[sketch], tol=tol, rank=rank, block=block, power=power,
                         max_blocks=max_blocks, sketch_p=p, sketch_zeta=zeta, reserved0=0, seed=seed)
 
@@ -186,6 +190,27 @@ def farpca_gemm_tn(A, Y, C, M, N, K, part, lda=None, ldy=None, ldc=None, stream=
                   "farpca_gemm_tn")
 
 
+def farpca_gemm_bf16_scratch_bytes(M: int, K: int) -> int:
+    return int(load_library().farpca_gemm_bf16_scratch_bytes(M, K))
+
+
+def farpca_gemm_bf16_nn(A, X, C, M, N, K, scratch, lda=None, ldx=None, ldc=None,
+                        stream=None) -> int:
+    """A: BF16 (torch.bfloat16 or int16/uint16 bit patterns), X, C: FP32."""
+    lib = load_library()
+    return _check(lib.farpca_gemm_bf16_nn(_ptr(A), lda or A.stride(0), _ptr(X), ldx or X.stride(0),
+                                          _ptr(C), ldc or C.stride(0), M, N, K, _ptr(scratch),
+                                          _stream(stream)), "farpca_gemm_bf16_nn")
+
+
+def farpca_gemm_bf16_tn(A, Y, C, M, N, K, scratch, lda=None, ldy=None, ldc=None,
+                        stream=None) -> int:
+    lib = load_library()
+    return _check(lib.farpca_gemm_bf16_tn(_ptr(A), lda or A.stride(0), _ptr(Y), ldy or Y.stride(0),
+                                          _ptr(C), ldc or C.stride(0), M, N, K, _ptr(scratch),
+                                          _stream(stream)), "farpca_gemm_bf16_tn")
+
+
 def farpca_eig_scratch_bytes(l: int) -> int:
     return int(load_library().farpca_eig_scratch_bytes(l))
 
@@ -235,13 +260,15 @@ def alloc_outputs(plan: Plan, device="cuda"):
 
 def solve(A, *, tol=0.0, rank=0, block=0, power=1, sketch="sparse_sign", p=0.0, zeta=0, seed=0,
           max_blocks=0, stream=None) -> SolveResult:
-    """Run the whole method on a row-major FP32 CUDA tensor A (m x n)."""
+    """Run the whole method on a row-major CUDA tensor A (m x n): float32, or
+    bfloat16 for the precision form."""
     import torch
-    if A.dtype != torch.float32 or not A.is_cuda or A.stride(1) != 1:
-        raise FarpcaError("A must be a row-major float32 tensor on the GPU")
+    if A.dtype not in (torch.float32, torch.bfloat16) or not A.is_cuda or A.stride(1) != 1:
+        raise FarpcaError("A must be a row-major float32 or bfloat16 tensor on the GPU")
     m, n = A.shape
+    dt = "bf16" if A.dtype == torch.bfloat16 else "f32"
     prm = make_params(m, n, A.stride(0), tol=tol, rank=rank, block=block, power=power, sketch=sketch,
-                      p=p, zeta=zeta, seed=seed, max_blocks=max_blocks)
+                      p=p, zeta=zeta, seed=seed, max_blocks=max_blocks, a_dtype=dt)
     plan = farpca_plan(prm)
     try:
         work, U, S, V, eh = alloc_outputs(plan, A.device)

@@ -17,6 +17,8 @@ Constructions (all seeded, numpy PCG64 unless stated):
   i.i.d. N(0, var) noise, the tall fixed-rank workload.
 * ``integer_matrix``: small-integer-valued matrices, for which any ordering
   of a short FP32 sum is exact.
+* ``bf16_bits`` / ``bf16_value``: BF16 storage of an FP32 matrix (round to
+  nearest even) for the precision form, and the exact values it holds.
 """
 from __future__ import annotations
 
@@ -114,3 +116,17 @@ def integer_matrix(m: int, n: int, seed: int, amax: int = 1024) -> np.ndarray:
 
 def gaussian_matrix(m: int, n: int, seed: int) -> np.ndarray:
     return _rng(seed).standard_normal((m, n))
+
+
+def bf16_bits(a) -> np.ndarray:
+    """Storage of a finite FP32 matrix in BF16: the upper 16 bits of each value
+    after round-to-nearest-even at bit 16 (uint16 bit patterns).  This is the
+    input of the precision form; the matrix it represents is bf16_value(bits)."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return r.astype(np.uint16)
+
+
+def bf16_value(bits) -> np.ndarray:
+    """The FP32 values (exact) of BF16 bit patterns."""
+    return (np.asarray(bits, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)

@@ -208,3 +208,69 @@ def test_bitwise_repeatable(fp, a_mid):
     U1, S1 = r1.U.clone(), r1.S.clone()
     r2 = fp.solve(A, tol=1e-3, block=32, power=2, sketch="sparse_sign", zeta=8, seed=11)
     assert torch.equal(U1, r2.U) and torch.equal(S1, r2.S)
+
+
+# ---------------------------------------------------------------- BF16 form
+# The precision form stores A in BF16 (round to nearest even) and computes the
+# A-passes on the BF16 matrix cores with exact products (three-term split of
+# the FP32 operand) and FP32 accumulation.  Its input is the BF16 matrix: the
+# oracle runs on those exact values in FP64, and the tolerances are the FP32
+# path's.  The storage error against the FP32 matrix is reported.
+def run_both_bf16(fp, a32, **kw):
+    import torch
+    bits = synth.bf16_bits(a32)
+    ab = synth.bf16_value(bits)
+    store = np.linalg.norm(ab.astype(np.float64) - a32) / np.linalg.norm(a32.astype(np.float64))
+    print(f"farpca_run bf16 m={a32.shape[0]} n={a32.shape[1]} {kw} storage error {store:.3e}", flush=True)
+    A = torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16)
+    res = fp.solve(A, **kw)
+    torch.cuda.synchronize()
+    okw = {k: v for k, v in kw.items() if k in ("tol", "rank", "block", "power", "sketch", "p", "zeta",
+                                                  "seed", "max_blocks")}
+    ref = farpca(ab.astype(np.float64), FarpcaParams(**okw), keep_bases=True)
+    return res, ref, ab
+
+
+@pytest.mark.parametrize("sketch,p,zeta", [("sparse_sign", 0.0, 8), ("sparse_gaussian", 0.05, 0),
+                                           ("std_bernoulli", 0.0, 0), ("gaussian", 0.0, 0)])
+@pytest.mark.parametrize("power", [0, 2])
+def test_bf16_sketches(fp, a_mid, sketch, p, zeta, power):
+    res, ref, ab = run_both_bf16(fp, a_mid, tol=1e-2, block=32, power=power, sketch=sketch, p=p,
+                                 zeta=zeta, seed=3)
+    assert res.status == ref.status == 0
+    if same_rank_or_tie(res, ref, 1e-4 * ref.norm_a2):
+        compare(res, ref, ab)
+
+
+def test_bf16_precision_workload_small(fp):
+    # the precision-form workload at reduced size: exp(-i/50) + 1e-6 spectrum,
+    # sparse Gaussian density 0.05, b = 64, P = 2, tol 1e-2
+    a = synth.spectral(4000, 3000, synth.exp_floor_sigma(3000), seed=2).astype(np.float32)
+    res, ref, ab = run_both_bf16(fp, a, tol=1e-2, block=64, power=2, sketch="sparse_gaussian",
+                                 p=0.05, seed=1000)
+    assert res.status == ref.status == 0
+    if same_rank_or_tie(res, ref, 1e-4 * ref.norm_a2):
+        compare(res, ref, ab)
+
+
+def test_bf16_matches_fp32_path_on_same_values(fp, a_mid):
+    # the two storage forms of the same (BF16-valued) matrix give the same
+    # solve up to FP32 accumulation order
+    import torch
+    bits = synth.bf16_bits(a_mid)
+    ab = synth.bf16_value(bits)
+    kw = dict(tol=1e-3, block=32, power=2, sketch="sparse_sign", zeta=8, seed=5)
+    r16 = fp.solve(torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16), **kw)
+    r32 = fp.solve(torch.from_numpy(ab).cuda(), **kw)
+    assert r16.info.rank_l == r32.info.rank_l
+    assert abs(r16.info.norm_a2 - r32.info.norm_a2) <= 1e-13 * r32.info.norm_a2
+    a = ab.astype(np.float64)
+    nA = np.linalg.norm(a)
+
+    def eps(r):
+        return np.linalg.norm(a - (r.U.cpu().double().numpy() * r.S.cpu().numpy())
+                              @ r.V.cpu().double().numpy().T) / nA
+    assert abs(eps(r16) - eps(r32)) <= 1e-6
+    s16, s32 = r16.S.cpu().numpy(), r32.S.cpu().numpy()
+    assert np.max(np.abs(s16 - s32)) <= 1e-6 * s32[0]
+    assert abs(r16.info.err_indicator - r32.info.err_indicator) <= 1e-7 * r32.info.norm_a2

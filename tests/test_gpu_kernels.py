@@ -214,6 +214,129 @@ def test_gemm_float_error_bound(fp, M, K, N, kind):
     assert np.all(err <= 6 * U32 * math.sqrt(K) * absref)
 
 
+# ---------------------------------------------------------------- BF16 form
+def bf16_dev(a32):
+    """BF16 storage of an FP32 matrix on the GPU (int16 bit patterns) and the
+    exact values it holds (float64)."""
+    import torch
+    bits = synth.bf16_bits(a32)
+    return (torch.from_numpy(bits.view(np.int16)).cuda(),
+            synth.bf16_value(bits).astype(np.float64))
+
+
+def bf16_scratch(fp, M, K):
+    import torch
+    n = fp.farpca_gemm_bf16_scratch_bytes(M, K)
+    buf = torch.empty(n + 256, dtype=torch.uint8, device="cuda")
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + n]
+
+
+# NN vector loads need K % 8 == 0, TN vector loads M % 4 == 0: both paths occur
+BF16_GEMM_SHAPES = [(1000, 777, 50), (130, 3000, 64), (64, 64, 1), (5000, 20000, 64), (1, 300, 7),
+                    (257, 1500, 33), (3000, 64, 64), (9001, 3001, 64), (20000, 1000, 64),
+                    (8200, 40, 64), (1024, 4096, 64), (700, 5, 3)]
+
+
+def bf16_gemm(fp, kind, A, x, M, N, K):
+    import torch
+    C = torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")
+    scratch = bf16_scratch(fp, M, K)
+    if kind == "nn":
+        fp.farpca_gemm_bf16_nn(A, dev(x), C, M, N, K, scratch)
+    else:
+        fp.farpca_gemm_bf16_tn(A, dev(x), C, M, N, K, scratch)
+    return host(C)
+
+
+@pytest.mark.parametrize("M,K,N", BF16_GEMM_SHAPES)
+@pytest.mark.parametrize("kind", ["nn", "tn"])
+def test_gemm_bf16_integer_exact(fp, M, K, N, kind):
+    rng = np.random.default_rng(M * 11 + K)
+    # A in [-4, 4] (exact in BF16); X up to 2^11 in magnitude, so that the
+    # split of X uses two BF16 terms; |sums| < 2^24: every order is exact
+    xmax = min(2048, (2 ** 24 - 1) // (4 * max(K, 1)))
+    shape = (M, K) if kind == "nn" else (K, M)
+    a = rng.integers(-4, 5, size=shape).astype(np.float32)
+    x = rng.integers(-xmax, xmax + 1, size=(K, N)).astype(np.float32)
+    A, a64 = bf16_dev(a)
+    assert np.array_equal(a64, a)
+    print(f"gemm bf16 {kind} M={M} K={K} N={N}", flush=True)
+    got = bf16_gemm(fp, kind, A, x, M, N, K)
+    ref = (a64 @ x.astype(np.float64)) if kind == "nn" else (a64.T @ x.astype(np.float64))
+    assert np.array_equal(got, ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("M,K,N", [(1000, 2048, 64), (3000, 777, 50), (9001, 3001, 64)])
+@pytest.mark.parametrize("kind", ["nn", "tn"])
+def test_gemm_bf16_split_exact(fp, M, K, N, kind):
+    # one nonzero +-2^e per output row of A's product, X with full 24-bit
+    # significands: every output is a single product, exact only if the
+    # three-term split of X is exact
+    rng = np.random.default_rng(K)
+    shape = (M, K) if kind == "nn" else (K, M)
+    a = np.zeros(shape, dtype=np.float32)
+    pick = rng.integers(0, K, size=M)
+    val = rng.choice([-1.0, 1.0], size=M) * 2.0 ** rng.integers(-3, 4, size=M)
+    if kind == "nn":
+        a[np.arange(M), pick] = val
+    else:
+        a[pick, np.arange(M)] = val
+    x = (rng.standard_normal((K, N)) * 2.0 ** rng.integers(-20, 20, size=(K, N))).astype(np.float32)
+    A, a64 = bf16_dev(a)
+    print(f"gemm bf16 split {kind} M={M} K={K} N={N}", flush=True)
+    got = bf16_gemm(fp, kind, A, x, M, N, K)
+    ref = (a64 @ x.astype(np.float64)) if kind == "nn" else (a64.T @ x.astype(np.float64))
+    assert np.array_equal(got, ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("M,K,N", [(2000, 15000, 64), (15000, 2000, 64), (333, 4000, 50),
+                                   (20000, 15000, 64)])
+@pytest.mark.parametrize("kind", ["nn", "tn"])
+def test_gemm_bf16_float_error_bound(fp, M, K, N, kind):
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal((M, K) if kind == "nn" else (K, M)).astype(np.float32)
+    x = rng.standard_normal((K, N)).astype(np.float32)
+    A, a64 = bf16_dev(a)
+    print(f"gemm bf16 float {kind} M={M} K={K} N={N}", flush=True)
+    got = bf16_gemm(fp, kind, A, x, M, N, K)
+    x64 = x.astype(np.float64)
+    if kind == "nn":
+        ref, absref = a64 @ x64, np.abs(a64) @ np.abs(x64)
+    else:
+        ref, absref = a64.T @ x64, np.abs(a64).T @ np.abs(x64)
+    # the products are exact; only the FP32 accumulation rounds
+    assert np.all(np.abs(got - ref) <= 6 * U32 * math.sqrt(K) * absref)
+
+
+@pytest.mark.parametrize("sketch,p,zeta,b,m,n", SKETCH_CASES[:6] + SKETCH_CASES[-3:])
+def test_sketch_bf16_bit_exact_integer_A(fp, sketch, p, zeta, b, m, n):
+    import torch
+    # integers up to 256 are exact in BF16
+    a = synth.integer_matrix(m, n, seed=m + 3 * n, amax=256)
+    A, a64 = bf16_dev(a.astype(np.float32))
+    assert np.array_equal(a64, a)
+    prm = fp.make_params(m, n, tol=0.1, block=b, power=1, sketch=sketch, p=p, zeta=zeta, seed=78,
+                         a_dtype="bf16")
+    plan = fp.farpca_plan(prm)
+    try:
+        work, *_ = fp.alloc_outputs(plan)
+        S = torch.full((m, 64), float("nan"), dtype=torch.float32, device="cuda")
+        for j in (0, 4):
+            print(f"sketch bf16 {sketch} p={p} zeta={zeta} b={b} m={m} n={n} block={j}", flush=True)
+            fp.farpca_sketch(plan, A, j, work, S)
+            got = host(S)
+            if sketch == "std_bernoulli":
+                bm = om.bernoulli_mask(n, b, j, 78, p).astype(np.float64)
+                ref = a @ bm - (a @ (p * np.ones(n)))[:, None]
+            else:
+                ref = a @ om.omega_dense(n, b, j, sketch, 78, p, zeta)
+            assert np.array_equal(got[:, :b], ref.astype(np.float32))
+            assert np.all(got[:, b:] == 0)
+    finally:
+        plan.free()
+
+
 @pytest.mark.parametrize("l", [5, 20, 64, 65, 100, 250])
 @pytest.mark.parametrize("spectrum", ["uniform", "graded"])
 def test_eig_vs_lapack(fp, l, spectrum):
