@@ -7,6 +7,9 @@ exp(-i/50) + 1e-6, U, V Haar (QR of seeded Gaussians); sparse sign test
 matrix with zeta = 8 nonzeros per row (+-1/sqrt(8)), b = 64, P = 2, relative
 tolerance 1e-3.  A step is one whole solve - every block of the loop and the
 final decomposition - with A resident in HBM; block seeds 1000 + r.
+Other workloads (--workload): the tall fixed-rank matrix, and the precision
+form (the same matrix stored in BF16, sparse Gaussian density 0.05 or sparse
+sign, tol 1e-2) beside its FP32 twin.
 
 The JSON line carries the roofline of the dominant kernel (HIP events on the
 library's stream around every launch of the kernel classes that stream A),
@@ -30,9 +33,19 @@ PEAK_HBM_GBPS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 
 WORKLOADS = {
-    # name: (m, n, spectrum, seed, tol, b, P, sketch, zeta, p)
-    "exp50_20000x15000_ss8": (20000, 15000, "exp50", 2, 1e-3, 64, 2, "sparse_sign", 8, 0.0),
-    "tall_200000x4000_rank200": (200000, 4000, "tall", 4, 0.0, 50, 1, "sparse_sign", 4, 0.0),
+    # name: (m, n, spectrum, seed, tol, b, P, sketch, zeta, p, storage of A)
+    "exp50_20000x15000_ss8": (20000, 15000, "exp50", 2, 1e-3, 64, 2, "sparse_sign", 8, 0.0, "f32"),
+    "tall_200000x4000_rank200": (200000, 4000, "tall", 4, 0.0, 50, 1, "sparse_sign", 4, 0.0, "f32"),
+    # precision form: the same matrix stored in BF16 (round to nearest even),
+    # sparse Gaussian test matrix of density 0.05, tol 1e-2; and its FP32 twin
+    "bf16_exp50_20000x15000_sg05": (20000, 15000, "exp50", 2, 1e-2, 64, 2, "sparse_gaussian", 0,
+                                    0.05, "bf16"),
+    "exp50_20000x15000_sg05": (20000, 15000, "exp50", 2, 1e-2, 64, 2, "sparse_gaussian", 0, 0.05,
+                               "f32"),
+    "bf16_exp50_20000x15000_ss8_tol1e-2": (20000, 15000, "exp50", 2, 1e-2, 64, 2, "sparse_sign", 8,
+                                           0.0, "bf16"),
+    "exp50_20000x15000_ss8_tol1e-2": (20000, 15000, "exp50", 2, 1e-2, 64, 2, "sparse_sign", 8, 0.0,
+                                      "f32"),
 }
 
 
@@ -45,6 +58,7 @@ def make_matrix(name, device):
     import torch
     from paper_2506_03859_amd import synth
     m, n, spec, seed = WORKLOADS[name][:4]
+    storage = WORKLOADS[name][10]
     if spec == "exp50":
         sigma = synth.exp_floor_sigma(min(m, n), decay=50.0, floor=1e-6)
         a64 = synth.spectral_torch(m, n, sigma, seed, device=device)
@@ -52,6 +66,8 @@ def make_matrix(name, device):
         del a64
     else:
         a = torch.from_numpy(synth.tall_lowrank(m, n, 100, 1e-6, seed, dtype=np.float32)).to(device)
+    if storage == "bf16":
+        a = a.to(torch.bfloat16).contiguous()     # round to nearest even
     torch.cuda.synchronize()
     return a
 
@@ -68,6 +84,9 @@ KERNEL_SOURCES = {
     "gemm_tn": ["paper_2506_03859_amd/csrc/gemm.hip"],
     "gemm_nn": ["paper_2506_03859_amd/csrc/gemm.hip"],
     "sketch": ["paper_2506_03859_amd/csrc/sketch.hip"],
+    "gemm_tn_bf16": ["paper_2506_03859_amd/csrc/gemm_bf16.hip"],
+    "gemm_nn_bf16": ["paper_2506_03859_amd/csrc/gemm_bf16.hip"],
+    "sketch_bf16": ["paper_2506_03859_amd/csrc/sketch.hip"],
 }
 
 
@@ -90,8 +109,8 @@ def cpu_baseline(a_dev, wl, blocks_gpu, min_seconds=10.0, max_solves=5):
     time have passed (a bounded sample of the workload)."""
     import numpy as np
     from oracle import FarpcaParams, farpca
-    m, n, _, _, tol, b, P, sketch, zeta, p = WORKLOADS[wl]
-    a = a_dev.cpu().numpy().astype(np.float64)
+    m, n, _, _, tol, b, P, sketch, zeta, p, _ = WORKLOADS[wl]
+    a = a_dev.float().cpu().numpy().astype(np.float64)
     try:
         from threadpoolctl import threadpool_info
         cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
@@ -120,19 +139,30 @@ def kernel_probe(wl, dev, reps=3):
     write of known size for scaling FETCH_SIZE / WRITE_SIZE)."""
     import torch
     from paper_2506_03859_amd import farpca as fp
-    m, n, _, _, tol, b, P, sketch, zeta, p = WORKLOADS[wl]
+    m, n, _, _, tol, b, P, sketch, zeta, p, storage = WORKLOADS[wl]
     A = torch.randn(m, n, device=dev)
+    if storage == "bf16":
+        A = A.to(torch.bfloat16)
     skinny_n = torch.randn(n, 64, device=dev)
     skinny_m = torch.randn(m, 64, device=dev)
     Cm = torch.zeros(m, 64, device=dev)
     Cn = torch.zeros(n, 64, device=dev)
-    part = torch.empty(fp.farpca_gemm_scratch_bytes(max(m, n)) // 4, device=dev)
     plan = fp.farpca_plan(fp.make_params(m, n, tol=tol, rank=(200 if tol == 0.0 else 0), block=b,
-                                         power=P, sketch=sketch, p=p, zeta=zeta, seed=1000))
+                                         power=P, sketch=sketch, p=p, zeta=zeta, seed=1000,
+                                         a_dtype=storage))
     work, _, _, _, _ = fp.alloc_outputs(plan, dev)
+    if storage == "bf16":
+        nb = fp.farpca_gemm_bf16_scratch_bytes(max(m, n), max(m, n))
+        buf = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        off = (-buf.data_ptr()) % 256
+        scratch = buf[off:off + nb]
+        gemm_tn, gemm_nn = fp.farpca_gemm_bf16_tn, fp.farpca_gemm_bf16_nn
+    else:
+        scratch = torch.empty(fp.farpca_gemm_scratch_bytes(max(m, n)) // 4, device=dev)
+        gemm_tn, gemm_nn = fp.farpca_gemm_tn, fp.farpca_gemm_nn
     for r in range(reps):
-        fp.farpca_gemm_tn(A, skinny_m, Cn, n, b, m, part)
-        fp.farpca_gemm_nn(A, skinny_n, Cm, m, b, n, part)
+        gemm_tn(A, skinny_m, Cn, n, b, m, scratch)
+        gemm_nn(A, skinny_n, Cm, m, b, n, scratch)
         fp.farpca_sketch(plan, A, r, work, Cm)
     torch.cuda.synchronize()
     plan.free()
@@ -172,7 +202,7 @@ def main():
     if args.kernel_probe:
         kernel_probe(wl, dev)
         return
-    m, n, _, _, tol, b, P, sketch, zeta, p = WORKLOADS[wl]
+    m, n, _, _, tol, b, P, sketch, zeta, p, storage = WORKLOADS[wl]
     rank = 200 if tol == 0.0 else 0
     log(f"generating {wl}")
     A = make_matrix(wl, dev)
@@ -180,7 +210,8 @@ def main():
 
     nruns = args.warmup + args.steps
     plans = [fp.farpca_plan(fp.make_params(m, n, tol=tol, rank=rank, block=b, power=P, sketch=sketch,
-                                           p=p, zeta=zeta, seed=1000 + r)) for r in range(nruns)]
+                                           p=p, zeta=zeta, seed=1000 + r, a_dtype=storage))
+             for r in range(nruns)]
     work, U, S, V, eh = fp.alloc_outputs(plans[0], dev)
     if args.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -218,7 +249,8 @@ def main():
         return (tot / cnt if cnt else None), cnt
 
     gemm_flops = 2.0 * m * n * b
-    a_bytes = 4.0 * m * n
+    elem = 2.0 if storage == "bf16" else 4.0
+    a_bytes = elem * m * n
     cand = {}
     for c in ("gemm_tn", "gemm_nn", "sketch"):
         a_ms, cnt = avg(c)
@@ -231,13 +263,23 @@ def main():
         achieved = alg / (a_ms * 1e-3) / 1e9
         roof = {"kernel": "sketch_kernel", "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS,
                 "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS}
+    elif storage == "bf16":
+        # BF16 A-passes: 2 m n bytes of A per launch against HBM (the exact
+        # three-term products need 3 x 2 m n b flop of BF16 MFMA, under its peak)
+        achieved = a_bytes / (a_ms * 1e-3) / 1e9
+        roof = {"kernel": f"{dom}_bf16_kernel", "bound": "hbm", "achieved": achieved,
+                "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS}
     else:
         achieved = gemm_flops / (a_ms * 1e-3) / 1e12
         roof = {"kernel": f"{dom}_kernel", "bound": "mfma", "achieved": achieved,
                 "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS}
-    roof.update({"avg_launch_ms": a_ms, "launches": cnt, "algorithmic_per_launch":
-                 (a_bytes + 4.0 * m * b) if dom == "sketch" else gemm_flops,
-                 "traffic": measured_traffic(dom)})
+    if dom == "sketch":
+        alg_per_launch = a_bytes + 4.0 * m * b
+    else:
+        alg_per_launch = a_bytes if storage == "bf16" else gemm_flops
+    traffic_key = dom if storage == "f32" else f"{dom}_bf16"
+    roof.update({"avg_launch_ms": a_ms, "launches": cnt, "algorithmic_per_launch": alg_per_launch,
+                 "traffic": measured_traffic(traffic_key)})
     classes = {}
     for c, (tot, cnt) in prof.items():
         classes[c] = {"total_ms_per_solve": tot / args.steps, "launches": cnt,
@@ -247,6 +289,7 @@ def main():
     for c in ("gemm_tn", "gemm_nn"):
         if classes[c]["avg_launch_ms"]:
             classes[c]["tflops"] = gemm_flops / (classes[c]["avg_launch_ms"] * 1e-3) / 1e12
+            classes[c]["a_GBps"] = a_bytes / (classes[c]["avg_launch_ms"] * 1e-3) / 1e9
 
     out = {
         "metric": "time-to-tolerance & sketch HBM GB/s per solve",
@@ -261,10 +304,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if storage == "f32" else "bf16",
         "data": "synthetic",
         "config": {"workload": wl, "m": m, "n": n, "tol": tol, "rank": rank, "block": b, "power": P,
-                   "sketch": sketch, "zeta": zeta, "blocks": sorted(set(blocks)), "l": sorted(set(ls)),
+                   "sketch": sketch, "zeta": zeta, "p": p, "a_storage": storage, "blocks": sorted(set(blocks)), "l": sorted(set(ls)),
                    "parallelism": "single GPU"},
         "roofline": roof,
         "kernels": classes,
