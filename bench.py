@@ -174,6 +174,127 @@ def kernel_probe(wl, dev, reps=3):
     log(f"kernel probe done ({reps} launches each, then a {src.numel() * 4 >> 20} MiB copy)")
 
 
+def serve_trace(nreq=512, rate=200.0, seed=5, bank=24):
+    """The serving workload: nreq requests with Poisson arrivals at `rate` per
+    second; shapes m in [500, 8000], n in [300, 4000] log-uniform; spectra
+    i^-1.5, exp(-i/30) or rank r + noise (r log-uniform in [5, min(m,n)/4],
+    noise variance 1e-6 sigma_1^2); tol in {1e-2, 1e-3, 1e-4}; storage FP32 or
+    BF16 (BF16 only where tol >= 4x the BF16 storage error, else FP32);
+    sparse sign test matrix (zeta = 8), b by the default rule, P = 1.  The
+    matrices come from a bank of `bank` seeded matrices drawn from the same
+    distribution (generation cost); each request picks one, plus its own tol,
+    storage and seed."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    mats = []
+    for i in range(bank):
+        m = int(round(math.exp(rng.uniform(math.log(500), math.log(8000)))))
+        n = int(round(math.exp(rng.uniform(math.log(300), math.log(4000)))))
+        kind = ("pow", "exp", "lowrank")[i % 3]
+        r = int(round(math.exp(rng.uniform(math.log(5), math.log(max(6, min(m, n) // 4))))))
+        mats.append((m, n, kind, r, 5000 + i))
+    t = np.cumsum(rng.exponential(1.0 / rate, size=nreq))
+    reqs = []
+    for i in range(nreq):
+        reqs.append(dict(t=float(t[i]), mat=int(rng.integers(0, bank)),
+                         tol=float(rng.choice([1e-2, 1e-3, 1e-4])),
+                         bf16=bool(rng.integers(0, 2)), seed=10000 + i))
+    return mats, reqs
+
+
+def serve_matrix(spec, device):
+    import numpy as np
+    import torch
+    from paper_2506_03859_amd import synth
+    m, n, kind, r, seed = spec
+    k = min(m, n, 1024)
+    if kind == "pow":
+        a = synth.spectral_torch(m, n, np.arange(1, k + 1, dtype=np.float64) ** -1.5, seed, device)
+    elif kind == "exp":
+        a = synth.spectral_torch(m, n, np.exp(-np.arange(1, k + 1, dtype=np.float64) / 30.0), seed, device)
+    else:
+        a = synth.spectral_torch(m, n, np.ones(min(r, k)), seed, device)
+        g = torch.Generator(device=device).manual_seed(seed)
+        a += 1e-3 * torch.randn(m, n, generator=g, device=device, dtype=torch.float64)
+    return a.to(torch.float32).contiguous()
+
+
+def serve_bench(args, dev):
+    """Open-loop replay of the serving trace through farpca_server_*; prints
+    one JSON line with solves/s and latency percentiles for the mixed-storage
+    trace and for the same trace with every request in FP32."""
+    import threading
+
+    import numpy as np
+    import torch
+    from paper_2506_03859_amd import farpca as fp
+    mats, reqs = serve_trace(nreq=args.serve_requests)
+    log(f"serve: generating {len(mats)} matrices")
+    A32 = [serve_matrix(sp, dev) for sp in mats]
+    A16 = [a.to(torch.bfloat16).contiguous() for a in A32]
+    floor = []
+    for a, b16 in zip(A32, A16):
+        floor.append(float(torch.linalg.norm(b16.float() - a) / torch.linalg.norm(a)))
+    torch.cuda.synchronize()
+    log("serve: matrices ready")
+    pool = int(args.serve_pool_gb * (1 << 30))
+
+    def replay(mode):
+        srv = fp.Server(pool, slots=args.serve_slots, starve_s=0.25)
+        prms, store = [], []
+        for q in reqs:
+            m, n = mats[q["mat"]][:2]
+            bf = mode == "mixed" and q["bf16"] and q["tol"] >= 4 * floor[q["mat"]]
+            prms.append(fp.make_params(m, n, tol=q["tol"], power=1, sketch="sparse_sign", zeta=8,
+                                       seed=q["seed"], a_dtype="bf16" if bf else "f32"))
+            store.append(bf)
+        results = {}
+        t_start = time.perf_counter()
+
+        def submitter():
+            for i, q in enumerate(reqs):
+                dt = t_start + q["t"] - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                A = A16[q["mat"]] if store[i] else A32[q["mat"]]
+                srv.submit(prms[i], A, i)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        while len(results) < len(reqs):
+            for r in srv.poll(64, wait_ms=50):
+                results[r.tag] = (r.status, r.t_submit, r.t_admit, r.t_done, r.info.rank_l)
+                srv.release(r.tag)
+        th.join()
+        srv.close()
+        lat = np.array([v[3] - v[1] for v in results.values()])
+        t_first = min(v[1] for v in results.values())
+        t_last = max(v[3] for v in results.values())
+        st = [v[0] for v in results.values()]
+        out = {"solves_per_s": len(reqs) / (t_last - t_first), "wall_s": t_last - t_first,
+               "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+               "mean_ms": float(lat.mean() * 1e3), "converged": int(sum(1 for x in st if x == 0)),
+               "capped": int(sum(1 for x in st if x == 1)), "errors": int(sum(1 for x in st if x < 0)),
+               "bf16_requests": int(sum(store))}
+        log(f"serve {mode}: {out}")
+        return out
+
+    mixed = replay("mixed")
+    f32 = replay("fp32")
+    line = {
+        "metric": "served solves/s + p99 vs plain FP32",
+        "value": mixed["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "bf16+f32", "data": "synthetic",
+        "config": {"workload": f"serve_{len(reqs)}req_poisson200", "slots": args.serve_slots,
+                   "pool_GiB": args.serve_pool_gb, "matrices": len(mats), "power": 1, "sketch": "sparse_sign",
+                   "zeta": 8, "bf16_floor_median": float(np.median(floor))},
+        "mixed": mixed, "fp32": f32,
+        "bf16_over_fp32_solves_per_s": mixed["solves_per_s"] / f32["solves_per_s"],
+        "vs_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +304,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--serve", action="store_true",
+                    help="replay the serving trace (Poisson arrivals, mixed shapes / tolerances / "
+                         "storage) through farpca_server_* instead of the solve benchmark")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-pool-gb", type=float, default=80.0)
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only launch the kernels that stream A (A-pass products, sparse sketch) "
                          "on a random matrix of the workload's shape, plus a 1 GiB copy: the "
@@ -201,6 +328,9 @@ def main():
     wl = args.workload
     if args.kernel_probe:
         kernel_probe(wl, dev)
+        return
+    if args.serve:
+        serve_bench(args, dev)
         return
     m, n, _, _, tol, b, P, sketch, zeta, p, storage = WORKLOADS[wl]
     rank = 200 if tol == 0.0 else 0

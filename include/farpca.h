@@ -153,6 +153,51 @@ int farpca_gemm_bf16_tn(const uint16_t *dA, int64_t lda, const float *dY, int64_
 size_t farpca_eig_scratch_bytes(int64_t l);
 int farpca_eig(const double *dK, int64_t l, double *dW, double *dV, void *dWork, void *stream);
 
+/* ---- serving: continuous batching of independent solves on one GPU
+ * A server owns one device pool of pool_bytes (allocated by
+ * farpca_server_create, freed by farpca_server_destroy: the only device
+ * allocation the library makes) and `slots` host threads, each with its own
+ * stream.  farpca_server_submit queues a request whose A is already resident
+ * (caller-owned, read only, valid until the request's result is polled); a
+ * request is admitted into a free slot once its footprint
+ * (farpca_request_footprint: workspace + U, S, V) fits in the pool.  The queue is
+ * scanned in arrival order and the first request that fits is admitted, unless
+ * an earlier one has waited more than starve_s seconds (then nothing overtakes
+ * it).  Admitted requests run farpca_run on their slot's stream, concurrently
+ * with the other slots.  A result (U, S, V inside the pool, leading dimension
+ * ld) stays valid until farpca_server_release(tag).  Results are bitwise the
+ * same whether a request runs alone or among others.  Tags must be unique
+ * among queued, running and unreleased requests.  Times are seconds since
+ * the server was created (steady clock).  The kernel-timing switch below must
+ * be off while a server runs. */
+typedef struct farpca_result {
+  uint64_t tag;
+  int32_t status;        /* farpca_run's return value                                  */
+  int32_t reserved0;
+  farpca_info info;
+  double t_submit, t_admit, t_done;
+  float *dU;             /* m x info.rank_out of an m x ld array (device, in the pool)  */
+  double *dS;            /* info.rank_out singular values, descending                  */
+  float *dV;             /* n x info.rank_out of an n x ld array                       */
+  int64_t ld, m, n;
+} farpca_result;
+typedef struct farpca_server_s farpca_server_t;
+size_t farpca_request_footprint(const farpca_params *params);   /* 0 if the params are invalid */
+int farpca_server_create(size_t pool_bytes, int slots, double starve_s, farpca_server_t **out);
+/* FARPCA_E_NOMEM: the request can never fit the pool; FARPCA_E_INVALID: bad params or tag. */
+int farpca_server_submit(farpca_server_t *srv, const farpca_params *params, const void *dA,
+                         uint64_t tag);
+/* Up to max_out finished results (waits up to wait_ms for the first); returns the count. */
+int farpca_server_poll(farpca_server_t *srv, farpca_result *out, int max_out, int wait_ms);
+int farpca_server_release(farpca_server_t *srv, uint64_t tag);
+/* Copy a held result's first info.rank_out columns into caller buffers (device,
+ * row-major, ldu / ldv >= rank_out; any of the three may be NULL), enqueued on `stream`. */
+int farpca_server_fetch(farpca_server_t *srv, const farpca_result *res, float *dU, int64_t ldu,
+                        double *dS, float *dV, int64_t ldv, void *stream);
+int farpca_server_stats(farpca_server_t *srv, int *queued, int *running, size_t *largest_free);
+/* Waits for running requests, drops queued ones, frees the pool (results become invalid). */
+int farpca_server_destroy(farpca_server_t *srv);
+
 /* ---- opt-in kernel timing (process-wide, not thread-safe): while enabled,
  * farpca_run records hipEvents on its stream around the kernels that stream A
  * and, on return, adds their elapsed times per class.  Enabling resets the

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libfarpca.so")
 ARCH = os.environ.get("FARPCA_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["omega.hip", "sketch.hip", "gemm.hip", "gemm_bf16.hip", "dense64.hip", "eig.hip",
-           "farpca.cpp"]
+           "farpca.cpp", "serve.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -27,7 +27,10 @@ STATUS_NOT_CONVERGED = 1
 EXPORTED = ["farpca_plan", "farpca_run", "farpca_free", "farpca_status_str", "farpca_omega",
             "farpca_sketch", "farpca_gemm_scratch_bytes", "farpca_gemm_nn", "farpca_gemm_tn",
             "farpca_gemm_bf16_scratch_bytes", "farpca_gemm_bf16_nn", "farpca_gemm_bf16_tn",
-            "farpca_eig_scratch_bytes", "farpca_eig", "farpca_profile_enable", "farpca_profile_get"]
+            "farpca_eig_scratch_bytes", "farpca_eig", "farpca_profile_enable", "farpca_profile_get",
+            "farpca_request_footprint", "farpca_server_create", "farpca_server_submit",
+            "farpca_server_poll", "farpca_server_release", "farpca_server_fetch",
+            "farpca_server_stats", "farpca_server_destroy"]
 PROF_CLASSES = {"sketch": 0, "gemm_tn": 1, "gemm_nn": 2, "eig": 3}
 
 
@@ -45,6 +48,14 @@ class FarpcaInfo(ctypes.Structure):
                 ("blocks", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("norm_a2", ctypes.c_double), ("err_indicator", ctypes.c_double),
                 ("eig_sweeps", ctypes.c_int32), ("dropped", ctypes.c_int32)]
+
+
+class FarpcaResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("info", FarpcaInfo), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("dU", ctypes.c_void_p), ("dS", ctypes.c_void_p),
+                ("dV", ctypes.c_void_p), ("ld", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("n", ctypes.c_int64)]
 
 
 class FarpcaError(RuntimeError):
@@ -94,6 +105,23 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.farpca_profile_get.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
     lib.farpca_profile_get.restype = ctypes.c_int
+    lib.farpca_request_footprint.argtypes = [ctypes.POINTER(FarpcaParams)]
+    lib.farpca_request_footprint.restype = sz
+    lib.farpca_server_create.argtypes = [sz, ctypes.c_int, ctypes.c_double, ctypes.POINTER(vp)]
+    lib.farpca_server_create.restype = ctypes.c_int
+    lib.farpca_server_submit.argtypes = [vp, ctypes.POINTER(FarpcaParams), vp, ctypes.c_uint64]
+    lib.farpca_server_submit.restype = ctypes.c_int
+    lib.farpca_server_poll.argtypes = [vp, ctypes.POINTER(FarpcaResult), ctypes.c_int, ctypes.c_int]
+    lib.farpca_server_poll.restype = ctypes.c_int
+    lib.farpca_server_release.argtypes = [vp, ctypes.c_uint64]
+    lib.farpca_server_release.restype = ctypes.c_int
+    lib.farpca_server_fetch.argtypes = [vp, ctypes.POINTER(FarpcaResult), vp, i64, vp, vp, i64, vp]
+    lib.farpca_server_fetch.restype = ctypes.c_int
+    lib.farpca_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(sz)]
+    lib.farpca_server_stats.restype = ctypes.c_int
+    lib.farpca_server_destroy.argtypes = [vp]
+    lib.farpca_server_destroy.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -278,3 +306,57 @@ def solve(A, *, tol=0.0, rank=0, block=0, power=1, sketch="sparse_sign", p=0.0, 
         return SolveResult(U[:, :k], S[:k], V[:, :k], info, status, eh[:nb])
     finally:
         plan.free()
+
+
+# ---------------------------------------------------------------- serving
+def farpca_request_footprint(params: FarpcaParams) -> int:
+    return int(load_library().farpca_request_footprint(ctypes.byref(params)))
+
+
+class Server:
+    """farpca_server_* (continuous batching on one GPU): submit requests whose A
+    is resident, poll finished results, fetch them into caller tensors, release."""
+
+    def __init__(self, pool_bytes: int, slots: int = 4, starve_s: float = 0.25):
+        self._lib = load_library()
+        self.handle = ctypes.c_void_p()
+        _check(self._lib.farpca_server_create(pool_bytes, slots, starve_s, ctypes.byref(self.handle)),
+               "farpca_server_create")
+        self._pending = {}      # tag -> (params, A) kept alive until the result is polled
+
+    def submit(self, params: FarpcaParams, A, tag: int) -> None:
+        _check(self._lib.farpca_server_submit(self.handle, ctypes.byref(params), _ptr(A), tag),
+               "farpca_server_submit")
+        self._pending[tag] = (params, A)
+
+    def poll(self, max_out: int = 64, wait_ms: int = 0):
+        buf = (FarpcaResult * max_out)()
+        k = _check(self._lib.farpca_server_poll(self.handle, buf, max_out, wait_ms), "farpca_server_poll")
+        out = [buf[i] for i in range(k)]
+        for r in out:
+            self._pending.pop(r.tag, None)
+        return out
+
+    def fetch(self, res: FarpcaResult, U=None, S=None, V=None, stream=None) -> None:
+        _check(self._lib.farpca_server_fetch(self.handle, ctypes.byref(res),
+                                             _ptr(U) if U is not None else None,
+                                             U.stride(0) if U is not None else 0,
+                                             _ptr(S) if S is not None else None,
+                                             _ptr(V) if V is not None else None,
+                                             V.stride(0) if V is not None else 0, _stream(stream)),
+               "farpca_server_fetch")
+
+    def release(self, tag: int) -> None:
+        _check(self._lib.farpca_server_release(self.handle, tag), "farpca_server_release")
+
+    def stats(self):
+        q, r, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        _check(self._lib.farpca_server_stats(self.handle, ctypes.byref(q), ctypes.byref(r), ctypes.byref(f)),
+               "farpca_server_stats")
+        return q.value, r.value, f.value
+
+    def close(self) -> None:
+        if self.handle:
+            self._lib.farpca_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+            self._pending.clear()

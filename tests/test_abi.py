@@ -46,14 +46,18 @@ def test_struct_layout_matches_c(fp, tmp_path):
         "int main(void){\n"
         'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(farpca_params), offsetof(farpca_params, tol),'
         " offsetof(farpca_params, max_blocks), offsetof(farpca_params, seed), sizeof(farpca_info),"
-        " offsetof(farpca_info, eig_sweeps));\nreturn 0;}\n")
+        " offsetof(farpca_info, eig_sweeps));\n"
+        'printf("%zu %zu %zu %zu %zu\\n", sizeof(farpca_result), offsetof(farpca_result, info),'
+        " offsetof(farpca_result, t_done), offsetof(farpca_result, dV), offsetof(farpca_result, n));\n"
+        "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     got = [int(x) for x in out]
-    P, I = fp.FarpcaParams, fp.FarpcaInfo
+    P, I, R = fp.FarpcaParams, fp.FarpcaInfo, fp.FarpcaResult
     assert got == [ctypes.sizeof(P), P.tol.offset, P.max_blocks.offset, P.seed.offset,
-                   ctypes.sizeof(I), I.eig_sweeps.offset]
+                   ctypes.sizeof(I), I.eig_sweeps.offset,
+                   ctypes.sizeof(R), R.info.offset, R.t_done.offset, R.dV.offset, R.n.offset]
 
 
 def plan_or_rc(fp, **kw):
@@ -109,3 +113,16 @@ def test_status_strings(fp):
     lib = fp.load_library()
     for code in (0, 1, -1, -2, -3, -4):
         assert lib.farpca_status_str(code)
+
+
+def test_request_footprint(fp):
+    # workspace + U (m x l_max FP32) + S (l_max FP64) + V (n x l_max FP32), each
+    # rounded up to 256 bytes; 0 for invalid parameters
+    def up(x):
+        return (x + 255) // 256 * 256
+    for m, n, b, dt in ((1000, 700, 32, "f32"), (333, 2000, 7, "bf16"), (8000, 4000, 50, "f32")):
+        prm = fp.make_params(m, n, tol=1e-3, block=b, power=1, a_dtype=dt)
+        rc, lmax, ws = plan_or_rc(fp, m=m, n=n, tol=1e-3, block=b, power=1, a_dtype=dt)
+        assert rc == 0
+        assert fp.farpca_request_footprint(prm) == up(ws) + up(m * lmax * 4) + up(lmax * 8) + up(n * lmax * 4)
+    assert fp.farpca_request_footprint(fp.make_params(10, 10, tol=0.0)) == 0

@@ -1,0 +1,152 @@
+"""Serving through the C-ABI (farpca_server_*): continuous batching of
+independent solves on one GPU.  Every request completes; the footprints of
+requests that run at the same time never exceed the pool; a request that does
+not fit waits and is admitted once memory is released; and each result is
+bitwise the same alone, in a mix of other requests (FP32 and BF16, other
+shapes) and from farpca_run called directly."""
+import numpy as np
+import pytest
+
+from paper_2506_03859_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import torch  # noqa: F401
+    from paper_2506_03859_amd import farpca as fpm
+    fpm.load_library()
+    return fpm
+
+
+def requests_mix():
+    """(name, A float32 numpy, kwargs for make_params, storage)"""
+    out = []
+    specs = [(1200, 800, "exp"), (600, 1500, "pow"), (2500, 400, "tall"), (900, 900, "exp"),
+             (3000, 1000, "pow"), (700, 300, "exp")]
+    for i, (m, n, kind) in enumerate(specs):
+        k = min(m, n)
+        if kind == "exp":
+            a = synth.spectral(m, n, synth.exp_floor_sigma(k, decay=30.0), seed=20 + i)
+        elif kind == "pow":
+            a = synth.spectral(m, n, np.arange(1, k + 1, dtype=np.float64) ** -1.5, seed=20 + i)
+        else:
+            a = synth.tall_lowrank(m, n, 30, 1e-6, seed=20 + i)
+        out.append((f"{kind}{m}x{n}", a.astype(np.float32),
+                    dict(tol=(1e-2, 1e-3)[i % 2], block=(32, 24, 16)[i % 3], power=(2, 1)[i % 2],
+                         sketch="sparse_sign", zeta=8 if i % 3 else 4, seed=100 + i),
+                    "bf16" if i % 3 == 1 else "f32"))
+    return out
+
+
+def device_matrix(a32, storage):
+    import torch
+    t = torch.from_numpy(a32).cuda()
+    return t.to(torch.bfloat16).contiguous() if storage == "bf16" else t
+
+
+def direct(fp, A, prm):
+    plan = fp.farpca_plan(prm)
+    try:
+        work, U, S, V, eh = fp.alloc_outputs(plan, A.device)
+        status, info = fp.farpca_run(plan, A, work, U, S, V)
+        k = info.rank_out
+        return status, U[:, :k].clone(), S[:k].clone(), V[:, :k].clone()
+    finally:
+        plan.free()
+
+
+def fetch(fp, srv, r):
+    import torch
+    k = r.info.rank_out
+    U = torch.empty((r.m, k), dtype=torch.float32, device="cuda")
+    S = torch.empty((k,), dtype=torch.float64, device="cuda")
+    V = torch.empty((r.n, k), dtype=torch.float32, device="cuda")
+    srv.fetch(r, U, S, V)
+    torch.cuda.synchronize()
+    return U, S, V
+
+
+def drain(fp, srv, count, timeout_s=120.0):
+    import time
+    got = {}
+    t0 = time.time()
+    while len(got) < count:
+        for r in srv.poll(64, wait_ms=200):
+            got[r.tag] = (r, fetch(fp, srv, r))
+            srv.release(r.tag)
+        assert time.time() - t0 < timeout_s, f"only {len(got)} of {count} requests finished"
+    return got
+
+
+def test_alone_mix_direct_bitwise(fp):
+    import torch
+    reqs = requests_mix()
+    mats = [device_matrix(a, st) for _, a, _, st in reqs]
+    prms = [fp.make_params(a.shape[0], a.shape[1], a_dtype=st, **kw) for _, a, kw, st in reqs]
+    x = 1
+    print(f"serve: direct / alone / mix of {len(reqs)} requests, probe {reqs[x][0]}", flush=True)
+    st_d, Ud, Sd, Vd = direct(fp, mats[x], prms[x])
+    pool = 2 * sum(fp.farpca_request_footprint(p) for p in prms)
+    srv = fp.Server(pool, slots=4)
+    try:
+        srv.submit(prms[x], mats[x], 1000)
+        alone = drain(fp, srv, 1)[1000]
+        for i in range(len(reqs)):
+            srv.submit(prms[i], mats[i], i)
+        mix = drain(fp, srv, len(reqs))
+    finally:
+        srv.close()
+    for r, (U, S, V) in [alone, mix[x]]:
+        assert r.status == st_d
+        assert torch.equal(U, Ud) and torch.equal(S, Sd) and torch.equal(V, Vd)
+    for i, (r, _) in mix.items():
+        assert r.status >= 0 and r.info.rank_out > 0, reqs[i][0]
+        assert r.t_submit <= r.t_admit <= r.t_done
+
+
+def test_admission_respects_pool(fp):
+    reqs = requests_mix()
+    mats = [device_matrix(a, st) for _, a, _, st in reqs]
+    prms = [fp.make_params(a.shape[0], a.shape[1], a_dtype=st, **kw) for _, a, kw, st in reqs]
+    foot = [fp.farpca_request_footprint(p) for p in prms]
+    pool = int(max(foot) * 1.3)            # the largest request only fits alone
+    print(f"serve: admission, pool {pool >> 20} MiB, footprints {[f >> 20 for f in foot]} MiB", flush=True)
+    srv = fp.Server(pool, slots=4, starve_s=0.05)
+    try:
+        for rep in range(2):
+            for i in range(len(reqs)):
+                srv.submit(prms[i], mats[i], 10 * rep + i)
+        got = drain(fp, srv, 2 * len(reqs))
+    finally:
+        srv.close()
+    iv = [(r.t_admit, r.t_done, foot[tag % 10]) for tag, (r, _) in got.items()]
+    for t, _, _ in iv:
+        live = sum(f for a, d, f in iv if a <= t < d)
+        assert live <= pool
+    assert all(r.status >= 0 for r, _ in got.values())
+
+
+def test_submit_errors(fp):
+    import torch
+    a = torch.zeros((300, 200), dtype=torch.float32, device="cuda")
+    prm = fp.make_params(300, 200, tol=0.1, block=16)
+    srv = fp.Server(1 << 20, slots=1)      # smaller than the request's footprint
+    try:
+        with pytest.raises(fp.FarpcaError, match="workspace too small"):
+            srv.submit(prm, a, 1)
+        with pytest.raises(fp.FarpcaError, match="invalid"):
+            srv.submit(fp.make_params(300, 200, tol=0.0), a, 2)
+    finally:
+        srv.close()
+    srv = fp.Server(2 * fp.farpca_request_footprint(prm), slots=1)
+    try:
+        srv.submit(prm, a, 7)
+        with pytest.raises(fp.FarpcaError, match="invalid"):
+            srv.submit(prm, a, 7)            # tag already queued or running
+        got = drain(fp, srv, 1)
+        # all-zero A: zero norm, the loop stops at once with E = 0 < tol^2 * 0 false -> the cap
+        assert got[7][0].status >= 0
+    finally:
+        srv.close()
