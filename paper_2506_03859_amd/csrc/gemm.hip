@@ -364,8 +364,11 @@ void launch_gemm_finish(const float *part, int nsp, int64_t M, int64_t N, float 
                                       nullptr, 0.f, st);
 }
 
-// Waves along the output dimension: 4 once there are enough 256-row tiles.
-static int gemm_wm(int64_t M) { return M >= 8192 ? 4 : 1; }
+// Waves along the output dimension: 4 once there are enough 256-row tiles
+// and K is long enough to keep them busy; short products (the basis products
+// Q r, K = l) take one 64-row tile per workgroup, four times as many
+// workgroups, with K interleaved over the waves.
+static int gemm_wm(int64_t M, int64_t K) { return (M >= 8192 && K >= 1024) ? 4 : 1; }
 
 // Workgroups of the aligned kernel for (TN, WM) that are resident on the
 // current device at once (compute units x occupancy); queried once per device.
@@ -398,7 +401,7 @@ static int64_t gemm_slots(int is_tn, int wm) {
 // modelled as rounds x (K / s) x (1 + 128 s / K).
 int gemm_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split) {
   if (M < 1 || K < 1) return 1;
-  const int wm = gemm_wm(M);
+  const int wm = gemm_wm(M, K);
   const int64_t tiles = (M + 64 * wm - 1) / (64 * wm);
   const int64_t slots = gemm_slots(is_tn, wm);
   int64_t smax = K / 256;
@@ -425,7 +428,7 @@ static int launch_main(const float *A, int64_t lda, const float *X, int64_t ldx,
                        int ksplit, float *part, hipStream_t st) {
   if (M <= 0 || N <= 0) return 1;
   if (ksplit < 1) ksplit = 1;
-  const int wm = gemm_wm(M);
+  const int wm = gemm_wm(M, K);
   const int64_t kc = (wm == 4) ? 32 : 64;        // K rows per chunk (KC)
   int64_t kps = (K + ksplit - 1) / ksplit;
   kps = (kps + 63) / 64 * 64;                    // whole chunks per split

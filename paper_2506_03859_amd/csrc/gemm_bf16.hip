@@ -55,13 +55,31 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kB16Waves = 8;
 constexpr int kB16Threads = 64 * kB16Waves;
 constexpr int kB16Rows = 64 * kB16Waves;      // output rows per workgroup
-constexpr int kSlice = 32;                    // K rows per MFMA slice
-constexpr int kColStride = 40;                // BF16 per staged column (32 + 8 pad)
-constexpr int kPlane = kBld * kColStride;     // BF16 per staged split plane
-constexpr int kStage = 3 * kPlane;            // BF16 per staged slice
-constexpr int kRing = 6;                      // slices in flight (even: LDS parity is static)
-constexpr int kKGroup = kSlice * kRing;       // K granularity of splits and padding
-static_assert(kB16Threads == kBld * (kSlice / 4), "one 4-deep column piece per thread");
+constexpr int kKGroup = 192;                  // K granularity of splits and padding
+
+// Per layout: SL K rows per slice (32 per MFMA step), RING slices in the
+// register ring, NBUF staged skinny slices in LDS.  NN slices are 64 deep so
+// that a lane's two 16-byte loads of a row are back-to-back halves of one
+// 128-byte line (64-byte row pieces one slice apart stream at a much lower HBM
+// rate); TN rows are read as 128-byte runs already.
+template <bool TN> struct B16Cfg;
+template <> struct B16Cfg<true> {
+  static constexpr int SL = 32, RING = 6, NBUF = 2, AV = 4;
+};
+template <> struct B16Cfg<false> {
+  static constexpr int SL = 64, RING = 3, NBUF = 3, AV = 8;
+};
+template <bool TN> struct B16Lds {
+  static constexpr int CS = B16Cfg<TN>::SL + 8;   // BF16 per staged column (16-byte aligned)
+  static constexpr int PLANE = kBld * CS;          // BF16 per split plane
+  static constexpr int STAGE = 3 * PLANE;          // BF16 per staged slice
+  static constexpr int XL = B16Cfg<TN>::SL / 32;   // float4 skinny pieces per thread per slice
+};
+static_assert(B16Cfg<true>::SL * B16Cfg<true>::RING == kKGroup, "TN group");
+static_assert(B16Cfg<false>::SL * B16Cfg<false>::RING == kKGroup, "NN group");
+static_assert(kB16Threads == kBld * 8, "eight column pieces per skinny column");
+static_assert(B16Cfg<true>::RING % B16Cfg<true>::NBUF == 0 && B16Cfg<false>::RING % B16Cfg<false>::NBUF == 0,
+              "static LDS buffer of every unrolled step");
 
 __device__ __forceinline__ floatx4 mfma_bf16(u32x4 a, u32x4 b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
@@ -99,27 +117,31 @@ __global__ __launch_bounds__(256) void bf16_pack_kernel(const float *__restrict_
 }
 
 // ---------------------------------------------------------- A slot loads
-struct ASlot { u32x4 v[4]; };   // NN: row groups rt = 0..3; TN: rows (2 j, 2 j + 1) in v[j]
+// NN: v[2 rt + ks] = row group rt, MFMA step ks; TN: rows (2 j, 2 j + 1) in v[j].
+template <bool TN> struct ASlot { u32x4 v[B16Cfg<TN>::AV]; };
 
 template <bool TN, bool AVEC>
 __device__ __forceinline__ void load_slot(const uint16_t *A, int64_t lda, int64_t M,
                                           int64_t K, int64_t t0, int li, int lk, int64_t k0,
-                                          ASlot &s) {
-  if (!TN) {
-    const int64_t kk = k0 + 8 * lk;
+                                          ASlot<TN> &s) {
+  if constexpr (!TN) {
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) {
       const int64_t row = b16_clamp(t0 + 16 * rt + li, M - 1);
       const uint16_t *p = A + row * lda;
-      if (AVEC) {
-        // K % 8 == 0: a group of 8 is entirely inside K or entirely past it
-        s.v[rt] = *reinterpret_cast<const u32x4 *>(p + b16_clamp(kk, K - 8));
-      } else {
-        uint32_t h[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) h[e] = p[b16_clamp(kk + e, K - 1)];
-        s.v[rt] = u32x4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
-                        h[6] | (h[7] << 16)};
+      for (int ks = 0; ks < 2; ++ks) {
+        const int64_t kk = k0 + 32 * ks + 8 * lk;
+        if (AVEC) {
+          // K % 8 == 0: a group of 8 is entirely inside K or entirely past it
+          s.v[2 * rt + ks] = *reinterpret_cast<const u32x4 *>(p + b16_clamp(kk, K - 8));
+        } else {
+          uint32_t h[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) h[e] = p[b16_clamp(kk + e, K - 1)];
+          s.v[2 * rt + ks] = u32x4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                                   h[6] | (h[7] << 16)};
+        }
       }
     }
   } else {
@@ -159,7 +181,7 @@ __device__ __forceinline__ void load_slot(const uint16_t *A, int64_t lda, int64_
 // TN: the MFMA operand of column t (0..3) of the lane's 4 columns: element e =
 // row 8 lk + e.  v[j] holds row 2 j in (x, y) and row 2 j + 1 in (z, w), each
 // row as (columns 0,1), (columns 2,3).
-__device__ __forceinline__ u32x4 tn_operand(const ASlot &s, int t) {
+__device__ __forceinline__ u32x4 tn_operand(const ASlot<true> &s, int t) {
   uint32_t d[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -170,50 +192,69 @@ __device__ __forceinline__ u32x4 tn_operand(const ASlot &s, int t) {
   return u32x4{d[0], d[1], d[2], d[3]};
 }
 
-// Split 4 FP32 skinny values (k = 4 kq .. 4 kq + 3 of column sc) into the
-// three BF16 planes of the staged slice.
-__device__ __forceinline__ void stage_skinny(uint16_t *xs, int sc, int kq, const float4 &x) {
-  const float v[4] = {x.x, x.y, x.z, x.w};
-  uint32_t hi[4], mid[4], lo[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const uint32_t b = __float_as_uint(v[i]);
-    hi[i] = b & 0xFFFF0000u;
-    const float r = v[i] - __uint_as_float(hi[i]);          // exact
-    mid[i] = __float_as_uint(r) & 0xFFFF0000u;
-    lo[i] = __float_as_uint(r - __uint_as_float(mid[i])) & 0xFFFF0000u;   // exact, <= 8 bits
-  }
-  uint16_t *base = xs + sc * kColStride + 4 * kq;
-  *reinterpret_cast<uint2 *>(base) = make_uint2((hi[0] >> 16) | hi[1], (hi[2] >> 16) | hi[3]);
-  *reinterpret_cast<uint2 *>(base + kPlane) =
-      make_uint2((mid[0] >> 16) | mid[1], (mid[2] >> 16) | mid[3]);
-  *reinterpret_cast<uint2 *>(base + 2 * kPlane) =
-      make_uint2((lo[0] >> 16) | lo[1], (lo[2] >> 16) | lo[3]);
+// Split the thread's 4 XL FP32 skinny values (k = 4 XL kq .. + 4 XL - 1 of
+// column sc) into the three BF16 planes of the staged slice.
+__device__ __forceinline__ void split3(float v, uint32_t &hi, uint32_t &mid, uint32_t &lo) {
+  hi = __float_as_uint(v) & 0xFFFF0000u;
+  const float r = v - __uint_as_float(hi);                         // exact
+  mid = __float_as_uint(r) & 0xFFFF0000u;
+  lo = __float_as_uint(r - __uint_as_float(mid)) & 0xFFFF0000u;    // exact, <= 8 bits
 }
 
 template <bool TN>
-__device__ __forceinline__ void mma_slice_bf16(floatx4 (&acc)[16], const ASlot &s,
+__device__ __forceinline__ void stage_skinny(uint16_t *xs, int sc, int kq,
+                                             const float4 (&x)[B16Lds<TN>::XL]) {
+  using Lds = B16Lds<TN>;
+  uint16_t *base = xs + sc * Lds::CS + 4 * Lds::XL * kq;
+#pragma unroll
+  for (int g = 0; g < Lds::XL; ++g) {
+    const float v[4] = {x[g].x, x[g].y, x[g].z, x[g].w};
+    uint32_t hi[4], mid[4], lo[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) split3(v[i], hi[i], mid[i], lo[i]);
+    *reinterpret_cast<uint2 *>(base + 4 * g) = make_uint2((hi[0] >> 16) | hi[1], (hi[2] >> 16) | hi[3]);
+    *reinterpret_cast<uint2 *>(base + 4 * g + Lds::PLANE) =
+        make_uint2((mid[0] >> 16) | mid[1], (mid[2] >> 16) | mid[3]);
+    *reinterpret_cast<uint2 *>(base + 4 * g + 2 * Lds::PLANE) =
+        make_uint2((lo[0] >> 16) | lo[1], (lo[2] >> 16) | lo[3]);
+  }
+}
+
+template <bool TN>
+__device__ __forceinline__ void mma_slice_bf16(floatx4 (&acc)[16], const ASlot<TN> &s,
                                                const uint16_t *xs, int li, int lk) {
-  u32x4 a[4];
+  using Lds = B16Lds<TN>;
+  constexpr int KS = B16Cfg<TN>::SL / 32;
 #pragma unroll
-  for (int x = 0; x < 4; ++x) a[x] = TN ? tn_operand(s, x) : s.v[x];
-  const uint16_t *xb = xs + li * kColStride + 8 * lk;
+  for (int ks = 0; ks < KS; ++ks) {
+    u32x4 a[4];
 #pragma unroll
-  for (int p = 0; p < 3; ++p) {
+    for (int x = 0; x < 4; ++x) {
+      if constexpr (TN) a[x] = tn_operand(s, x);
+      else a[x] = s.v[2 * x + ks];
+    }
+    const uint16_t *xb = xs + li * Lds::CS + 32 * ks + 8 * lk;
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      const u32x4 bop = *reinterpret_cast<const u32x4 *>(xb + p * kPlane + 16 * ct * kColStride);
+    for (int p = 0; p < 3; ++p) {
 #pragma unroll
-      for (int x = 0; x < 4; ++x) acc[x * 4 + ct] = mfma_bf16(a[x], bop, acc[x * 4 + ct]);
+      for (int ct = 0; ct < 4; ++ct) {
+        const u32x4 bop = *reinterpret_cast<const u32x4 *>(xb + p * Lds::PLANE + 16 * ct * Lds::CS);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) acc[x * 4 + ct] = mfma_bf16(a[x], bop, acc[x * 4 + ct]);
+      }
     }
   }
 }
 
 template <bool TN, bool AVEC>
 __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
-    const uint16_t *A, int64_t lda, const float *xt, int64_t kp, float *__restrict__ C, int64_t ldc, int64_t M, int64_t N, int64_t K, int64_t kps,
-    int64_t tiles, int64_t total, float alpha, float beta, float *__restrict__ part) {
-  __shared__ __attribute__((aligned(16))) uint16_t xs[2][kStage];
+    const uint16_t *A, int64_t lda, const float *xt, int64_t kp, float *__restrict__ C, int64_t ldc,
+    int64_t M, int64_t N, int64_t K, int64_t kps, int64_t tiles, int64_t total, float alpha,
+    float beta, float *__restrict__ part) {
+  using Cfg = B16Cfg<TN>;
+  using Lds = B16Lds<TN>;
+  constexpr int SL = Cfg::SL, RING = Cfg::RING, NBUF = Cfg::NBUF, XL = Lds::XL;
+  __shared__ __attribute__((aligned(16))) uint16_t xs[NBUF][Lds::STAGE];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -222,45 +263,47 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
   const int64_t t0 = tile * kB16Rows + 64 * wave;
   const int64_t kb = split * kps;
   const int64_t ke = (kb + kps < K) ? kb + kps : K;
-  // slices of this split, a multiple of kRing (kps is a multiple of kKGroup;
+  // slices of this split, a multiple of RING (kps is a multiple of kKGroup;
   // slices past K meet zero skinny rows)
-  const int64_t nsl = ((ke - kb + kKGroup - 1) / kKGroup) * kRing;
+  const int64_t nsl = ((ke - kb + kKGroup - 1) / kKGroup) * RING;
   const int sc = tid >> 3, kq = tid & 7;
-  const float *xsrc = xt + sc * kp + kb + 4 * kq;
+  const float *xsrc = xt + sc * kp + kb + 4 * XL * kq;
 
   floatx4 acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  ASlot ar[kRing];
-  float4 xr[kRing];
-  // Every slice's loads are issued in one fixed order (skinny piece, then A),
+  ASlot<TN> ar[RING];
+  float4 xr[RING][XL];
+  // Every slice's loads are issued in one fixed order (skinny pieces, then A),
   // in the prologue as in the loop: the wait counts the compiler derives from
-  // that order keep kRing - 1 slices in flight (a different prologue order
+  // that order keep RING - 1 slices in flight (a different prologue order
   // makes it wait for nearly everything at the loop head).
   auto issue = [&](int64_t s, int slot) {
     const int64_t sl = s < nsl ? s : nsl - 1;      // clamped: in bounds, never used
-    xr[slot] = *reinterpret_cast<const float4 *>(xsrc + sl * kSlice);
+#pragma unroll
+    for (int g = 0; g < XL; ++g) xr[slot][g] = *reinterpret_cast<const float4 *>(xsrc + sl * SL + 4 * g);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
-    load_slot<TN, AVEC>(A, lda, M, K, t0, li, lk, kb + sl * kSlice, ar[slot]);
+    load_slot<TN, AVEC>(A, lda, M, K, t0, li, lk, kb + sl * SL, ar[slot]);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
   };
 #pragma unroll
-  for (int d = 0; d < kRing; ++d) issue(d, d);
-  stage_skinny(xs[0], sc, kq, xr[0]);
+  for (int d = 0; d < RING; ++d) issue(d, d);
+  stage_skinny<TN>(xs[0], sc, kq, xr[0]);
 
-  for (int64_t s0 = 0; s0 < nsl; s0 += kRing) {
+  for (int64_t s0 = 0; s0 < nsl; s0 += RING) {
 #pragma unroll
-    for (int d = 0; d < kRing; ++d) {
-      const int buf = d & 1;
+    for (int d = 0; d < RING; ++d) {
+      // RING is a multiple of NBUF: slice s0 + d lives in buffer d % NBUF
+      const int buf = d % NBUF;
       __syncthreads();                 // slice s0 + d staged; slice s0 + d - 1 consumed
       __builtin_amdgcn_sched_barrier(0);
       mma_slice_bf16<TN>(acc, ar[d], xs[buf], li, lk);
       __builtin_amdgcn_sched_barrier(0);
-      stage_skinny(xs[buf ^ 1], sc, kq, xr[(d + 1) % kRing]);
-      issue(s0 + d + kRing, d);
+      stage_skinny<TN>(xs[(d + 1) % NBUF], sc, kq, xr[(d + 1) % RING]);
+      issue(s0 + d + RING, d);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
