@@ -120,32 +120,30 @@ void launch_gram(const float *X, int64_t ldx, int64_t K, int b, double *part, do
                      nblk, b, G);
 }
 
-// ------------------------------------------- Cholesky factor and its inverse
-// G (kMaxBlock x kMaxBlock, FP64, valid b x b) = R^T R; the output is the
-// upper triangular W with X W = X R^{-1}: the orthonormal columns spanning X.
-// A column whose pivot after elimination falls to drop_rel * (its own
-// diagonal) or below is numerically dependent on the previous ones (for FP32
-// data the residual is rounding noise): it is dropped - its row of R is zero,
-// so it eliminates nothing later, and its column of W is zero, so that output
-// column is exactly zero.  flags[0] |= 1 when a column is dropped.  (The
-// method's Z^{-1} is read as the pseudo-inverse there.)
+// ------------------------------------------------------- Cholesky factor
+// G (kMaxBlock x kMaxBlock, FP64, valid b x b) = R^T R.  The output F holds R
+// strictly above the diagonal and F_jj = 1 / R_jj on it (zero below): what
+// the row-wise triangular solve X <- X R^{-1} needs.  A column whose pivot
+// after elimination falls to drop_rel * (its own diagonal) or below is
+// numerically dependent on the previous ones (for FP32 data the residual is
+// rounding noise): it is dropped - its row of R is zero, so it eliminates
+// nothing later, and F_jj = 0, so that output column is exactly zero.
+// flags[0] |= 1 when a column is dropped.  (The method's Z^{-1} is read as
+// the pseudo-inverse there.)
 //
-// One wave.  Factorisation: lane j holds column j of the working matrix in
-// registers; step k broadcasts the pivot and row k of R through LDS and
-// updates the trailing columns.  Inverse: with F = R off the diagonal and
-// F_jj = 1 / R_jj (0 for a dropped column), row r of W follows from
-// W[r][j] = F_jj (delta_rj - sum_{i<j} W[r][i] R[i][j]), lane r per row.
+// One wave: lane j holds column j of the working matrix in registers; step k
+// broadcasts the pivot and row k of R through LDS and updates the trailing
+// columns.
 __device__ __forceinline__ double bcast_f64(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
   return __hiloint2double(hi, lo);
 }
 
-__global__ __launch_bounds__(64) void chol_inv_kernel(const double *__restrict__ G, int b,
-                                                      double drop_rel, double *__restrict__ W,
-                                                      int *__restrict__ flags) {
+__global__ __launch_bounds__(64) void chol_kernel(const double *__restrict__ G, int b,
+                                                  double drop_rel, double *__restrict__ F,
+                                                  int *__restrict__ flags) {
   __shared__ double rk[kMaxBlock];
-  __shared__ double Rs[kMaxBlock * (kMaxBlock + 1)];
   const int j = threadIdx.x;
   double c[kMaxBlock];
 #pragma unroll
@@ -174,64 +172,92 @@ __global__ __launch_bounds__(64) void chol_inv_kernel(const double *__restrict__
     }
   }
   if (any_drop && j == 0) atomicOr(flags, 1);
-  // F into LDS: rows i <= j of column j (c[i] for i < j is R[i][j], c[j] is F_jj)
+  // c[i] for i < j is R[i][j], c[j] is F_jj; row i of F is written by the 64
+  // lanes together (coalesced)
 #pragma unroll
-  for (int i = 0; i < kMaxBlock; ++i) Rs[i * (kMaxBlock + 1) + j] = (i <= j && j < b) ? c[i] : 0.0;
-  __syncthreads();
-  const int r = j;
-  double w[kMaxBlock];
+  for (int i = 0; i < kMaxBlock; ++i) F[i * kMaxBlock + j] = (i <= j && j < b) ? c[i] : 0.0;
+}
+
+void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags, hipStream_t st) {
+  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(64), 0, st, G, b, drop_rel, F, flags);
+}
+
+// Y = X R^{-1} row by row: forward substitution y_c = F_cc (x_c - sum_{i<c}
+// y_i R_ic) in FP64, each value rounded once to FP32.  One wave per 64 rows:
+// the row tile is read coalesced into LDS (row stride 65 floats), each lane
+// solves its row from there with F transposed in LDS (column c contiguous,
+// stride 65 doubles: conflict-free staging), and the result leaves through
+// the same tile.  Columns >= b are not written.  Y may alias X (a tile is
+// read completely before any of it is written).
+constexpr int kTrsmRows = 64;
+__global__ __launch_bounds__(64) void trsm_rows_kernel(const float *__restrict__ X, int64_t ldx,
+                                                       int64_t K, int b, const double *__restrict__ Fg,
+                                                       float *__restrict__ Y, int64_t ldy, int vec) {
+  __shared__ double Ft[kMaxBlock * (kMaxBlock + 1)];     // Ft[c][i] = F[i][c]
+  __shared__ float xt[kTrsmRows * (kMaxBlock + 1)];
+  const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * kTrsmRows;
+  for (int e = t; e < kMaxBlock * kMaxBlock; e += 64)
+    Ft[(e % kMaxBlock) * (kMaxBlock + 1) + e / kMaxBlock] = Fg[e];
+  // tile in: instruction q covers rows 4 q + t / 16, columns 4 (t % 16) .. + 3
+#pragma unroll 4
+  for (int q = 0; q < kTrsmRows / 4; ++q) {
+    const int row = 4 * q + (t >> 4), c4 = 4 * (t & 15);
+    const int64_t gr = r0 + row;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (gr < K) {
+      const float *xr = X + gr * ldx + c4;
+      if (vec) {
+        const float4 u = *reinterpret_cast<const float4 *>(xr);
+        v[0] = u.x; v[1] = u.y; v[2] = u.z; v[3] = u.w;
+      } else {
 #pragma unroll
-  for (int jj = 0; jj < kMaxBlock; ++jj) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = 0; i < 4; ++i) v[i] = (c4 + i < b) ? xr[i] : 0.f;
+      }
+    }
 #pragma unroll
-    for (int i = 0; i < jj; ++i) s[i & 3] = fma(Rs[i * (kMaxBlock + 1) + jj], w[i], s[i & 3]);
-    const double d = ((r == jj) ? 1.0 : 0.0) - ((s[0] + s[1]) + (s[2] + s[3]));
-    w[jj] = Rs[jj * (kMaxBlock + 1) + jj] * d;
+    for (int i = 0; i < 4; ++i) xt[row * (kMaxBlock + 1) + c4 + i] = (c4 + i < b) ? v[i] : 0.f;
   }
   __syncthreads();
+  double y[kMaxBlock];
 #pragma unroll
-  for (int jj = 0; jj < kMaxBlock; ++jj) Rs[r * (kMaxBlock + 1) + jj] = w[jj];
-  __syncthreads();
-  for (int e = j; e < kMaxBlock * kMaxBlock; e += 64)
-    W[e] = Rs[(e / kMaxBlock) * (kMaxBlock + 1) + (e % kMaxBlock)];
-}
-
-void launch_chol(const double *G, int b, double drop_rel, double *W, int *flags, hipStream_t st) {
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(64), 0, st, G, b, drop_rel, W, flags);
-}
-
-// Y = X W for upper triangular W (kMaxBlock x kMaxBlock, FP64): FP64 sums of
-// the FP32 data, rounded once.  One row per thread (256 rows per workgroup);
-// W is staged transposed in LDS so that W[0..c][c] is contiguous.  Each thread
-// reads its whole row before writing it, so Y may alias X.
-__global__ __launch_bounds__(256) void trsm_rows_kernel(const float *__restrict__ X, int64_t ldx,
-                                                        int64_t K, int b, const double *__restrict__ Wg,
-                                                        float *__restrict__ Y, int64_t ldy) {
-  __shared__ double Wt[kMaxBlock * kMaxBlock];     // Wt[c][i] = W[i][c]
-  const int t = threadIdx.x;
-  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256) Wt[(e % kMaxBlock) * kMaxBlock + e / kMaxBlock] = Wg[e];
-  const int64_t row = (int64_t)blockIdx.x * 256 + t;
-  const bool valid = row < K;
-  double x[kMaxBlock];
-  const float *xr = X + (valid ? row : 0) * ldx;
-#pragma unroll
-  for (int i = 0; i < kMaxBlock; ++i) x[i] = (valid && i < b) ? (double)xr[i] : 0.0;
-  __syncthreads();
-  float *yr = Y + (valid ? row : 0) * ldy;
+  for (int c = 0; c < kMaxBlock; ++c) y[c] = (double)xt[t * (kMaxBlock + 1) + c];
 #pragma unroll
   for (int c = 0; c < kMaxBlock; ++c) {
     double s[4] = {0.0, 0.0, 0.0, 0.0};
+    const double *fc = Ft + c * (kMaxBlock + 1);
 #pragma unroll
-    for (int i = 0; i <= c; ++i) s[i & 3] = fma(x[i], Wt[c * kMaxBlock + i], s[i & 3]);
-    if (valid && c < b) yr[c] = (float)((s[0] + s[1]) + (s[2] + s[3]));
+    for (int i = 0; i < c; ++i) s[i & 3] = fma(y[i], fc[i], s[i & 3]);
+    y[c] = (y[c] - ((s[0] + s[1]) + (s[2] + s[3]))) * fc[c];
+  }
+  // own row only: no other lane reads it until the barrier
+#pragma unroll
+  for (int c = 0; c < kMaxBlock; ++c) xt[t * (kMaxBlock + 1) + c] = (float)y[c];
+  __syncthreads();
+#pragma unroll 4
+  for (int q = 0; q < kTrsmRows / 4; ++q) {
+    const int row = 4 * q + (t >> 4), c4 = 4 * (t & 15);
+    const int64_t gr = r0 + row;
+    if (gr >= K || c4 >= b) continue;
+    float *yr = Y + gr * ldy + c4;
+    const float *src = xt + row * (kMaxBlock + 1) + c4;
+    if (vec && c4 + 4 <= b) {
+      *reinterpret_cast<float4 *>(yr) = make_float4(src[0], src[1], src[2], src[3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (c4 + i < b) yr[i] = src[i];
+    }
   }
 }
 
-void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *W, float *Y,
+void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *F, float *Y,
                       int64_t ldy, hipStream_t st) {
   if (K <= 0) return;
-  hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, X, ldx, K,
-                     b, W, Y, ldy);
+  const int vec = (ldx % 4 == 0) && (ldy % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
+                  ((reinterpret_cast<uintptr_t>(Y) & 15) == 0) && b == kMaxBlock;
+  hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((K + kTrsmRows - 1) / kTrsmRows)), dim3(64), 0,
+                     st, X, ldx, K, b, F, Y, ldy, vec);
 }
 
 // ------------------------------------------------------------ setup pass

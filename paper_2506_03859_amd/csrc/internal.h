@@ -112,12 +112,12 @@ int gram_num_partials(int64_t K);
 int gram_max_partials();
 void launch_gram(const float *X, int64_t ldx, int64_t K, int b, double *part, double *G,
                  hipStream_t st);
-// Cholesky factor G = R^T R and W = R^{-1} (upper triangular, 64 x 64 FP64);
-// columns whose pivot is <= drop_rel * diagonal are dropped (zero row of R,
-// zero column of W); flags[0] |= 1 then.
-void launch_chol(const double *G, int b, double drop_rel, double *W, int *flags, hipStream_t st);
-// Y = X W row by row (FP64 sums; in place allowed).
-void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *W, float *Y,
+// Cholesky factor G = R^T R (64 x 64 FP64): F = R strictly above the
+// diagonal, 1 / R_jj on it.  Columns whose pivot is <= drop_rel * diagonal
+// are dropped (zero row of R, F_jj = 0); flags[0] |= 1 then.
+void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags, hipStream_t st);
+// Y = X R^{-1} row by row (forward substitution in FP64; in place allowed).
+void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *F, float *Y,
                       int64_t ldy, hipStream_t st);
 // Setup pass over A: partial sums of squares (FP64, per row block) and the
 // row sums (FP64, rowsum[i]); nonfinite flag.
