@@ -306,14 +306,15 @@ __global__ void bj_init_kernel(const double *__restrict__ K, int64_t l, int64_t 
 // method's blocks make K nearly block-diagonal) and store its eigenvectors as
 // the diagonal block V[I, I] of the starting basis.
 constexpr int kPre = 64;
-__global__ __launch_bounds__(256) void bj_pre_eig_kernel(const double *__restrict__ M, int64_t lp,
+constexpr int kPreThreads = 1024;
+__global__ __launch_bounds__(kPreThreads) void bj_pre_eig_kernel(const double *__restrict__ M, int64_t lp,
                                                          double *__restrict__ V) {
   __shared__ double a[kPre * kSmallLd];
   __shared__ double v[kPre * kSmallLd];
   __shared__ double fl;
   const int tid = threadIdx.x;
   const int64_t o = (int64_t)blockIdx.x * kPre;
-  for (int e = tid; e < kPre * kPre; e += 256) {
+  for (int e = tid; e < kPre * kPre; e += kPreThreads) {
     const int i = e / kPre, j = e % kPre;
     a[i * kSmallLd + j] = M[(o + i) * lp + o + j];
     v[i * kSmallLd + j] = (i == j) ? 1.0 : 0.0;
@@ -325,9 +326,9 @@ __global__ __launch_bounds__(256) void bj_pre_eig_kernel(const double *__restric
     fl = mx * kJacobiAbs;
   }
   __syncthreads();
-  jacobi_lds<kPre, kSmallLd, 256>(a, v, fl, kPreSweeps);
+  jacobi_lds<kPre, kSmallLd, kPreThreads>(a, v, fl, kPreSweeps);
   __syncthreads();
-  for (int e = tid; e < kPre * kPre; e += 256) {
+  for (int e = tid; e < kPre * kPre; e += kPreThreads) {
     const int i = e / kPre, j = e % kPre;
     V[(o + i) * lp + o + j] = v[i * kSmallLd + j];
   }
@@ -428,7 +429,7 @@ int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, hip
   const double abs_factor = kJacobiAbs;
   hipLaunchKernelGGL(bj_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, K, l, lp, M, V);
   const int npre = (int)(lp / kPre);
-  hipLaunchKernelGGL(bj_pre_eig_kernel, dim3(npre), dim3(256), 0, st, M, lp, V);
+  hipLaunchKernelGGL(bj_pre_eig_kernel, dim3(npre), dim3(kPreThreads), 0, st, M, lp, V);
   hipLaunchKernelGGL(bj_pre_rotate_kernel, dim3(npre, npre), dim3(256), 0, st, M, V, lp);
   int sweeps = 0;
   const int max_sweeps = 40;
