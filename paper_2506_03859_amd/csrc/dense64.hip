@@ -142,13 +142,36 @@ __device__ __forceinline__ double bcast_f64(double v, int lane) {
 
 __global__ __launch_bounds__(64) void chol_kernel(const double *__restrict__ G, int b,
                                                   double drop_rel, double *__restrict__ F,
-                                                  int *__restrict__ flags) {
+                                                  int *__restrict__ flags, double skip_tol,
+                                                  int *__restrict__ apply) {
   __shared__ double rk[kMaxBlock];
   const int j = threadIdx.x;
   double c[kMaxBlock];
 #pragma unroll
   for (int i = 0; i < kMaxBlock; ++i) c[i] = G[i * kMaxBlock + j];
   const double dg = G[j * kMaxBlock + j];
+  if (skip_tol > 0.0) {
+    // G of already orthonormal columns (a repeated pass): when every kept
+    // column (nonzero diagonal) is orthonormal to skip_tol, R = I and the
+    // solve is left out (apply[0] = 0)
+    double dev = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxBlock; ++i) {
+      const bool kept = j < b && i < b && dg != 0.0 && G[i * kMaxBlock + i] != 0.0;
+      const double e = kept ? fabs(c[i] - (i == j ? 1.0 : 0.0)) : 0.0;
+      dev = (e > dev || e != e) ? e : dev;              // NaN counts as a deviation
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(dev, off);
+      dev = (o > dev || o != o) ? o : dev;
+    }
+    const bool skip = dev <= skip_tol;                  // false for NaN
+    if (j == 0) apply[0] = skip ? 0 : 1;
+    if (skip) return;
+  } else if (apply && j == 0) {
+    apply[0] = 1;
+  }
   bool any_drop = false;
 #pragma unroll
   for (int k = 0; k < kMaxBlock; ++k) {
@@ -178,8 +201,9 @@ __global__ __launch_bounds__(64) void chol_kernel(const double *__restrict__ G, 
   for (int i = 0; i < kMaxBlock; ++i) F[i * kMaxBlock + j] = (i <= j && j < b) ? c[i] : 0.0;
 }
 
-void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags, hipStream_t st) {
-  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(64), 0, st, G, b, drop_rel, F, flags);
+void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags, double skip_tol,
+                 int *apply, hipStream_t st) {
+  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(64), 0, st, G, b, drop_rel, F, flags, skip_tol, apply);
 }
 
 // Y = X R^{-1} row by row: forward substitution y_c = F_cc (x_c - sum_{i<c}
@@ -192,9 +216,11 @@ void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags,
 constexpr int kTrsmRows = 64;
 __global__ __launch_bounds__(64) void trsm_rows_kernel(const float *__restrict__ X, int64_t ldx,
                                                        int64_t K, int b, const double *__restrict__ Fg,
-                                                       float *__restrict__ Y, int64_t ldy, int vec) {
+                                                       float *__restrict__ Y, int64_t ldy, int vec,
+                                                       const int *__restrict__ apply) {
   __shared__ double Ft[kMaxBlock * (kMaxBlock + 1)];     // Ft[c][i] = F[i][c]
   __shared__ float xt[kTrsmRows * (kMaxBlock + 1)];
+  if (apply && apply[0] == 0) return;                    // R = I: nothing to do (in place)
   const int t = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * kTrsmRows;
   for (int e = t; e < kMaxBlock * kMaxBlock; e += 64)
@@ -252,12 +278,12 @@ __global__ __launch_bounds__(64) void trsm_rows_kernel(const float *__restrict__
 }
 
 void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *F, float *Y,
-                      int64_t ldy, hipStream_t st) {
+                      int64_t ldy, const int *apply, hipStream_t st) {
   if (K <= 0) return;
   const int vec = (ldx % 4 == 0) && (ldy % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
                   ((reinterpret_cast<uintptr_t>(Y) & 15) == 0) && b == kMaxBlock;
   hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((K + kTrsmRows - 1) / kTrsmRows)), dim3(64), 0,
-                     st, X, ldx, K, b, F, Y, ldy, vec);
+                     st, X, ldx, K, b, F, Y, ldy, vec, apply);
 }
 
 // ------------------------------------------------------------ setup pass

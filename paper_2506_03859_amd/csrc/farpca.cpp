@@ -39,6 +39,10 @@ using namespace farpca_int;
 // squared relative pivot below which a block direction counts as dependent
 static constexpr double kDropRel = 1e-10;
 static constexpr int kCholqrPasses = 2;
+// a repeated CholeskyQR pass is skipped when the Gram of its input deviates
+// from the identity by at most this much (orthonormal far beyond what the
+// FP32 data and the method need)
+static constexpr double kRepeatSkip = 1e-8;
 
 struct farpca_plan_s {
   farpca_params prm;
@@ -356,21 +360,26 @@ void project_out(const farpca_plan_s *pl, const Ws &w, int64_t l, float *T, hipS
 // (residual below 1e-5 of the column, i.e. rounding noise of the FP32 data)
 // become exactly zero.  Two passes suffice: the first leaves an orthogonality
 // error of about u64 cond(X)^2, the second brings it to the FP32 rounding of
-// the stored result, which further passes cannot go below.  If gram_eig, the
-// eigenvalues of the first Gram go to w64 (descending).
+// the stored result, which further passes cannot go below.  A repeated pass
+// whose Gram shows the columns orthonormal to kRepeatSkip already (well
+// conditioned X: the first pass reached that level) applies nothing: its
+// factor and solve are skipped on the device.  If gram_eig, the eigenvalues of
+// the first Gram go to w64 (descending).
 void cholqr(const farpca_plan_s *pl, const Ws &w, float *X, int64_t K, int passes, bool gram_eig,
             hipStream_t st) {
   double *gpart = w.at<double>(pl->off_gpart);
   double *G = w.at<double>(pl->off_g64);
-  double *Rinv = w.at<double>(pl->off_rinv);
+  double *Rf = w.at<double>(pl->off_rinv);
   int *flags = reinterpret_cast<int *>(w.at<double>(pl->off_scal) + 3);
+  int *apply = flags + 1;
   for (int pass = 0; pass < passes; ++pass) {
     launch_gram(X, kBld, K, pl->b, gpart, G, st);
     if (pass == 0 && gram_eig)
       launch_eig_small(G, pl->b, kMaxBlock, w.at<double>(pl->off_w64), w.at<double>(pl->off_v64),
                        kMaxBlock, st);
-    launch_chol(G, pl->b, kDropRel, Rinv, flags, st);
-    launch_trsm_rows(X, kBld, K, pl->b, Rinv, X, kBld, st);
+    const bool repeat = pass > 0;
+    launch_chol(G, pl->b, kDropRel, Rf, flags, repeat ? kRepeatSkip : 0.0, repeat ? apply : nullptr, st);
+    launch_trsm_rows(X, kBld, K, pl->b, Rf, X, kBld, repeat ? apply : nullptr, st);
   }
 }
 

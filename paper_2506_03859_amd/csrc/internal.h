@@ -114,11 +114,16 @@ void launch_gram(const float *X, int64_t ldx, int64_t K, int b, double *part, do
                  hipStream_t st);
 // Cholesky factor G = R^T R (64 x 64 FP64): F = R strictly above the
 // diagonal, 1 / R_jj on it.  Columns whose pivot is <= drop_rel * diagonal
-// are dropped (zero row of R, F_jj = 0); flags[0] |= 1 then.
-void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags, hipStream_t st);
-// Y = X R^{-1} row by row (forward substitution in FP64; in place allowed).
+// are dropped (zero row of R, F_jj = 0); flags[0] |= 1 then.  skip_tol > 0
+// (a repeated pass): if every kept column of G is orthonormal to skip_tol,
+// nothing is factored and apply[0] = 0, else apply[0] = 1 (apply may be null
+// when skip_tol == 0).
+void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags, double skip_tol,
+                 int *apply, hipStream_t st);
+// Y = X R^{-1} row by row (forward substitution in FP64; in place allowed);
+// nothing is done when apply is non-null and apply[0] == 0 (requires Y == X).
 void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const double *F, float *Y,
-                      int64_t ldy, hipStream_t st);
+                      int64_t ldy, const int *apply, hipStream_t st);
 // Setup pass over A: partial sums of squares (FP64, per row block) and the
 // row sums (FP64, rowsum[i]); nonfinite flag.
 int setup_num_partials(int64_t m);
