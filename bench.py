@@ -286,6 +286,7 @@ def serve_bench(args, dev):
         "value": mixed["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "bf16+f32", "data": "synthetic",
         "config": {"workload": f"serve_{len(reqs)}req_poisson200", "slots": args.serve_slots,
+                   "hw_queues": args.serve_hw_queues or None,
                    "pool_GiB": args.serve_pool_gb, "matrices": len(mats), "power": 1, "sketch": "sparse_sign",
                    "zeta": 8, "bf16_floor_median": float(np.median(floor))},
         "mixed": mixed, "fp32": f32,
@@ -310,6 +311,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-pool-gb", type=float, default=80.0)
+    ap.add_argument("--serve-hw-queues", type=int, default=0,
+                    help="hardware queues of the process (GPU_MAX_HW_QUEUES, set before the HIP "
+                         "runtime starts; 0 = the runtime's default)")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only launch the kernels that stream A (A-pass products, sparse sketch) "
                          "on a random matrix of the workload's shape, plus a 1 GiB copy: the "
@@ -319,6 +323,10 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
               file=sys.stderr)
         sys.exit(2)
+    if args.serve and args.serve_hw_queues > 0:
+        # streams of concurrent slots map onto distinct hardware queues only up
+        # to this count; must be set before the runtime initialises
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, args.serve_hw_queues))
 
     import torch
     from paper_2506_03859_amd import farpca as fp
