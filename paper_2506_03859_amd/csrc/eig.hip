@@ -21,8 +21,9 @@
 
 namespace farpca_int {
 
-// A pair (p, q) is left alone when |a_pq| <= 1e-14 sqrt(|a_pp a_qq|) (the
-// relative test that keeps Jacobi's small eigenvalues accurate) or when
+// A pair (p, q) is left alone when |a_pq| <= rel sqrt(|a_pp a_qq|) (the
+// relative test that keeps Jacobi's small eigenvalues accurate; rel = 1e-14
+// unless the caller asks for less) or when
 // |a_pq| <= 1e-13 max_i |a_ii|.  The absolute floor sits above the FP64
 // rounding that the block updates themselves leave behind (sums of 32 terms
 // of size max |a_ii|); with a floor at that level the sweeps never end.
@@ -36,9 +37,10 @@ constexpr int kInnerMaxSweeps = 30;   // a small matrix solved on its own
 constexpr int kPreSweeps = 2;
 constexpr int kPairSweeps = 1;
 
-__device__ __forceinline__ bool negligible(double apq, double app, double aqq, double floor_abs) {
+__device__ __forceinline__ bool negligible(double apq, double app, double aqq, double floor_abs,
+                                           double rel) {
   const double x = fabs(apq);
-  return x == 0.0 || x <= kJacobiRel * sqrt(fabs(app) * fabs(aqq)) || x <= floor_abs;
+  return x == 0.0 || x <= rel * sqrt(fabs(app) * fabs(aqq)) || x <= floor_abs;
 }
 
 __device__ __forceinline__ int rr_player(int pos, int step, int n) {
@@ -49,7 +51,7 @@ __device__ __forceinline__ int rr_player(int pos, int step, int n) {
 // Cyclic Jacobi on an S x S symmetric matrix a (LDS, stride LD) accumulating
 // rotations into v (LDS, stride LD, holds the starting orthogonal matrix).
 template <int S, int LD, int NT>
-__device__ void jacobi_lds(double *a, double *v, double floor_abs, int max_sweeps) {
+__device__ void jacobi_lds(double *a, double *v, double floor_abs, int max_sweeps, double rel) {
   constexpr int H = S / 2;
   __shared__ double cs_c[H], cs_s[H], cs_t[H];
   __shared__ int cs_p[H], cs_q[H], cs_on[H];
@@ -64,7 +66,7 @@ __device__ void jacobi_lds(double *a, double *v, double floor_abs, int max_sweep
         const double app = a[p * LD + p], aqq = a[q * LD + q], apq = a[p * LD + q];
         double c = 1.0, s = 0.0, t = 0.0;
         int on = 0;
-        if (!negligible(apq, app, aqq, floor_abs)) {
+        if (!negligible(apq, app, aqq, floor_abs, rel)) {
           const double theta = (aqq - app) / (2.0 * apq);
           t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(fma(theta, theta, 1.0)));
           c = rsqrt(fma(t, t, 1.0));
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(256) void eig_small_kernel(const double *__restrict
     fl = mx * kJacobiAbs;
   }
   __syncthreads();
-  jacobi_lds<64, kSmallLd, 256>(a, v, fl, kInnerMaxSweeps);
+  jacobi_lds<64, kSmallLd, 256>(a, v, fl, kInnerMaxSweeps, kJacobiRel);
   __syncthreads();
   // descending order among the first s positions (ties by index)
   if (tid < s) {
@@ -177,7 +179,8 @@ __device__ __forceinline__ int sub_index(int u, int bi, int bj) {
 constexpr int kPairThreads = 512;
 __global__ __launch_bounds__(kPairThreads) void bj_pair_kernel(const double *__restrict__ M, int64_t lp, int nb,
                                                      int step, double *__restrict__ R,
-                                                     const double *__restrict__ floor_abs) {
+                                                     const double *__restrict__ floor_abs,
+                                                     double rel) {
   __shared__ double a[kSub * kSubLd];
   __shared__ double v[kSub * kSubLd];
   const int pair = blockIdx.x, tid = threadIdx.x;
@@ -193,10 +196,10 @@ __global__ __launch_bounds__(kPairThreads) void bj_pair_kernel(const double *__r
   const double fl = floor_abs[0];
   for (int e = tid; e < kSub * kSub; e += kPairThreads) {
     const int u = e / kSub, x = e % kSub;
-    if (u < x && !negligible(a[u * kSubLd + x], a[u * kSubLd + u], a[x * kSubLd + x], fl)) any_big = 1;
+    if (u < x && !negligible(a[u * kSubLd + x], a[u * kSubLd + u], a[x * kSubLd + x], fl, rel)) any_big = 1;
   }
   __syncthreads();
-  if (any_big) jacobi_lds<kSub, kSubLd, kPairThreads>(a, v, fl, kPairSweeps);   // else R = I
+  if (any_big) jacobi_lds<kSub, kSubLd, kPairThreads>(a, v, fl, kPairSweeps, rel);   // else R = I
   __syncthreads();
   double *Rp = R + (int64_t)pair * kSub * kSub;
   for (int e = tid; e < kSub * kSub; e += kPairThreads) Rp[e] = v[(e / kSub) * kSubLd + (e % kSub)];
@@ -283,13 +286,14 @@ __global__ __launch_bounds__(256) void bj_floor_kernel(const double *__restrict_
 // block row; integer atomics, so the count is exact).
 __global__ __launch_bounds__(256) void bj_check_kernel(const double *__restrict__ M, int64_t lp,
                                                        int *__restrict__ count,
-                                                       const double *__restrict__ floor_abs) {
+                                                       const double *__restrict__ floor_abs,
+                                                       double rel) {
   const int64_t i = blockIdx.x;
   const double fl = floor_abs[0];
   const double aii = M[i * lp + i];
   int c = 0;
   for (int64_t j = i + 1 + threadIdx.x; j < lp; j += 256)
-    if (!negligible(M[i * lp + j], aii, M[j * lp + j], fl)) ++c;
+    if (!negligible(M[i * lp + j], aii, M[j * lp + j], fl, rel)) ++c;
   if (c) atomicAdd(count, c);
 }
 
@@ -308,7 +312,7 @@ __global__ void bj_init_kernel(const double *__restrict__ K, int64_t l, int64_t 
 constexpr int kPre = 64;
 constexpr int kPreThreads = 1024;
 __global__ __launch_bounds__(kPreThreads) void bj_pre_eig_kernel(const double *__restrict__ M, int64_t lp,
-                                                         double *__restrict__ V) {
+                                                         double *__restrict__ V, double rel) {
   __shared__ double a[kPre * kSmallLd];
   __shared__ double v[kPre * kSmallLd];
   __shared__ double fl;
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(kPreThreads) void bj_pre_eig_kernel(const double *_
     fl = mx * kJacobiAbs;
   }
   __syncthreads();
-  jacobi_lds<kPre, kSmallLd, kPreThreads>(a, v, fl, kPreSweeps);
+  jacobi_lds<kPre, kSmallLd, kPreThreads>(a, v, fl, kPreSweeps, rel);
   __syncthreads();
   for (int e = tid; e < kPre * kPre; e += kPreThreads) {
     const int i = e / kPre, j = e % kPre;
@@ -408,7 +412,9 @@ size_t eig_workspace_bytes(int64_t l) {
   return bytes;
 }
 
-int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, hipStream_t st) {
+int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, double rel,
+            hipStream_t st) {
+  if (!(rel > 0.0)) rel = kJacobiRel;
   if (l <= 64) {
     launch_eig_small(K, (int)l, (int)l, w, Vout, (int)l, st);
     return 1;
@@ -429,19 +435,21 @@ int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, hip
   const double abs_factor = kJacobiAbs;
   hipLaunchKernelGGL(bj_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, K, l, lp, M, V);
   const int npre = (int)(lp / kPre);
-  hipLaunchKernelGGL(bj_pre_eig_kernel, dim3(npre), dim3(kPreThreads), 0, st, M, lp, V);
+  hipLaunchKernelGGL(bj_pre_eig_kernel, dim3(npre), dim3(kPreThreads), 0, st, M, lp, V, rel);
   hipLaunchKernelGGL(bj_pre_rotate_kernel, dim3(npre, npre), dim3(256), 0, st, M, V, lp);
   int sweeps = 0;
   const int max_sweeps = 40;
   for (; sweeps < max_sweeps; ++sweeps) {
     hipLaunchKernelGGL(bj_floor_kernel, dim3(1), dim3(256), 0, st, M, lp, abs_factor, count, floor_abs);
-    hipLaunchKernelGGL(bj_check_kernel, dim3((unsigned)lp), dim3(256), 0, st, M, lp, count, floor_abs);
+    hipLaunchKernelGGL(bj_check_kernel, dim3((unsigned)lp), dim3(256), 0, st, M, lp, count, floor_abs,
+                       rel);
     int h_count = 0;
     hipMemcpyAsync(&h_count, count, sizeof(int), hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
     if (h_count == 0) break;
     for (int step = 0; step < nb - 1; ++step) {
-      hipLaunchKernelGGL(bj_pair_kernel, dim3(npairs), dim3(kPairThreads), 0, st, M, lp, nb, step, R, floor_abs);
+      hipLaunchKernelGGL(bj_pair_kernel, dim3(npairs), dim3(kPairThreads), 0, st, M, lp, nb, step, R, floor_abs,
+                         rel);
       const int64_t nwg = (int64_t)npairs * npairs + (lp / kSub) * npairs;
       hipLaunchKernelGGL(bj_update_kernel, dim3((unsigned)nwg), dim3(256), 0, st, M, V, lp, nb, step, R);
     }

@@ -43,6 +43,13 @@ static constexpr int kCholqrPasses = 2;
 // from the identity by at most this much (orthonormal far beyond what the
 // FP32 data and the method need)
 static constexpr double kRepeatSkip = 1e-8;
+// Final eigensolve of K = C C^T: Jacobi stops once every off-diagonal entry is
+// below 1e-8 of the geometric mean of its two diagonal entries.  The
+// eigenvalues are then exact to FP64 rounding (their error is quadratic in the
+// off-diagonal entries); V = C^T U~ Sigma^{-1} is orthonormal to the same 1e-8,
+// and U S V^T = Q Q^T A holds for any orthogonal U~, so FP32 outputs lose
+// nothing.
+static constexpr double kFinalEigRel = 1e-8;
 
 struct farpca_plan_s {
   farpca_params prm;
@@ -502,7 +509,7 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
   int sweeps;
   {
     ProfScope ps(FARPCA_PROF_EIG, st);
-    sweeps = eig_sym(Kbig, l, wfin, vfin, w.at<void>(pl->off_eig), st);
+    sweeps = eig_sym(Kbig, l, wfin, vfin, w.at<void>(pl->off_eig), kFinalEigRel, st);
   }
   launch_sqrt_clip(wfin, rout, dS, st);
   // U = Q U~ (first rout columns)
@@ -646,7 +653,7 @@ extern "C" size_t farpca_eig_scratch_bytes(int64_t l) { return eig_workspace_byt
 extern "C" int farpca_eig(const double *dK, int64_t l, double *dW, double *dV, void *dWork,
                           void *stream) {
   if (!dK || !dW || !dV || !dWork || l < 1) return FARPCA_E_INVALID;
-  const int sweeps = eig_sym(dK, l, dW, dV, dWork, static_cast<hipStream_t>(stream));
+  const int sweeps = eig_sym(dK, l, dW, dV, dWork, 0.0, static_cast<hipStream_t>(stream));
   HIP_OK(hipGetLastError());
   return sweeps;
 }

@@ -153,7 +153,10 @@ size_t eig_workspace_bytes(int64_t l);
 // Eigen-decomposition of the symmetric l x l matrix K (FP64, row-major, ld l):
 // eigenvalues descending in w[l], eigenvectors in Vout (l x l row-major, column
 // i <-> w[i]).  Returns number of sweeps used (host-synchronous).
-int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, hipStream_t st);
+// Off-diagonal entries are reduced until |a_pq| <= rel sqrt(|a_pp a_qq|) (or
+// an absolute floor); rel <= 0 selects the default 1e-14.
+int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, double rel,
+            hipStream_t st);
 // Single-workgroup Jacobi for s <= 64 (used for the b x b Gram in the shift).
 void launch_eig_small(const double *K, int s, int ldk, double *w, double *Vout, int ldv,
                       hipStream_t st);
