@@ -207,7 +207,29 @@ __global__ __launch_bounds__(kPairThreads) void bj_pair_kernel(const double *__r
   for (int e = tid; e < kSub * kSub; e += kPairThreads) Rp[e] = v[(e / kSub) * kSubLd + (e % kSub)];
 }
 
-// Rotate M (pair blocks) and V (row tiles x pair columns) in place.
+// 32 x 32 products on the FP64 matrix cores (v_mfma_f64_16x16x4f64): wave w
+// of the workgroup forms the 16 x 16 quadrant (w / 2, w % 2) of L * Rm (L read
+// transposed when TRANS_L), K = 32 in 8 steps.  Operand layout: lane l holds
+// A (row l % 16, k l / 16) and B (k l / 16, col l % 16); result element v of
+// lane l is (row 4 v + l / 16, col l % 16).
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+template <bool TRANS_L>
+__device__ __forceinline__ doublex4 mm32_quadrant(const double *L, const double *Rm, int w, int lane) {
+  const int qr = w >> 1, qc = w & 1, li = lane & 15, lk = lane >> 4;
+  doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int st = 0; st < kSub / 4; ++st) {
+    const int k = 4 * st + lk;
+    const double av = TRANS_L ? L[k * kSubLd + 16 * qr + li] : L[(16 * qr + li) * kSubLd + k];
+    const double bv = Rm[k * kSubLd + 16 * qc + li];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Rotate M (pair blocks) and V (row tiles x pair columns) in place:
+// M[S_p, S_q] <- R_p^T M[S_p, S_q] R_q, V[:, S_q] <- V[:, S_q] R_q.  Each
+// workgroup reads its whole block before writing it back.
 __global__ __launch_bounds__(256) void bj_update_kernel(double *__restrict__ M, double *__restrict__ V,
                                                         int64_t lp, int nb, int step,
                                                         const double *__restrict__ R) {
@@ -217,6 +239,8 @@ __global__ __launch_bounds__(256) void bj_update_kernel(double *__restrict__ M, 
   __shared__ double rp[kSub * kSubLd];
   const int npairs = nb / 2;
   const int tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63;
+  const int qr = w >> 1, qc = w & 1, li = lane & 15, lk = lane >> 4;
   const int64_t nm = (int64_t)npairs * npairs;
   const int64_t id = blockIdx.x;
   const bool is_m = id < nm;
@@ -236,21 +260,14 @@ __global__ __launch_bounds__(256) void bj_update_kernel(double *__restrict__ M, 
       blk[u * kSubLd + x] = M[(int64_t)sub_index(u, pi, pj) * lp + sub_index(x, qi, qj)];
     }
     __syncthreads();
-    // tmp = blk * R_q
-    for (int e = tid; e < kSub * kSub; e += 256) {
-      const int u = e / kSub, x = e % kSub;
-      double s = 0.0;
-      for (int k = 0; k < kSub; ++k) s = fma(blk[u * kSubLd + k], rq[k * kSubLd + x], s);
-      tmp[u * kSubLd + x] = s;
-    }
+    const doublex4 t = mm32_quadrant<false>(blk, rq, w, lane);      // blk R_q
+#pragma unroll
+    for (int v = 0; v < 4; ++v) tmp[(16 * qr + 4 * v + lk) * kSubLd + 16 * qc + li] = t[v];
     __syncthreads();
-    // M block = R_p^T * tmp
-    for (int e = tid; e < kSub * kSub; e += 256) {
-      const int u = e / kSub, x = e % kSub;
-      double s = 0.0;
-      for (int k = 0; k < kSub; ++k) s = fma(rp[k * kSubLd + u], tmp[k * kSubLd + x], s);
-      M[(int64_t)sub_index(u, pi, pj) * lp + sub_index(x, qi, qj)] = s;
-    }
+    const doublex4 o = mm32_quadrant<true>(rp, tmp, w, lane);       // R_p^T (blk R_q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      M[(int64_t)sub_index(16 * qr + 4 * v + lk, pi, pj) * lp + sub_index(16 * qc + li, qi, qj)] = o[v];
   } else {
     const int64_t r0 = rowtile * kSub;
     for (int e = tid; e < kSub * kSub; e += 256) {
@@ -258,12 +275,9 @@ __global__ __launch_bounds__(256) void bj_update_kernel(double *__restrict__ M, 
       blk[u * kSubLd + x] = V[(r0 + u) * lp + sub_index(x, qi, qj)];
     }
     __syncthreads();
-    for (int e = tid; e < kSub * kSub; e += 256) {
-      const int u = e / kSub, x = e % kSub;
-      double s = 0.0;
-      for (int k = 0; k < kSub; ++k) s = fma(blk[u * kSubLd + k], rq[k * kSubLd + x], s);
-      V[(r0 + u) * lp + sub_index(x, qi, qj)] = s;
-    }
+    const doublex4 o = mm32_quadrant<false>(blk, rq, w, lane);      // V_tile R_q
+#pragma unroll
+    for (int v = 0; v < 4; ++v) V[(r0 + 16 * qr + 4 * v + lk) * lp + sub_index(16 * qc + li, qi, qj)] = o[v];
   }
 }
 
