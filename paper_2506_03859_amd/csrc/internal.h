@@ -28,14 +28,12 @@ struct OmegaSpec {
 // staged A tile, and the unscaled value (+-1, 1 or a Gaussian draw).  Every
 // column's list is padded with zero-valued entries to a multiple of
 // kListPad, so the sketch consumes whole groups; kEntCap entries per chunk.
-// The last kListPad slots of every chunk's region (kZeroEnt ..) hold zero
-// entries, a group the sketch may read in place of a real one; the lists
-// themselves use at most kChunk * kMaxBlock + (kListPad - 1) * kMaxBlock slots.
+// The lists use at most kChunk * kMaxBlock + (kListPad - 1) * kMaxBlock
+// slots; the 128 + kMaxBlock slots after them are room for the sketch's
+// fixed-size reads past a list's end (never used as entries).
 struct ChunkEntry { uint32_t lds_off; float val; };
 constexpr int kListPad = 4;
-constexpr int kEntCap = kChunk * kMaxBlock + kListPad * kMaxBlock;
-constexpr int kZeroEnt = kEntCap - kListPad;
-static_assert(kChunk * kMaxBlock + (kListPad - 1) * kMaxBlock <= kZeroEnt, "zero group overlaps lists");
+constexpr int kEntCap = kChunk * kMaxBlock + kListPad * kMaxBlock + 128;
 
 // ---- omega.hip
 // Generates Omega_j for rows [0, n): mask/sign words (n each), the dense copy

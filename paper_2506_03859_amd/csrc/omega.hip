@@ -117,7 +117,6 @@ __global__ __launch_bounds__(64) void omega_kernel(OmegaSpec s, int64_t n, int64
   uint32_t *cp = colptr + chunk * (kMaxBlock + 1);
   cp[c] = cstart[c];
   if (t == 0) cp[kMaxBlock] = cstart[kMaxBlock];
-  if (t < kListPad) entries[chunk * (int64_t)kEntCap + kZeroEnt + t] = ChunkEntry{0u, 0.0f};
   if (c < b) {
     ChunkEntry *ent = entries + chunk * (int64_t)kEntCap;
     uint32_t pos = cstart[c];
