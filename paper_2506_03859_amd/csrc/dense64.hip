@@ -195,10 +195,10 @@ __global__ __launch_bounds__(64) void chol_kernel(const double *__restrict__ G, 
     }
   }
   if (any_drop && j == 0) atomicOr(flags, 1);
-  // c[i] for i < j is R[i][j], c[j] is F_jj; row i of F is written by the 64
-  // lanes together (coalesced)
+  // c[i] for i < j is R[i][j], c[j] is F_jj; F is stored by columns (lane j
+  // writes column j, contiguous), the order in which the solve reads it
 #pragma unroll
-  for (int i = 0; i < kMaxBlock; ++i) F[i * kMaxBlock + j] = (i <= j && j < b) ? c[i] : 0.0;
+  for (int i = 0; i < kMaxBlock; ++i) F[j * kMaxBlock + i] = (i <= j && j < b) ? c[i] : 0.0;
 }
 
 void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags, double skip_tol,
@@ -209,22 +209,23 @@ void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags,
 // Y = X R^{-1} row by row: forward substitution y_c = F_cc (x_c - sum_{i<c}
 // y_i R_ic) in FP64, each value rounded once to FP32.  One wave per 64 rows:
 // the row tile is read coalesced into LDS (row stride 65 floats), each lane
-// solves its row from there with F transposed in LDS (column c contiguous,
-// stride 65 doubles: conflict-free staging), and the result leaves through
-// the same tile.  Columns >= b are not written.  Y may alias X (a tile is
-// read completely before any of it is written).
+// solves its row from there, and the result leaves through the same tile.
+// The factor (stored by columns: column c = R_0c .. R_(c-1)c, F_cc) is the
+// same for every lane and not written while the solve runs, so it is read
+// through the constant address space: scalar loads, requested far ahead of
+// their use, with no LDS traffic.  Columns >= b are not written.  Y may
+// alias X (a tile is read completely before any of it is written).
 constexpr int kTrsmRows = 64;
 __global__ __launch_bounds__(64) void trsm_rows_kernel(const float *__restrict__ X, int64_t ldx,
                                                        int64_t K, int b, const double *__restrict__ Fg,
                                                        float *__restrict__ Y, int64_t ldy, int vec,
                                                        const int *__restrict__ apply) {
-  __shared__ double Ft[kMaxBlock * (kMaxBlock + 1)];     // Ft[c][i] = F[i][c]
   __shared__ float xt[kTrsmRows * (kMaxBlock + 1)];
   if (apply && apply[0] == 0) return;                    // R = I: nothing to do (in place)
+  typedef __attribute__((address_space(4))) const double ConstF64;
+  ConstF64 *Ft = (ConstF64 *)(uintptr_t)Fg;
   const int t = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * kTrsmRows;
-  for (int e = t; e < kMaxBlock * kMaxBlock; e += 64)
-    Ft[(e % kMaxBlock) * (kMaxBlock + 1) + e / kMaxBlock] = Fg[e];
   // tile in: instruction q covers rows 4 q + t / 16, columns 4 (t % 16) .. + 3
 #pragma unroll 4
   for (int q = 0; q < kTrsmRows / 4; ++q) {
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(64) void trsm_rows_kernel(const float *__restrict__
 #pragma unroll
   for (int c = 0; c < kMaxBlock; ++c) {
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    const double *fc = Ft + c * (kMaxBlock + 1);
+    ConstF64 *fc = Ft + c * kMaxBlock;
 #pragma unroll
     for (int i = 0; i < c; ++i) s[i & 3] = fma(y[i], fc[i], s[i & 3]);
     y[c] = (y[c] - ((s[0] + s[1]) + (s[2] + s[3]))) * fc[c];

@@ -52,11 +52,18 @@ __device__ __forceinline__ int rr_player(int pos, int step, int n) {
 
 // Cyclic Jacobi on an S x S symmetric matrix a (LDS, stride LD) accumulating
 // rotations into v (LDS, stride LD, holds the starting orthogonal matrix).
+// A step: threads 0 .. S/2 - 1 compute the step's rotations (c, s, t and
+// whether the pair is rotated at all) into LDS; then every thread applies
+// them to its 2 x 2 blocks of a and its row pairs of v.  The pairs of a step
+// follow from the step number alone, so the appliers compute them and read
+// the rotation together with the matrix entries (one LDS round trip); an
+// identity rotation is applied like any other (c = 1, s = 0 copy exactly),
+// only the diagonal blocks test it.
 template <int S, int LD, int NT>
 __device__ void jacobi_lds(double *a, double *v, double floor_abs, int max_sweeps, double rel) {
   constexpr int H = S / 2;
   __shared__ double cs_c[H], cs_s[H], cs_t[H];
-  __shared__ int cs_p[H], cs_q[H], cs_on[H];
+  __shared__ int cs_on[H];
   __shared__ int any_rot;
   const int tid = threadIdx.x;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
@@ -76,23 +83,24 @@ __device__ void jacobi_lds(double *a, double *v, double floor_abs, int max_sweep
           on = 1;
           any_rot = 1;
         }
-        cs_c[tid] = c; cs_s[tid] = s; cs_t[tid] = t; cs_p[tid] = p; cs_q[tid] = q; cs_on[tid] = on;
+        cs_c[tid] = c; cs_s[tid] = s; cs_t[tid] = t; cs_on[tid] = on;
       }
       __syncthreads();
-      // A <- J^T A J, one 2x2 block (pair ia rows, pair ib columns) at a time
       for (int e = tid; e < H * H; e += NT) {
         const int ia = e / H, ib = e % H;
-        if (!cs_on[ia] && !cs_on[ib]) continue;
-        const int pa = cs_p[ia], qa = cs_q[ia], pb = cs_p[ib], qb = cs_q[ib];
+        const int pa = rr_player(ia, step, S), qa = rr_player(S - 1 - ia, step, S);
         if (ia == ib) {
-          const double apq = a[pa * LD + qa];
-          const double t = cs_t[ia];
-          a[pa * LD + pa] -= t * apq;
-          a[qa * LD + qa] += t * apq;
-          a[pa * LD + qa] = 0.0;
-          a[qa * LD + pa] = 0.0;
+          if (cs_on[ia]) {
+            const double apq = a[pa * LD + qa];
+            const double t = cs_t[ia];
+            a[pa * LD + pa] -= t * apq;
+            a[qa * LD + qa] += t * apq;
+            a[pa * LD + qa] = 0.0;
+            a[qa * LD + pa] = 0.0;
+          }
           continue;
         }
+        const int pb = rr_player(ib, step, S), qb = rr_player(S - 1 - ib, step, S);
         const double ca = cs_c[ia], sa = cs_s[ia], cb = cs_c[ib], sb = cs_s[ib];
         const double x11 = a[pa * LD + pb], x12 = a[pa * LD + qb];
         const double x21 = a[qa * LD + pb], x22 = a[qa * LD + qb];
@@ -103,11 +111,9 @@ __device__ void jacobi_lds(double *a, double *v, double floor_abs, int max_sweep
         a[qa * LD + pb] = cb * y21 - sb * y22;
         a[qa * LD + qb] = sb * y21 + cb * y22;
       }
-      // V <- V J
       for (int e = tid; e < S * H; e += NT) {
         const int r = e / H, ib = e % H;
-        if (!cs_on[ib]) continue;
-        const int pb = cs_p[ib], qb = cs_q[ib];
+        const int pb = rr_player(ib, step, S), qb = rr_player(S - 1 - ib, step, S);
         const double c = cs_c[ib], s = cs_s[ib];
         const double vp = v[r * LD + pb], vq = v[r * LD + qb];
         v[r * LD + pb] = c * vp - s * vq;
@@ -120,7 +126,6 @@ __device__ void jacobi_lds(double *a, double *v, double floor_abs, int max_sweep
   }
 }
 
-// ----------------------------------------------------------- small (<= 64)
 constexpr int kSmallLd = 65;
 
 __global__ __launch_bounds__(256) void eig_small_kernel(const double *__restrict__ K, int s, int ldk,
