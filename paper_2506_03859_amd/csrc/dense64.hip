@@ -134,6 +134,9 @@ void launch_gram(const float *X, int64_t ldx, int64_t K, int b, double *part, do
 // One wave: lane j holds column j of the working matrix in registers; step k
 // broadcasts the pivot and row k of R through LDS and updates the trailing
 // columns.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int kInvLd = kMaxBlock + 1;      // LDS stride of the factor and its inverse
+
 __device__ __forceinline__ double bcast_f64(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -180,7 +183,7 @@ __global__ __launch_bounds__(64) void chol_kernel(const double *__restrict__ G, 
       const double dgk = bcast_f64(dg, k);
       double r = 0.0;                               // R[k][j] for j > k
       if (piv > drop_rel * dgk && piv > 0.0) {     // false for NaN too
-        const double inv = 1.0 / sqrt(piv);
+        const double inv = rsqrt(piv);
         r = (j > k) ? c[k] * inv : 0.0;
         c[k] = (j == k) ? inv : ((j > k) ? r : c[k]);
       } else {
@@ -195,10 +198,70 @@ __global__ __launch_bounds__(64) void chol_kernel(const double *__restrict__ G, 
     }
   }
   if (any_drop && j == 0) atomicOr(flags, 1);
-  // c[i] for i < j is R[i][j], c[j] is F_jj; F is stored by columns (lane j
-  // writes column j, contiguous), the order in which the solve reads it
+  // c[i] for i < j is R[i][j], c[j] is F_jj = 1 / R_jj (0 for a dropped
+  // column, whose row of R is zero too); columns >= b are zero.  The solve
+  // y_c = F_cc (x_c - sum_{i<c} y_i R_ic) is linear in x: y = x M with M the
+  // inverse of R (rows and columns of dropped pivots zero, since F_kk = 0
+  // there).  M is formed here once, so that the row solve is a plain product.
+  __shared__ double Rl[kMaxBlock * kInvLd];
+  __shared__ double Ml[kMaxBlock * kInvLd];
+  __shared__ double Tl[16 * 17];
 #pragma unroll
-  for (int i = 0; i < kMaxBlock; ++i) F[j * kMaxBlock + i] = (i <= j && j < b) ? c[i] : 0.0;
+  for (int i = 0; i < kMaxBlock; ++i) {
+    Rl[i * kInvLd + j] = (i <= j && j < b) ? c[i] : 0.0;
+    Ml[i * kInvLd + j] = 0.0;
+  }
+  __syncthreads();
+  // diagonal 16 x 16 blocks by back substitution: lane j forms column j of
+  // its block, M_jj = F_jj, M_ij = -F_ii sum_{i<k<=j} R_ik M_kj
+  {
+    const int blk = j >> 4, jl = j & 15, o = 16 * blk;
+    double m[16];
+#pragma unroll
+    for (int il = 0; il < 16; ++il) m[il] = (il == jl) ? Rl[j * kInvLd + j] : 0.0;
+#pragma unroll
+    for (int il = 14; il >= 0; --il) {
+      double acc = 0.0;
+#pragma unroll
+      for (int kl = il + 1; kl < 16; ++kl) acc = fma(Rl[(o + il) * kInvLd + o + kl], m[kl], acc);
+      if (il < jl) m[il] = -Rl[(o + il) * kInvLd + o + il] * acc;
+    }
+#pragma unroll
+    for (int il = 0; il < 16; ++il) Ml[(o + il) * kInvLd + j] = m[il];
+  }
+  __syncthreads();
+  // off-diagonal blocks, nearest the diagonal first:
+  // M_ab = -M_aa (sum_{a<c<=b} R_ac M_cb), as 16 x 16 products on the FP64
+  // matrix cores (lane l: A (row l % 16, k l / 16), B (k l / 16, col l % 16),
+  // result element v at (row 4 v + l / 16, col l % 16))
+  const int li = j & 15, lk = j >> 4;
+  for (int d = 1; d < 4; ++d) {
+    for (int a = 0; a + d < 4; ++a) {
+      const int bb = a + d;
+      doublex4 t = {0.0, 0.0, 0.0, 0.0};
+      for (int st = 0; st < 4 * d; ++st) {
+        const int k = 16 * (a + 1) + 4 * st + lk;
+        t = __builtin_amdgcn_mfma_f64_16x16x4f64(Rl[(16 * a + li) * kInvLd + k],
+                                                 Ml[k * kInvLd + 16 * bb + li], t, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Tl[(4 * v + lk) * 17 + li] = t[v];
+      __syncthreads();
+      doublex4 u = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int k = 4 * st + lk;
+        u = __builtin_amdgcn_mfma_f64_16x16x4f64(Ml[(16 * a + li) * kInvLd + 16 * a + k],
+                                                 Tl[k * 17 + li], u, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Ml[(16 * a + 4 * v + lk) * kInvLd + 16 * bb + li] = -u[v];
+      __syncthreads();
+    }
+  }
+  // M stored by columns (lane j writes column j, contiguous)
+#pragma unroll
+  for (int i = 0; i < kMaxBlock; ++i) F[j * kMaxBlock + i] = Ml[i * kInvLd + j];
 }
 
 void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags, double skip_tol,
@@ -206,30 +269,30 @@ void launch_chol(const double *G, int b, double drop_rel, double *F, int *flags,
   hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(64), 0, st, G, b, drop_rel, F, flags, skip_tol, apply);
 }
 
-// Y = X R^{-1} row by row: forward substitution y_c = F_cc (x_c - sum_{i<c}
-// y_i R_ic) in FP64, each value rounded once to FP32.  One wave per 64 rows:
-// the row tile is read coalesced into LDS (row stride 65 floats), each lane
-// solves its row from there, and the result leaves through the same tile.
-// The factor (stored by columns: column c = R_0c .. R_(c-1)c, F_cc) is the
-// same for every lane and not written while the solve runs, so it is read
-// through the constant address space: scalar loads, requested far ahead of
-// their use, with no LDS traffic.  Columns >= b are not written.  Y may
+// Y = X R^{-1} = X M (M the inverse formed by chol_kernel, stored by
+// columns), FP64 products of the FP32 rows, each value rounded once to FP32.
+// A workgroup (4 waves) per 64 rows: the row tile is read coalesced into LDS
+// (row stride 65 floats) and M transposed into LDS (row stride 65 doubles);
+// wave w forms rows 16 w .. 16 w + 15 of the product on the FP64 matrix cores
+// (four 16 x 16 output blocks, K = 64) and writes them back into its own rows
+// of the tile, which leaves coalesced.  Columns >= b are not written.  Y may
 // alias X (a tile is read completely before any of it is written).
 constexpr int kTrsmRows = 64;
-__global__ __launch_bounds__(64) void trsm_rows_kernel(const float *__restrict__ X, int64_t ldx,
-                                                       int64_t K, int b, const double *__restrict__ Fg,
-                                                       float *__restrict__ Y, int64_t ldy, int vec,
-                                                       const int *__restrict__ apply) {
+__global__ __launch_bounds__(256) void trsm_rows_kernel(const float *__restrict__ X, int64_t ldx,
+                                                        int64_t K, int b, const double *__restrict__ Fg,
+                                                        float *__restrict__ Y, int64_t ldy, int vec,
+                                                        const int *__restrict__ apply) {
+  __shared__ double Ml[kMaxBlock * kInvLd];           // Ml[i][c] = M_ic
   __shared__ float xt[kTrsmRows * (kMaxBlock + 1)];
   if (apply && apply[0] == 0) return;                    // R = I: nothing to do (in place)
-  typedef __attribute__((address_space(4))) const double ConstF64;
-  ConstF64 *Ft = (ConstF64 *)(uintptr_t)Fg;
   const int t = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * kTrsmRows;
+  for (int e = t; e < kMaxBlock * kMaxBlock; e += 256)
+    Ml[(e % kMaxBlock) * kInvLd + e / kMaxBlock] = Fg[e];
   // tile in: instruction q covers rows 4 q + t / 16, columns 4 (t % 16) .. + 3
-#pragma unroll 4
-  for (int q = 0; q < kTrsmRows / 4; ++q) {
-    const int row = 4 * q + (t >> 4), c4 = 4 * (t & 15);
+#pragma unroll
+  for (int q = t >> 4; q < kTrsmRows; q += 16) {
+    const int row = q, c4 = 4 * (t & 15);
     const int64_t gr = r0 + row;
     float v[4] = {0.f, 0.f, 0.f, 0.f};
     if (gr < K) {
@@ -246,24 +309,28 @@ __global__ __launch_bounds__(64) void trsm_rows_kernel(const float *__restrict__
     for (int i = 0; i < 4; ++i) xt[row * (kMaxBlock + 1) + c4 + i] = (c4 + i < b) ? v[i] : 0.f;
   }
   __syncthreads();
-  double y[kMaxBlock];
+  const int w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  doublex4 acc[4];
 #pragma unroll
-  for (int c = 0; c < kMaxBlock; ++c) y[c] = (double)xt[t * (kMaxBlock + 1) + c];
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = doublex4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int c = 0; c < kMaxBlock; ++c) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    ConstF64 *fc = Ft + c * kMaxBlock;
+  for (int st = 0; st < kMaxBlock / 4; ++st) {
+    const int k = 4 * st + lk;
+    const double av = (double)xt[(16 * w + li) * (kMaxBlock + 1) + k];
 #pragma unroll
-    for (int i = 0; i < c; ++i) s[i & 3] = fma(y[i], fc[i], s[i & 3]);
-    y[c] = (y[c] - ((s[0] + s[1]) + (s[2] + s[3]))) * fc[c];
+    for (int ct = 0; ct < 4; ++ct)
+      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ml[k * kInvLd + 16 * ct + li], acc[ct], 0, 0, 0);
   }
-  // own row only: no other lane reads it until the barrier
+  // own rows only: no other wave reads them until the barrier
 #pragma unroll
-  for (int c = 0; c < kMaxBlock; ++c) xt[t * (kMaxBlock + 1) + c] = (float)y[c];
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      xt[(16 * w + 4 * v + lk) * (kMaxBlock + 1) + 16 * ct + li] = (float)acc[ct][v];
   __syncthreads();
-#pragma unroll 4
-  for (int q = 0; q < kTrsmRows / 4; ++q) {
-    const int row = 4 * q + (t >> 4), c4 = 4 * (t & 15);
+#pragma unroll
+  for (int q = t >> 4; q < kTrsmRows; q += 16) {
+    const int row = q, c4 = 4 * (t & 15);
     const int64_t gr = r0 + row;
     if (gr >= K || c4 >= b) continue;
     float *yr = Y + gr * ldy + c4;
@@ -283,7 +350,7 @@ void launch_trsm_rows(const float *X, int64_t ldx, int64_t K, int b, const doubl
   if (K <= 0) return;
   const int vec = (ldx % 4 == 0) && (ldy % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
                   ((reinterpret_cast<uintptr_t>(Y) & 15) == 0) && b == kMaxBlock;
-  hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((K + kTrsmRows - 1) / kTrsmRows)), dim3(64), 0,
+  hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((K + kTrsmRows - 1) / kTrsmRows)), dim3(256), 0,
                      st, X, ldx, K, b, F, Y, ldy, vec, apply);
 }
 
