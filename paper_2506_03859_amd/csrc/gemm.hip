@@ -334,28 +334,69 @@ __global__ __launch_bounds__(256, AVEC ? 3 : 2) void gemm_kernel(const float *__
 }
 
 // ---------------------------------------------------------------- reduce
-__global__ void reduce_partials_kernel(const float *__restrict__ part, int nsplit, int64_t M,
-                                       int64_t N, float *__restrict__ C, int64_t ldc, float alpha,
-                                       float beta, const float *__restrict__ D, int64_t ldd,
-                                       float gamma, const float *__restrict__ z, float zc) {
+// C = alpha * (sum of the partial tiles in split order) [+ beta C] [+ gamma D]
+// [+ zc z_row].  A thread owns 4 adjacent columns of a row: the partials are
+// read with 16-byte loads when the buffer is 16-byte aligned (VEC; the tiles
+// are 64 floats wide), the splits requested together; each element's
+// arithmetic is the same as with one thread per element.
+template <bool VEC>
+__global__ __launch_bounds__(256) void reduce_partials_kernel(
+    const float *__restrict__ part, int nsplit, int64_t M, int64_t N, float *__restrict__ C,
+    int64_t ldc, float alpha, float beta, const float *__restrict__ D, int64_t ldd, float gamma,
+    const float *__restrict__ z, float zc) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t row = idx / 64, col = idx % 64;
-  if (row >= M || col >= N) return;
-  float s = 0.0f;
-  for (int q = 0; q < nsplit; ++q) s += part[((int64_t)q * M + row) * kBld + col];
-  float r = alpha * s;
-  if (beta != 0.0f) r += beta * C[row * ldc + col];
-  if (D) r += gamma * D[row * ldd + col];
-  if (z) r += zc * z[row];
-  C[row * ldc + col] = r;
+  const int64_t row = idx / 16;
+  const int c4 = (int)(idx % 16) * 4;
+  if (row >= M || c4 >= N) return;
+  float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (VEC) {
+    const float4 *p = reinterpret_cast<const float4 *>(part + row * kBld + c4);
+    const int64_t stride = M * kBld / 4;               // one split, in float4
+    int q = 0;
+    for (; q + 4 <= nsplit; q += 4) {
+      float4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = p[(int64_t)(q + u) * stride];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        s[0] += v[u].x; s[1] += v[u].y; s[2] += v[u].z; s[3] += v[u].w;
+      }
+    }
+    for (; q < nsplit; ++q) {
+      const float4 v = p[(int64_t)q * stride];
+      s[0] += v.x; s[1] += v.y; s[2] += v.z; s[3] += v.w;
+    }
+  } else {
+    for (int q = 0; q < nsplit; ++q) {
+      const float *pq = part + ((int64_t)q * M + row) * kBld + c4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s[i] += pq[i];
+    }
+  }
+  const float zr = z ? zc * z[row] : 0.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t col = c4 + i;
+    if (col >= N) break;
+    float r = alpha * s[i];
+    if (beta != 0.0f) r += beta * C[row * ldc + col];
+    if (D) r += gamma * D[row * ldd + col];
+    if (z) r += zr;
+    C[row * ldc + col] = r;
+  }
 }
 
 void launch_reduce_partials(const float *part, int nsplit, int64_t M, int64_t N, float *C,
                             int64_t ldc, float alpha, float beta, const float *D, int64_t ldd,
                             float gamma, const float *z, float zc, hipStream_t st) {
-  const int64_t total = M * 64;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                     part, nsplit, M, N, C, ldc, alpha, beta, D, ldd, gamma, z, zc);
+  const int64_t total = M * 16;
+  const dim3 grid((unsigned)((total + 255) / 256)), blk(256);
+  if ((reinterpret_cast<uintptr_t>(part) & 15) == 0)
+    hipLaunchKernelGGL(reduce_partials_kernel<true>, grid, blk, 0, st, part, nsplit, M, N, C, ldc,
+                       alpha, beta, D, ldd, gamma, z, zc);
+  else
+    hipLaunchKernelGGL(reduce_partials_kernel<false>, grid, blk, 0, st, part, nsplit, M, N, C, ldc,
+                       alpha, beta, D, ldd, gamma, z, zc);
 }
 
 void launch_gemm_finish(const float *part, int nsp, int64_t M, int64_t N, float *C, int64_t ldc,
