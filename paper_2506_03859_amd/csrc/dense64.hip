@@ -175,43 +175,83 @@ __global__ __launch_bounds__(64) void chol_kernel(const double *__restrict__ G, 
   } else if (apply && j == 0) {
     apply[0] = 1;
   }
-  bool any_drop = false;
-#pragma unroll
-  for (int k = 0; k < kMaxBlock; ++k) {
-    if (k < b) {
-      const double piv = bcast_f64(c[k], k);
-      const double dgk = bcast_f64(dg, k);
-      double r = 0.0;                               // R[k][j] for j > k
-      if (piv > drop_rel * dgk && piv > 0.0) {     // false for NaN too
-        const double inv = rsqrt(piv);
-        r = (j > k) ? c[k] * inv : 0.0;
-        c[k] = (j == k) ? inv : ((j > k) ? r : c[k]);
-      } else {
-        any_drop = true;
-        c[k] = (j >= k) ? 0.0 : c[k];
-      }
-      rk[j] = r;
-      __syncthreads();
-#pragma unroll
-      for (int i = k + 1; i < kMaxBlock; ++i) c[i] = fma(-rk[i], r, c[i]);
-      __syncthreads();
-    }
-  }
-  if (any_drop && j == 0) atomicOr(flags, 1);
-  // c[i] for i < j is R[i][j], c[j] is F_jj = 1 / R_jj (0 for a dropped
-  // column, whose row of R is zero too); columns >= b are zero.  The solve
-  // y_c = F_cc (x_c - sum_{i<c} y_i R_ic) is linear in x: y = x M with M the
-  // inverse of R (rows and columns of dropped pivots zero, since F_kk = 0
-  // there).  M is formed here once, so that the row solve is a plain product.
+  // Right-looking factorization in panels of 16 pivots.  The working matrix
+  // (upper triangle) lives in LDS.  Within a panel every lane j >= the
+  // panel's first pivot keeps the panel's 16 rows of its column in registers
+  // and takes the 16 pivot steps exactly as the unblocked algorithm does on
+  // those rows (pivot, scaling, rank-1 update of the later panel rows).  The
+  // rows below the panel are then updated in one step on the FP64 matrix
+  // cores: A_ij -= sum over the panel's pivots k of R_ki R_kj (the
+  // accumulator starts at A_ij).  R goes to Rl: R_kj above the diagonal,
+  // F_kk = 1 / R_kk on it, rows of dropped pivots and columns >= b zero.
+  __shared__ double Al[kMaxBlock * kInvLd];
   __shared__ double Rl[kMaxBlock * kInvLd];
   __shared__ double Ml[kMaxBlock * kInvLd];
   __shared__ double Tl[16 * 17];
 #pragma unroll
   for (int i = 0; i < kMaxBlock; ++i) {
-    Rl[i * kInvLd + j] = (i <= j && j < b) ? c[i] : 0.0;
+    Al[i * kInvLd + j] = c[i];
+    Rl[i * kInvLd + j] = 0.0;
     Ml[i * kInvLd + j] = 0.0;
   }
   __syncthreads();
+  const int li = j & 15, lk = j >> 4;
+  bool any_drop = false;
+  for (int p = 0; p < 4; ++p) {
+    const int k0 = 16 * p;
+    if (k0 >= b) break;
+    double x[16];
+#pragma unroll
+    for (int il = 0; il < 16; ++il) x[il] = Al[(k0 + il) * kInvLd + j];
+#pragma unroll
+    for (int kl = 0; kl < 16; ++kl) {
+      const int k = k0 + kl;
+      if (k < b) {
+        const double piv = bcast_f64(x[kl], k);
+        const double dgk = bcast_f64(dg, k);
+        double r = 0.0;                               // R[k][j] for j > k
+        if (piv > drop_rel * dgk && piv > 0.0) {     // false for NaN too
+          const double inv = rsqrt(piv);
+          r = (j > k) ? x[kl] * inv : 0.0;
+          x[kl] = (j == k) ? inv : ((j > k) ? r : x[kl]);
+        } else {
+          any_drop = true;
+          x[kl] = (j >= k) ? 0.0 : x[kl];
+        }
+        rk[j] = r;
+        __syncthreads();
+#pragma unroll
+        for (int il = kl + 1; il < 16; ++il) x[il] = fma(-rk[k0 + il], r, x[il]);
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int il = 0; il < 16; ++il)
+      Rl[(k0 + il) * kInvLd + j] = (j >= k0 + il && j < b && k0 + il < b) ? x[il] : 0.0;
+    __syncthreads();
+    for (int ti = p + 1; ti < 4; ++ti) {
+      for (int tj = ti; tj < 4; ++tj) {
+        doublex4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = Al[(16 * ti + 4 * v + lk) * kInvLd + 16 * tj + li];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int kk = k0 + 4 * st + lk;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Rl[kk * kInvLd + 16 * ti + li],
+                                                     Rl[kk * kInvLd + 16 * tj + li], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Al[(16 * ti + 4 * v + lk) * kInvLd + 16 * tj + li] = acc[v];
+      }
+    }
+    __syncthreads();
+  }
+  if (any_drop && j == 0) atomicOr(flags, 1);
+  // Rl: R[i][j] for i < j, F_jj = 1 / R_jj on the diagonal (0 for a dropped
+  // column, whose row of R is zero too); columns >= b are zero.  The solve
+  // y_c = F_cc (x_c - sum_{i<c} y_i R_ic) is linear in x: y = x M with M the
+  // inverse of R (rows and columns of dropped pivots zero, since F_kk = 0
+  // there).  M is formed here once, so that the row solve is a plain product.
   // diagonal 16 x 16 blocks by back substitution: lane j forms column j of
   // its block, M_jj = F_jj, M_ij = -F_ii sum_{i<k<=j} R_ik M_kj
   {
@@ -234,7 +274,6 @@ __global__ __launch_bounds__(64) void chol_kernel(const double *__restrict__ G, 
   // M_ab = -M_aa (sum_{a<c<=b} R_ac M_cb), as 16 x 16 products on the FP64
   // matrix cores (lane l: A (row l % 16, k l / 16), B (k l / 16, col l % 16),
   // result element v at (row 4 v + l / 16, col l % 16))
-  const int li = j & 15, lk = j >> 4;
   for (int d = 1; d < 4; ++d) {
     for (int a = 0; a + d < 4; ++a) {
       const int bb = a + d;
