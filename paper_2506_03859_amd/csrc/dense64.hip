@@ -9,6 +9,8 @@
 
 namespace farpca_int {
 
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -19,10 +21,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // part[blk][i][j] = sum over the rows of block blk of X[k][i] X[k][j] (FP64;
 // columns >= b read as zero), then G = sum of the partials in block order.
 // Up to kGramParts workgroups, each over a contiguous row range in chunks of
-// 64 rows staged in LDS; thread t owns the 4 x 4 sub-block
-// (4 (t / 16) .., 4 (t % 16) ..).
+// 128 rows staged in LDS (all of a chunk's loads in flight at once), products
+// on the FP64 matrix cores.
 constexpr int kGramParts = 256;
-constexpr int kGramChunk = 64;
+constexpr int kGramChunk = 128;   // rows staged per step: one step per workgroup up to 32768 rows
 
 int gram_max_partials() { return kGramParts; }
 
@@ -31,12 +33,14 @@ __global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ X, 
                                                    bool vec, double *__restrict__ part) {
   __shared__ float xs[kGramChunk][kMaxBlock + 1];
   const int t = threadIdx.x;
-  const int ti = (t >> 4) * 4, tj = (t & 15) * 4;
-  double acc[4][4];
+  // wave w forms the output blocks (w, 0 .. 3) (16 x 16 each) on the FP64
+  // matrix cores, K = the chunk's rows: lane l supplies X^T (row l % 16,
+  // k l / 16) and X (k l / 16, col l % 16); result element v of lane l is
+  // (row 4 v + l / 16, col l % 16).  FP32 values enter exactly.
+  const int w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  doublex4 acc[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+  for (int c = 0; c < 4; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
   const int64_t k_begin = (int64_t)blockIdx.x * rows_per_blk;
   int64_t k_end = k_begin + rows_per_blk;
   if (k_end > K) k_end = K;
@@ -59,21 +63,20 @@ __global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ X, 
       xs[r][c4 + 3] = (c4 + 3 < b) ? v.w : 0.0f;
     }
     __syncthreads();
-    for (int r = 0; r < nr; ++r) {
-      double xi[4], xj[4];
+    const int steps = (nr + 3) / 4;              // rows past nr are zero
+    for (int st = 0; st < steps; ++st) {
+      const int r = 4 * st + lk;
+      const double av = (double)xs[r][16 * w + li];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) { xi[a] = (double)xs[r][ti + a]; xj[a] = (double)xs[r][tj + a]; }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = fma(xi[a], xj[c], acc[a][c]);
+      for (int c = 0; c < 4; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, (double)xs[r][16 * c + li], acc[c], 0, 0, 0);
     }
   }
   double *o = part + (int64_t)blockIdx.x * kMaxBlock * kMaxBlock;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int c = 0; c < 4; ++c)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) o[(ti + a) * kMaxBlock + tj + c] = acc[a][c];
+    for (int v = 0; v < 4; ++v) o[(16 * w + 4 * v + lk) * kMaxBlock + 16 * c + li] = acc[c][v];
 }
 
 // G[e] = sum_q part[q][e] in a fixed order: workgroup g owns 16 entries; its
@@ -134,7 +137,6 @@ void launch_gram(const float *X, int64_t ldx, int64_t K, int b, double *part, do
 // One wave: lane j holds column j of the working matrix in registers; step k
 // broadcasts the pivot and row k of R through LDS and updates the trailing
 // columns.
-typedef double doublex4 __attribute__((ext_vector_type(4)));
 constexpr int kInvLd = kMaxBlock + 1;      // LDS stride of the factor and its inverse
 
 __device__ __forceinline__ double bcast_f64(double v, int lane) {
