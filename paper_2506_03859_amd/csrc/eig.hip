@@ -50,20 +50,43 @@ __device__ __forceinline__ int rr_player(int pos, int step, int n) {
   return pos == 0 ? 0 : ((pos - 1 + step) % (n - 1)) + 1;
 }
 
+// Rotation that (nearly) zeroes a_pq: t = tan(angle) from the hardware
+// reciprocal and square root (a few ulps off the exact angle, which only
+// leaves a tiny a_pq for the next sweep), then c = 1 / sqrt(1 + t^2) to full
+// FP64 accuracy (hardware reciprocal square root and one Newton step) and
+// s = t c, so that c^2 + s^2 = 1 to rounding and every update below is an
+// exact similarity.  Standard form: theta = (a_qq - a_pp) / (2 a_pq),
+// t = sign(theta) / (|theta| + sqrt(theta^2 + 1)); here multiplied through
+// by |2 a_pq|: t = sign(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp,
+// with d and 2 a_pq first scaled by about 1 / max(|d|, |2 a_pq|) (t depends
+// only on their ratio; the squares neither overflow nor underflow).
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double &c,
+                                                double &s) {
+  const double d0 = aqq - app, e0 = 2.0 * apq;
+  const double sc = __builtin_amdgcn_rcp(fmax(fabs(d0), fabs(e0)));   // a_pq != 0 here
+  const double d = d0 * sc, e = e0 * sc;
+  const double h = __builtin_amdgcn_sqrt(fma(d, d, e * e));
+  const double t = (d >= 0.0 ? e : -e) * __builtin_amdgcn_rcp(fabs(d) + h);
+  const double u = fma(t, t, 1.0);
+  double r = __builtin_amdgcn_rsq(u);
+  r = r * fma(-0.5 * u * r, r, 1.5);
+  c = r;
+  s = t * r;
+}
+
 // Cyclic Jacobi on an S x S symmetric matrix a (LDS, stride LD) accumulating
 // rotations into v (LDS, stride LD, holds the starting orthogonal matrix).
-// A step: threads 0 .. S/2 - 1 compute the step's rotations (c, s, t and
+// A step: threads 0 .. S/2 - 1 compute the step's rotations (c, s and
 // whether the pair is rotated at all) into LDS; then every thread applies
-// them to its 2 x 2 blocks of a and its row pairs of v.  The pairs of a step
-// follow from the step number alone, so the appliers compute them and read
-// the rotation together with the matrix entries (one LDS round trip); an
-// identity rotation is applied like any other (c = 1, s = 0 copy exactly),
-// only the diagonal blocks test it.
+// them to its 2 x 2 blocks of a (rows, then columns; the diagonal blocks
+// like the others) and its row pairs of v.  The pairs of a step follow from
+// the step number alone, so the appliers compute them and read the rotation
+// together with the matrix entries (one LDS round trip); an identity
+// rotation is applied like any other (c = 1, s = 0 copy exactly).
 template <int S, int LD, int NT>
 __device__ void jacobi_lds(double *a, double *v, double floor_abs, int max_sweeps, double rel) {
   constexpr int H = S / 2;
-  __shared__ double cs_c[H], cs_s[H], cs_t[H];
-  __shared__ int cs_on[H];
+  __shared__ double cs_c[H], cs_s[H];
   __shared__ int any_rot;
   const int tid = threadIdx.x;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
@@ -73,33 +96,17 @@ __device__ void jacobi_lds(double *a, double *v, double floor_abs, int max_sweep
       if (tid < H) {
         const int p = rr_player(tid, step, S), q = rr_player(S - 1 - tid, step, S);
         const double app = a[p * LD + p], aqq = a[q * LD + q], apq = a[p * LD + q];
-        double c = 1.0, s = 0.0, t = 0.0;
-        int on = 0;
+        double c = 1.0, s = 0.0;
         if (!negligible(apq, app, aqq, floor_abs, rel)) {
-          const double theta = (aqq - app) / (2.0 * apq);
-          t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(fma(theta, theta, 1.0)));
-          c = rsqrt(fma(t, t, 1.0));
-          s = t * c;
-          on = 1;
+          jacobi_rotation(app, aqq, apq, c, s);
           any_rot = 1;
         }
-        cs_c[tid] = c; cs_s[tid] = s; cs_t[tid] = t; cs_on[tid] = on;
+        cs_c[tid] = c; cs_s[tid] = s;
       }
       __syncthreads();
       for (int e = tid; e < H * H; e += NT) {
         const int ia = e / H, ib = e % H;
         const int pa = rr_player(ia, step, S), qa = rr_player(S - 1 - ia, step, S);
-        if (ia == ib) {
-          if (cs_on[ia]) {
-            const double apq = a[pa * LD + qa];
-            const double t = cs_t[ia];
-            a[pa * LD + pa] -= t * apq;
-            a[qa * LD + qa] += t * apq;
-            a[pa * LD + qa] = 0.0;
-            a[qa * LD + pa] = 0.0;
-          }
-          continue;
-        }
         const int pb = rr_player(ib, step, S), qb = rr_player(S - 1 - ib, step, S);
         const double ca = cs_c[ia], sa = cs_s[ia], cb = cs_c[ib], sb = cs_s[ib];
         const double x11 = a[pa * LD + pb], x12 = a[pa * LD + qb];
