@@ -621,13 +621,15 @@ __global__ __launch_bounds__(256) void gram_big_kernel(const float *__restrict__
   __shared__ float xi_s[kGramRows][65];
   __shared__ float xj_s[kGramRows][65];
   const int t = threadIdx.x;
-  const int ti = (t >> 4) * 4, tj = (t & 15) * 4;
+  // wave w forms rows 16 w .. 16 w + 15 of the 64 x 64 tile (four 16 x 16
+  // blocks) on the FP64 matrix cores, K = the staged rows (FP32 values enter
+  // exactly): lane l supplies X_i^T (row l % 16, k l / 16) and X_j (k l / 16,
+  // col l % 16); result element v of lane l is (row 4 v + l / 16, col l % 16).
+  const int w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
   const int64_t ci0 = (int64_t)ti_blk * 64, cj0 = (int64_t)tj_blk * 64;
-  double acc[4][4];
+  doublex4 acc[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+  for (int c = 0; c < 4; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
   const int64_t kb = (int64_t)blockIdx.z * rows_per_split;
   int64_t ke = kb + rows_per_split;
   if (ke > n) ke = n;
@@ -640,21 +642,20 @@ __global__ __launch_bounds__(256) void gram_big_kernel(const float *__restrict__
       xj_s[r][c] = (k < ke && cj0 + c < l) ? X[k * ldx + cj0 + c] : 0.0f;
     }
     __syncthreads();
-    for (int r = 0; r < kGramRows; ++r) {
-      double xi[4], xj[4];
+#pragma unroll 4
+    for (int st = 0; st < kGramRows / 4; ++st) {
+      const int r = 4 * st + lk;
+      const double av = (double)xi_s[r][16 * w + li];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) { xi[a] = (double)xi_s[r][ti + a]; xj[a] = (double)xj_s[r][tj + a]; }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = fma(xi[a], xj[c], acc[a][c]);
+      for (int c = 0; c < 4; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, (double)xj_s[r][16 * c + li], acc[c], 0, 0, 0);
     }
   }
   double *o = part + (int64_t)blockIdx.z * lp * lp;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int c = 0; c < 4; ++c)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) o[(ci0 + ti + a) * lp + cj0 + tj + c] = acc[a][c];
+    for (int v = 0; v < 4; ++v) o[(ci0 + 16 * w + 4 * v + lk) * lp + cj0 + 16 * c + li] = acc[c][v];
 }
 
 __global__ void gram_big_reduce_kernel(const double *__restrict__ part, int nsplit, int64_t l,

@@ -283,7 +283,8 @@ void gen_omega(const farpca_plan_s *pl, const Ws &w, int64_t j, hipStream_t st,
                uint64_t *mask = nullptr, uint64_t *neg = nullptr, float *dense = nullptr) {
   const bool lists = pl->kind != FARPCA_GAUSSIAN;
   launch_omega(omega_spec(pl), pl->prm.n, j, mask ? mask : w.at<uint64_t>(pl->off_mask),
-               neg ? neg : w.at<uint64_t>(pl->off_neg), dense ? dense : w.at<float>(pl->off_om),
+               neg ? neg : w.at<uint64_t>(pl->off_neg),
+               dense ? dense : (lists ? nullptr : w.at<float>(pl->off_om)),   // dense copy: Gaussian product only
                lists ? w.at<uint32_t>(pl->off_colptr) : nullptr,
                lists ? w.at<ChunkEntry>(pl->off_ent) : nullptr, sketch_lds_row_stride_bytes(), st);
 }

@@ -3,7 +3,8 @@
 // 64 rows of Omega_j (= 64 columns of A); one thread per row.
 //
 // Outputs per row r:   mask word (nonzero columns), negative-sign word
-//                      (bit c set iff entry (r, c) < 0), dense row (FP32).
+//                      (bit c set iff entry (r, c) < 0), dense row (FP32;
+//                      only if dense_out is given).
 // Outputs per chunk:   column lists (ascending row inside each column) that
 //                      the sketch kernel walks: colptr[c] .. colptr[c+1].
 #include "internal.h"
@@ -19,9 +20,7 @@ __global__ __launch_bounds__(64) void omega_kernel(OmegaSpec s, int64_t n, int64
                                                    uint32_t *__restrict__ colptr,
                                                    ChunkEntry *__restrict__ entries,
                                                    int lds_stride) {
-  __shared__ uint64_t rmask[kChunk];
   __shared__ float rval[kChunk][kMaxBlock + 1];
-  __shared__ uint32_t cstart[kMaxBlock + 1];
 
   const int t = threadIdx.x;
   const int64_t chunk = blockIdx.x;
@@ -67,7 +66,7 @@ __global__ __launch_bounds__(64) void omega_kernel(OmegaSpec s, int64_t n, int64
     }
     // Unscaled values (what the sketch accumulates) and the dense copy
     // (values computed in FP64, rounded once).
-    float *drow = dense_out + r * (int64_t)kBld;
+    float *drow = dense_out ? dense_out + r * (int64_t)kBld : nullptr;
     uint64_t negative = 0;
     for (int c = 0; c < b; ++c) {
       double v = 0.0, dv = 0.0;
@@ -84,52 +83,56 @@ __global__ __launch_bounds__(64) void omega_kernel(OmegaSpec s, int64_t n, int64
         default: v = on ? 1.0 : 0.0; dv = v; break;
       }
       rval[t][c] = (float)v;
-      drow[c] = (float)dv;
+      if (drow) drow[c] = (float)dv;
       if (dv < 0.0) negative |= 1ull << c;
     }
-    for (int c = b; c < kBld; ++c) drow[c] = 0.0f;
+    if (drow)
+      for (int c = b; c < kBld; ++c) drow[c] = 0.0f;
     mask_out[r] = mask;
     sign_out[r] = negative;
   }
-  rmask[t] = mask;
-  __syncthreads();
+  __syncthreads();                   // rval complete
   if (colptr == nullptr) return;
 
-  // Column lists of this chunk: thread t owns column c = t.
+  // Column lists of this chunk: thread t owns column c = t.  The rows of
+  // column c are the lanes whose mask has bit c: one ballot per column gives
+  // them as a bit set (ascending rows = ascending bits); the starts are an
+  // exclusive prefix sum over the lanes.
   const int c = t;
+  uint64_t colbits = 0;
+  for (int cc = 0; cc < kMaxBlock; ++cc) {
+    const uint64_t bal = __ballot(((mask >> cc) & 1ull) != 0ull);
+    if (c == cc) colbits = bal;
+  }
   uint32_t cnt = 0;
   if (c < b) {
-    for (int k = 0; k < kChunk; ++k) cnt += (uint32_t)((rmask[k] >> c) & 1ull);
+    cnt = (uint32_t)__popcll(colbits);
     cnt = (cnt + kListPad - 1) / kListPad * kListPad;     // padded to whole groups
   }
-  if (t == 0) cstart[0] = 0;
-  __syncthreads();
-  // exclusive prefix over columns (64 values, done by one thread in order)
-  __shared__ uint32_t counts[kMaxBlock];
-  counts[c] = cnt;
-  __syncthreads();
-  if (t == 0) {
-    uint32_t acc = 0;
-    for (int q = 0; q < kMaxBlock; ++q) { cstart[q] = acc; acc += counts[q]; }
-    cstart[kMaxBlock] = acc;
+  uint32_t incl = cnt;
+#pragma unroll
+  for (int off = 1; off < kMaxBlock; off <<= 1) {
+    const uint32_t v = __shfl_up(incl, off, kMaxBlock);
+    if (t >= off) incl += v;
   }
-  __syncthreads();
+  const uint32_t start = incl - cnt;
   uint32_t *cp = colptr + chunk * (kMaxBlock + 1);
-  cp[c] = cstart[c];
-  if (t == 0) cp[kMaxBlock] = cstart[kMaxBlock];
+  cp[c] = start;
+  if (t == kMaxBlock - 1) cp[kMaxBlock] = incl;
   if (c < b) {
     ChunkEntry *ent = entries + chunk * (int64_t)kEntCap;
-    uint32_t pos = cstart[c];
-    for (int k = 0; k < kChunk; ++k) {
-      if ((rmask[k] >> c) & 1ull) {
-        ChunkEntry e;
-        e.lds_off = (uint32_t)(k * lds_stride);
-        e.val = rval[k][c];
-        ent[pos++] = e;
-      }
+    uint32_t pos = start;
+    uint64_t rows = colbits;
+    while (rows) {
+      const int k = __ffsll((long long)rows) - 1;
+      rows &= rows - 1ull;
+      ChunkEntry e;
+      e.lds_off = (uint32_t)(k * lds_stride);
+      e.val = rval[k][c];
+      ent[pos++] = e;
     }
     const ChunkEntry pad = {0u, 0.0f};      // adds 0 * A[i, first column]: exact no-op
-    while (pos < cstart[c + 1]) ent[pos++] = pad;
+    while (pos < start + cnt) ent[pos++] = pad;
   }
 }
 
