@@ -24,5 +24,5 @@ from .omega import (  # noqa: F401
     threshold32, default_p, sketch_scale,
 )
 from .farpca import (  # noqa: F401
-    FarpcaParams, farpca, eig_svd, default_block, default_maxit, projection_svd,
+    FarpcaParams, farpca, eig_svd, default_block, default_maxit, projection_svd, truncation_rank,
 )

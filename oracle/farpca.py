@@ -222,3 +222,30 @@ def projection_svd(a: np.ndarray, y: np.ndarray) -> np.ndarray:
     keep = sv * sv > sv[0] * sv[0] * y.shape[1] * np.finfo(np.float64).eps
     q = u[:, keep]
     return np.linalg.svd(q.T @ np.asarray(a, dtype=np.float64), compute_uv=False)
+
+
+def truncation_rank(s: np.ndarray, err_indicator: float, norm_a2: float, tol: float) -> int:
+    """Post-processing for the fixed-precision problem (Section 5.4, after
+    Hallman's block method): the smallest rank r to which the computed SVD
+    U S V^T can be truncated while still meeting the tolerance.  With Q the
+    orthonormal basis behind U (U = Q U~), A - Q Q^T A is orthogonal to every
+    matrix with columns in range(Q), so the error of the rank-r truncation is
+    ||A - U_r S_r V_r^T||_F^2 = E + sum_{i >= r} s_i^2 (E the indicator,
+    singular values descending).  r is the smallest r with that error below
+    tol^2 ||A||_F^2, with the strict test of the stop rule (reading of the
+    stop test); len(s) when even r = len(s) fails it."""
+    s = np.asarray(s, dtype=np.float64)
+    thr = tol * tol * norm_a2
+    k = s.size
+    r = k
+    tail = 0.0
+    for i in range(k - 1, -1, -1):   # r = i is valid iff E + sum_{j >= i} s_j^2 < thr
+        tail += s[i] * s[i]
+        if err_indicator + tail < thr:
+            r = i
+        else:
+            break
+    if not (err_indicator < thr):
+        return k
+    return r
+
