@@ -85,6 +85,12 @@ typedef struct farpca_info {
   int32_t eig_sweeps;    /* Jacobi sweeps of the final eigendecomposition                     */
   int32_t dropped;       /* nonzero if a block direction was dropped as numerically dependent
                             (its column of U, V is zero and its singular value 0)     */
+  int64_t rank_trunc;    /* post-processing for the fixed-precision problem (Section 5.4, after
+                            Hallman's block method): the smallest r such that the first r
+                            singular triplets still meet the tolerance,
+                            E + sum_{i >= r} S_i^2 < tol^2 ||A||_F^2 (S descending; the rank-r
+                            truncation error, since A - Q Q^T A is orthogonal to range(Q)).
+                            rank_out when the run did not converge or in fixed-rank use.  */
 } farpca_info;
 
 typedef struct farpca_plan_s farpca_plan_t;

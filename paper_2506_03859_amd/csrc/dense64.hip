@@ -725,6 +725,33 @@ __global__ void sqrt_clip_kernel(const double *__restrict__ w, int64_t l, double
   if (i < l) s[i] = w[i] > 0.0 ? sqrt(w[i]) : 0.0;
 }
 
+// Truncation rank of the fixed-precision output (Section 5.4 post-processing):
+// scal[0] = ||A||_F^2, scal[1] = E; s (k values, descending).  The smallest r
+// with E + sum_{i >= r} s_i^2 < tol^2 ||A||_F^2, the sum accumulated from the
+// smallest value up and the scan stopped at the first r that fails; k when
+// E itself fails or when `fixed` (fixed-rank use).  One thread: k <= l_max.
+__global__ void trunc_rank_kernel(const double *__restrict__ s, int64_t k,
+                                  const double *__restrict__ scal, double tol, int fixed,
+                                  int64_t *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double thr = tol * tol * scal[0], e = scal[1];
+  int64_t r = k;
+  if (!fixed && e < thr) {
+    double tail = 0.0;
+    for (int64_t i = k - 1; i >= 0; --i) {
+      tail += s[i] * s[i];
+      if (e + tail < thr) r = i;
+      else break;
+    }
+  }
+  out[0] = r;
+}
+
+void launch_trunc_rank(const double *s, int64_t k, const double *scal, double tol, bool fixed,
+                       int64_t *out, hipStream_t st) {
+  hipLaunchKernelGGL(trunc_rank_kernel, dim3(1), dim3(64), 0, st, s, k, scal, tol, fixed ? 1 : 0, out);
+}
+
 void launch_sqrt_clip(const double *w, int64_t l, double *s, hipStream_t st) {
   hipLaunchKernelGGL(sqrt_clip_kernel, dim3((unsigned)((l + 255) / 256)), dim3(256), 0, st, w, l, s);
 }

@@ -201,7 +201,7 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   pl->off_v64 = c.take((size_t)kMaxBlock * kMaxBlock * 8);
   pl->off_setup = c.take((size_t)setup_num_partials(m) * 8);
   pl->off_sq = c.take((size_t)256 * 8);                               // <= 256 partials for any K
-  pl->off_scal = c.take(64);                        // nA2, E, alpha, flags
+  pl->off_scal = c.take(64);                        // nA2, E, alpha, flags, truncation rank
   pl->off_ehist = c.take((size_t)maxblk * 8);
   pl->off_kbig = c.take((size_t)lmax * lmax * 8);
   pl->off_eig = c.take(eig_workspace_bytes(lmax));
@@ -513,6 +513,7 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
     sweeps = eig_sym(Kbig, l, wfin, vfin, w.at<void>(pl->off_eig), kFinalEigRel, st);
   }
   launch_sqrt_clip(wfin, rout, dS, st);
+  launch_trunc_rank(dS, rout, scal, q.tol, q.rank > 0, reinterpret_cast<int64_t *>(scal + 4), st);
   // U = Q U~ (first rout columns)
   launch_convert_f64_f32(vfin, l, rout, l, nullptr, u32, rout, st);
   for (int64_t c0 = 0; c0 < rout; c0 += kBld) {
@@ -527,8 +528,8 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
     launch_gemm_nn(Ct, pl->ldq, u32 + c0, rout, static_cast<float *>(dV) + c0, pl->lmax, n, nc, l,
                    1.f, 0.f, 1, part, st);
   }
-  double h_tail[4];
-  HIP_OK(hipMemcpyAsync(h_tail, scal, 32, hipMemcpyDeviceToHost, st));
+  double h_tail[5];
+  HIP_OK(hipMemcpyAsync(h_tail, scal, 40, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   HIP_OK(hipGetLastError());
   if (g_prof.on) prof_resolve();
@@ -542,6 +543,7 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
     info->eig_sweeps = sweeps;
     int fl = 0;
     std::memcpy(&fl, &h_tail[3], sizeof(int));
+    std::memcpy(&info->rank_trunc, &h_tail[4], sizeof(int64_t));
     info->dropped = fl & 1;
   }
   return status;

@@ -162,6 +162,9 @@ void launch_eig_small(const double *K, int s, int ldk, double *w, double *Vout, 
 void launch_convert_f64_f32(const double *X, int64_t rows, int64_t cols, int64_t ldx,
                             const double *s, float *Y, int64_t ldy, hipStream_t st);
 void launch_sqrt_clip(const double *w, int64_t l, double *s, hipStream_t st);
+// rank_trunc of farpca_info into out[0] (device): see trunc_rank_kernel.
+void launch_trunc_rank(const double *s, int64_t k, const double *scal, double tol, bool fixed,
+                       int64_t *out, hipStream_t st);
 
 // ---- gram64 (big FP64 Gram for the final step): K = X^T X, X n x l FP32 (ldx)
 size_t gram_big_workspace_bytes(int64_t n, int64_t l);

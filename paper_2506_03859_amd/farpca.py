@@ -47,7 +47,8 @@ class FarpcaInfo(ctypes.Structure):
     _fields_ = [("rank_l", ctypes.c_int64), ("rank_out", ctypes.c_int64),
                 ("blocks", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("norm_a2", ctypes.c_double), ("err_indicator", ctypes.c_double),
-                ("eig_sweeps", ctypes.c_int32), ("dropped", ctypes.c_int32)]
+                ("eig_sweeps", ctypes.c_int32), ("dropped", ctypes.c_int32),
+                ("rank_trunc", ctypes.c_int64)]
 
 
 class FarpcaResult(ctypes.Structure):

@@ -274,3 +274,43 @@ def test_bf16_matches_fp32_path_on_same_values(fp, a_mid):
     s16, s32 = r16.S.cpu().numpy(), r32.S.cpu().numpy()
     assert np.max(np.abs(s16 - s32)) <= 1e-6 * s32[0]
     assert abs(r16.info.err_indicator - r32.info.err_indicator) <= 1e-7 * r32.info.norm_a2
+
+
+@pytest.mark.parametrize("tol,sketch,p,zeta", [(1e-2, "sparse_sign", 0.0, 4), (3e-2, "std_bernoulli", 0.0, 0),
+                                               (5e-3, "sparse_gaussian", 0.05, 0)])
+def test_truncation_rank(fp, tol, sketch, p, zeta):
+    # post-processing (Section 5.4): rank_trunc is the oracle's rule on the
+    # GPU's own S and E (same arithmetic order, so equal), its truncation meets
+    # the tolerance and one fewer triplet does not (direct residuals in FP64 of
+    # the FP32 factors), and it agrees with the oracle's own run up to a tie
+    from oracle import truncation_rank
+    a32 = synth.spectral(1500, 1000, np.arange(1, 1001, dtype=np.float64) ** -1.5, seed=8).astype(np.float32)
+    res, ref = run_both(fp, a32, tol=tol, block=20, power=1, sketch=sketch, p=p, zeta=zeta, seed=6)
+    assert res.status == 0
+    S = res.S.cpu().numpy()
+    r = res.info.rank_trunc
+    assert r == truncation_rank(S, res.info.err_indicator, res.info.norm_a2, tol)
+    assert 0 < r < res.info.rank_out
+    a = a32.astype(np.float64)
+    U = res.U.cpu().double().numpy()
+    V = res.V.cpu().double().numpy()
+    thr = tol * tol * res.info.norm_a2
+
+    def resid(k):
+        return float(np.sum((a - (U[:, :k] * S[:k]) @ V[:, :k].T) ** 2))
+
+    print(f"  l={res.info.rank_l} r={r} resid(r)/thr={resid(r) / thr:.6f} resid(r-1)/thr={resid(r - 1) / thr:.6f}",
+          flush=True)
+    assert resid(r) < thr * (1 + 1e-5)
+    assert resid(r - 1) >= thr * (1 - 1e-5)
+    r_or = truncation_rank(ref.S, ref.err_indicator, ref.norm_a2, tol)
+    if r != r_or:
+        # a tie: the oracle's truncation error at the GPU's rank sits at the threshold
+        tail = ref.err_indicator + float(np.sum(ref.S[min(r, r_or):] ** 2))
+        assert abs(r - r_or) == 1 and abs(tail - thr) <= 1e-3 * thr, (r, r_or, tail / thr)
+
+
+def test_truncation_rank_fixed_rank(fp):
+    a32 = synth.spectral(600, 400, np.arange(1, 401, dtype=np.float64) ** -1.5, seed=2).astype(np.float32)
+    res, _ = run_both(fp, a32, rank=30, block=10, power=1, sketch="sparse_sign", zeta=4, seed=3)
+    assert res.info.rank_out == 30 and res.info.rank_trunc == 30
