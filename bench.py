@@ -296,6 +296,52 @@ def serve_bench(args, dev):
     print(json.dumps(line), flush=True)
 
 
+def stability_bench(args, dev):
+    """Section 5.5 stability experiment: Matrix 1 form (sigma_j = j^-2, n x n)
+    with block-diagonal right singular vectors (d Haar blocks of size n / d,
+    d = 1, n / 10, n), tol 1e-4, b by the default rule, P = 1, at most
+    ceil(n / 2b) blocks; for each test matrix and p in {ln(n)/n, 2e-3, 1e-2},
+    `trials` solves with seeds 1..trials.  A solve succeeds when it reaches
+    the tolerance within the block cap (status 0).  One JSON line with the
+    success rates (percent) and the mean blocks per solve."""
+    import numpy as np
+    import torch
+    from paper_2506_03859_amd import farpca as fp
+    from paper_2506_03859_amd import synth
+    n, trials, tol = args.stability_n, args.stability_trials, 1e-4
+    ds = [1, n // 10, n]
+    ps = [("ln(n)/n", math.log(n) / n), ("2e-3", 2e-3), ("1e-2", 1e-2)]
+    sketches = [("SB", "std_bernoulli"), ("SS", "sparse_sign"), ("SG", "sparse_gaussian"), ("B", "bernoulli")]
+    table = {}
+    blocks = {}
+    t_start = time.perf_counter()
+    for d in ds:
+        log(f"stability: generating {n} x {n}, d = {d}")
+        A = synth.spectral_blockdiag_v_torch(n, synth.matrix1_sigma(n), d, seed=11, device=dev)
+        A = A.to(torch.float32).contiguous()
+        torch.cuda.synchronize()
+        for pname, pv in ps:
+            for short, sk in sketches:
+                ok, nb = 0, 0
+                for t in range(1, trials + 1):
+                    res = fp.solve(A, tol=tol, power=1, sketch=sk, p=pv, seed=t)
+                    ok += int(res.status == 0)
+                    nb += res.info.blocks
+                table[f"{short} p={pname} d={d}"] = 100.0 * ok / trials
+                blocks[f"{short} p={pname} d={d}"] = nb / trials
+                log(f"stability: {short} p={pname} d={d}: {ok}/{trials} converged, "
+                    f"{nb / trials:.1f} blocks on average")
+        del A
+        torch.cuda.empty_cache()
+    line = {"metric": "success rate (converged within ceil(n/2b) blocks)", "unit": "percent",
+            "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": f"stability_matrix1_{n}x{n}_blockdiagV", "tol": tol, "power": 1,
+                       "trials": trials, "d": ds, "p": [pn for pn, _ in ps]},
+            "success_percent": table, "mean_blocks": blocks,
+            "wall_s": time.perf_counter() - t_start}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +360,11 @@ def main():
     ap.add_argument("--serve-hw-queues", type=int, default=0,
                     help="hardware queues of the process (GPU_MAX_HW_QUEUES, set before the HIP "
                          "runtime starts; 0 = the runtime's default)")
+    ap.add_argument("--stability", action="store_true",
+                    help="the Section 5.5 stability experiment (block-diagonal right singular "
+                         "vectors, success rates per test matrix, p and d)")
+    ap.add_argument("--stability-n", type=int, default=5000)
+    ap.add_argument("--stability-trials", type=int, default=20)
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only launch the kernels that stream A (A-pass products, sparse sketch) "
                          "on a random matrix of the workload's shape, plus a 1 GiB copy: the "
@@ -339,6 +390,9 @@ def main():
         return
     if args.serve:
         serve_bench(args, dev)
+        return
+    if args.stability:
+        stability_bench(args, dev)
         return
     m, n, _, _, tol, b, P, sketch, zeta, p, storage = WORKLOADS[wl]
     rank = 200 if tol == 0.0 else 0

@@ -15,6 +15,9 @@ Constructions (all seeded, numpy PCG64 unless stated):
 * ``exp_floor_spectrum``: sigma_i = exp(-i/50) + 1e-6 (additive floor).
 * ``tall_lowrank``: L diag(1/i) R + N with Gaussian L (m x r), R (r x n) and
   i.i.d. N(0, var) noise, the tall fixed-rank workload.
+* ``spectral_blockdiag_v``: A = U diag(sigma) V^T with U Haar and V block
+  diagonal, d Haar blocks of size n/d (Section 5.5: the right singular
+  vectors are sparse when d is large; V is diagonal, +-1, for d = n).
 * ``integer_matrix``: small-integer-valued matrices, for which any ordering
   of a short FP32 sum is exact.
 * ``bf16_bits`` / ``bf16_value``: BF16 storage of an FP32 matrix (round to
@@ -71,6 +74,47 @@ def spectral_torch(m: int, n: int, sigma: np.ndarray, seed: int, device: str = "
     v = haar_t(n, k)
     s = torch.from_numpy(sigma).to(device)
     return (u * s[None, :]) @ v.T
+
+
+def spectral_blockdiag_v(n: int, sigma: np.ndarray, d: int, seed: int) -> np.ndarray:
+    """n x n A = U diag(sigma) V^T in float64: U Haar (n x n), V block diagonal
+    with d Haar blocks of size n / d (d divides n), drawn after U from the same
+    stream, block by block."""
+    sigma = np.asarray(sigma, dtype=np.float64)
+    assert sigma.shape[0] == n and n % d == 0
+    rng = _rng(seed)
+    u = haar_columns(n, n, rng)
+    w = n // d
+    us = u * sigma[None, :]
+    a = np.empty((n, n))
+    for j in range(d):
+        vj = haar_columns(w, w, rng)
+        a[:, j * w:(j + 1) * w] = us[:, j * w:(j + 1) * w] @ vj.T
+    return a
+
+
+def spectral_blockdiag_v_torch(n: int, sigma: np.ndarray, d: int, seed: int, device: str = "cpu"):
+    """Same construction as ``spectral_blockdiag_v`` (same draws from the same
+    stream) with the QRs and products done by torch in float64 on ``device``."""
+    import torch
+
+    sigma = np.asarray(sigma, dtype=np.float64)
+    assert sigma.shape[0] == n and n % d == 0
+    rng = _rng(seed)
+    w = n // d
+
+    def haar_t(g):
+        q, r = torch.linalg.qr(g, mode="reduced")
+        sg = torch.sign(torch.diagonal(r, dim1=-2, dim2=-1))
+        sg[sg == 0] = 1.0
+        return q * sg[..., None, :]
+
+    u = haar_t(torch.from_numpy(rng.standard_normal((n, n))).to(device))
+    g = np.stack([rng.standard_normal((w, w)) for _ in range(d)])
+    v = haar_t(torch.from_numpy(g).to(device))                     # d x w x w
+    us = u * torch.from_numpy(sigma).to(device)[None, :]
+    a = torch.bmm(us.reshape(n, d, w).transpose(0, 1).contiguous(), v.transpose(1, 2).contiguous())
+    return a.transpose(0, 1).reshape(n, n)
 
 
 def matrix1_sigma(n: int) -> np.ndarray:

@@ -51,7 +51,7 @@ def run_both(fp, a32, **kw):
     return res, ref
 
 
-def compare(res, ref, a32, tol_rec=2e-5):
+def compare(res, ref, a32, tol_rec=2e-5, v_rel=1e-5):
     a = a32.astype(np.float64)
     nA = np.linalg.norm(a)
     assert abs(res.info.norm_a2 - ref.norm_a2) <= 1e-12 * ref.norm_a2
@@ -65,7 +65,7 @@ def compare(res, ref, a32, tol_rec=2e-5):
     assert np.all(U[:, kg:] == 0) and np.all(V[:, kg:] == 0)
     U, S, V = U[:, :kg], S[:kg], V[:, :kg]
     assert np.abs(U.T @ U - np.eye(kg)).max() < 1e-5
-    nz = S > S[0] * 1e-5
+    nz = S > S[0] * v_rel       # V = C^T U~ S^-1 carries the FP32 error of C times s_1 / s_i
     assert np.abs(V[:, nz].T @ V[:, nz] - np.eye(nz.sum())).max() < 1e-4
     rec_g = (U * S) @ V.T
     rec_o = (ref.U * ref.S) @ ref.V.T
@@ -314,3 +314,43 @@ def test_truncation_rank_fixed_rank(fp):
     a32 = synth.spectral(600, 400, np.arange(1, 401, dtype=np.float64) ** -1.5, seed=2).astype(np.float32)
     res, _ = run_both(fp, a32, rank=30, block=10, power=1, sketch="sparse_sign", zeta=4, seed=3)
     assert res.info.rank_out == 30 and res.info.rank_trunc == 30
+
+
+@pytest.mark.parametrize("d", [1, 40, 400])
+@pytest.mark.parametrize("sketch", ["std_bernoulli", "sparse_sign", "sparse_gaussian", "bernoulli"])
+def test_stability_blockdiag_v(fp, d, sketch):
+    # Section 5.5 inputs (V_A block diagonal with d Haar blocks) at p = ln(n)/n.
+    # With a sparse V_A and a small p the sketch is often rank deficient
+    # (directions dropped as dependent) and ill-conditioned, so the FP32 and
+    # FP64 bases differ by more than in the well-conditioned cases and the
+    # outputs are not compared entry by entry.  What the section measures is
+    # compared: the same convergence outcome, the rank within two blocks; and
+    # the GPU result is checked on its own: its indicator is
+    # the true residual of its basis, its approximation meets the tolerance up
+    # to the indicator's FP32 accuracy, U is orthonormal.
+    n, tol, b = 400, 1e-2, 20
+    a32 = synth.spectral_blockdiag_v(n, synth.matrix1_sigma(n), d, seed=7).astype(np.float32)
+    a = a32.astype(np.float64)
+    for seed in (0, 1):
+        res, ref = run_both(fp, a32, tol=tol, block=b, power=1, sketch=sketch, p=math.log(n) / n,
+                            seed=seed)
+        thr = tol * tol * ref.norm_a2
+        assert res.status == ref.status == 0
+        # the stop can come a block or two apart (the FP32 rank-1 correction of
+        # the standardized Bernoulli sketch, A B_j - z, cancels most when V_A
+        # is diagonal)
+        assert abs(res.info.rank_l - ref.rank) <= 2 * b
+        U = res.U.cpu().double().numpy()
+        S = res.S.cpu().numpy()
+        V = res.V.cpu().double().numpy()
+        kg = int(np.sum(S > 0))
+        U, S, V = U[:, :kg], S[:kg], V[:, :kg]
+        assert np.abs(U.T @ U - np.eye(kg)).max() < 1e-4        # FP32 basis, ill-conditioned blocks
+        true_e = np.linalg.norm(a - U @ (U.T @ a)) ** 2
+        # FP32 basis orthogonality on these ill-conditioned blocks: 5e-7 ||A||^2
+        assert abs(res.info.err_indicator - true_e) <= 5e-7 * ref.norm_a2 + 1e-3 * true_e
+        err = np.linalg.norm(a - (U * S) @ V.T) ** 2
+        print(f"  l={res.info.rank_l} (oracle {ref.rank}) kept={kg} E/thr={res.info.err_indicator / thr:.3f} "
+              f"err/thr={err / thr:.3f}", flush=True)
+        # met up to the FP32 accuracy of the indicator the stop test used
+        assert err < thr + 5e-7 * ref.norm_a2
