@@ -141,6 +141,44 @@ __device__ __forceinline__ void load_a_tail(const float *__restrict__ A, int64_t
 // number f = tid + 256 j (chunk row f / 16, columns 4 (f % 16) .. +3).
 // XVEC (N == 64, rows 16-byte aligned) and rows inside K: one 16-byte load;
 // otherwise clamped scalar loads, zero outside K x N.
+// NN with WM = 4 (the A-passes A G): a wave's 64 rows x 32 K of a chunk are
+// read as 8 rows x 128 contiguous bytes per instruction (lane l: row
+// 8 q + l / 8, K 4 (l % 8) .. + 3) - twice the row piece of the MFMA operand
+// layout, which the memory system serves faster - and regrouped through a
+// wave-private LDS area into that layout: row r, K group g (4 floats) at
+// r * 32 + 4 (g ^ (r % 8)); the XOR keeps both the 8-lane row writes and the
+// 16-row column reads bank-conflict free without padding.
+constexpr int kStageRowF = 32;   // floats per staged row (one chunk of K)
+__device__ __forceinline__ int stage_off(int r, int g) { return r * kStageRowF + 4 * (g ^ (r & 7)); }
+
+__device__ __forceinline__ void load_a_runs(const float *__restrict__ A, int64_t lda, int64_t M,
+                                            int64_t t0, int lane, int64_t kc, float4 (&r)[2][4]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t row = clampi(t0 + 8 * q + (lane >> 3), M - 1);
+    const floatx4 v = *reinterpret_cast<const floatx4 *>(A + row * lda + kc + 4 * (lane & 7));
+    r[q >> 2][q & 3] = make_float4(v[0], v[1], v[2], v[3]);   // element copies: no struct memcpy
+  }
+}
+
+__device__ __forceinline__ void stage_in(float *wst, int lane, const float4 (&r)[2][4]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const float4 &v = r[q >> 2][q & 3];
+    *reinterpret_cast<floatx4 *>(wst + stage_off(8 * q + (lane >> 3), lane & 7)) = floatx4{v.x, v.y, v.z, v.w};
+  }
+}
+
+// The MFMA operand of slice s, row tile rt: row 16 rt + li, K 16 s + 4 lk .. + 3
+// (the same values load_a_full reads for NN).
+__device__ __forceinline__ void stage_out(const float *wst, int li, int lk, int s, float4 (&a)[4]) {
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) {
+    const floatx4 v = *reinterpret_cast<const floatx4 *>(wst + stage_off(16 * rt + li, 4 * s + lk));
+    a[rt] = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
 template <int NX, bool XVEC>
 __device__ __forceinline__ void load_x(const float *__restrict__ X, int64_t ldx, int64_t N,
                                        int64_t ke, int64_t kc, int tid, bool full,
@@ -203,8 +241,10 @@ __device__ __forceinline__ void mma_slice(floatx4 (&acc)[16], const float4 (&a)[
   }
 }
 
+// Occupancy: 3 blocks per CU, except the staged NN form, whose two register
+// copies of a chunk plus the accumulators need up to 2 blocks' worth of VGPRs.
 template <bool TN, int WM, bool AVEC, bool XVEC>
-__global__ __launch_bounds__(256, AVEC ? 3 : 2) void gemm_kernel(const float *__restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256, (AVEC && (TN || WM != 4)) ? 3 : 2) void gemm_kernel(const float *__restrict__ A, int64_t lda,
                                                       const float *__restrict__ X, int64_t ldx,
                                                       float *__restrict__ C, int64_t ldc,
                                                       int64_t M, int64_t N, int64_t K,
@@ -216,7 +256,10 @@ __global__ __launch_bounds__(256, AVEC ? 3 : 2) void gemm_kernel(const float *__
   constexpr int KW = 16 * SL;             // K rows per wave per chunk
   constexpr int KC = KW * WK;             // skinny rows per staged chunk
   constexpr int NX = KC / 16;             // skinny float4 loads per thread per chunk
+  constexpr bool STAGE = !TN && WM == 4 && AVEC;
+  static_assert(!STAGE || (SL == 2 && KC == kStageRowF), "staging covers one 32-deep chunk");
   __shared__ float xs[2][KC * kXs];
+  __shared__ float ast[STAGE ? 4 * 64 * kStageRowF : 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wk = wave / WM;
@@ -238,21 +281,39 @@ __global__ __launch_bounds__(256, AVEC ? 3 : 2) void gemm_kernel(const float *__
   // fetched (A into `nxt`, skinny rows into `xr`) before the MFMAs of chunk
   // c; the scheduling barriers keep the compiler from sinking those loads
   // below the MFMAs, which would serialise memory latency and compute.
+  // STAGE: `a` receives the 8 row pieces (row-piece layout), not MFMA operands
   float4 cur[SL][4], nxt[SL][4], xr[NX];
+  float *wst = ast + (STAGE ? wave * 64 * kStageRowF : 0);
   auto fetch = [&](int64_t c, float4 (&a)[SL][4]) {
     const int64_t kc = kb + c * KC;
     load_x<NX, XVEC>(X, ldx, N, ke, kc, tid, true, xr);
+    if constexpr (STAGE) {
+      load_a_runs(A, lda, M, t0, lane, kc, a);
+    } else {
 #pragma unroll
-    for (int s = 0; s < SL; ++s)
-      load_a_full<TN, AVEC>(ab, lda, M, t0, li, kc + KW * wk + 16 * s, a[s]);
+      for (int s = 0; s < SL; ++s)
+        load_a_full<TN, AVEC>(ab, lda, M, t0, li, kc + KW * wk + 16 * s, a[s]);
+    }
   };
   auto mma_chunk = [&](int64_t c) {
 #pragma unroll
     for (int s = 0; s < SL; ++s) mma_slice<TN>(acc, cur[s], xs[c & 1] + (KW * wk + 16 * s) * kXs, li, lk);
   };
+  // STAGE: the staged chunk is read back into `cur` right after the
+  // barrier (reading it slice by slice between the MFMAs measured slower)
+  auto unstage = [&]() {
+#pragma unroll
+    for (int s = 0; s < SL; ++s) stage_out(wst, li, lk, s, cur[s]);
+  };
 
   if (nfull > 0) {
-    fetch(0, cur);
+    if constexpr (STAGE) {
+      fetch(0, nxt);
+      stage_in(wst, lane, nxt);
+      unstage();
+    } else {
+      fetch(0, cur);
+    }
     store_x<NX>(xs[0], tid, xr);
     __syncthreads();
     for (int64_t c = 0; c + 1 < nfull; ++c) {
@@ -261,11 +322,18 @@ __global__ __launch_bounds__(256, AVEC ? 3 : 2) void gemm_kernel(const float *__
       mma_chunk(c);
       __builtin_amdgcn_sched_barrier(0);
       store_x<NX>(xs[(c + 1) & 1], tid, xr);
+      // wave-private area: the wave's reads of chunk c precede these writes
+      // in its own program order
+      if constexpr (STAGE) stage_in(wst, lane, nxt);
       __syncthreads();
+      if constexpr (STAGE) {
+        unstage();
+      } else {
 #pragma unroll
-      for (int s = 0; s < SL; ++s)
+        for (int s = 0; s < SL; ++s)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cur[s][q] = nxt[s][q];
+          for (int q = 0; q < 4; ++q) cur[s][q] = nxt[s][q];
+      }
     }
     mma_chunk(nfull - 1);
     __syncthreads();
