@@ -46,7 +46,16 @@ WORKLOADS = {
                                            0.0, "bf16"),
     "exp50_20000x15000_ss8_tol1e-2": (20000, 15000, "exp50", 2, 1e-2, 64, 2, "sparse_sign", 8, 0.0,
                                       "f32"),
+    # the paper's sparse regime (p = 1e-3, about 15 nonzeros per column of
+    # Omega_j) with A stored column-major, so that the sketch gathers only the
+    # columns Omega_j touches; and the same solve on row-major A
+    "col_exp50_20000x15000_sg1e-3": (20000, 15000, "exp50", 2, 1e-2, 64, 2, "sparse_gaussian", 0,
+                                     1e-3, "f32"),
+    "exp50_20000x15000_sg1e-3": (20000, 15000, "exp50", 2, 1e-2, 64, 2, "sparse_gaussian", 0, 1e-3,
+                                 "f32"),
 }
+# storage order of A (default row-major)
+LAYOUTS = {"col_exp50_20000x15000_sg1e-3": "col"}
 
 
 def log(msg):
@@ -68,6 +77,8 @@ def make_matrix(name, device):
         a = torch.from_numpy(synth.tall_lowrank(m, n, 100, 1e-6, seed, dtype=np.float32)).to(device)
     if storage == "bf16":
         a = a.to(torch.bfloat16).contiguous()     # round to nearest even
+    if LAYOUTS.get(name, "row") == "col":
+        a = a.t().contiguous().t()                # column-major view (A^T row-major in memory)
     torch.cuda.synchronize()
     return a
 
@@ -402,7 +413,8 @@ def main():
 
     nruns = args.warmup + args.steps
     plans = [fp.farpca_plan(fp.make_params(m, n, tol=tol, rank=rank, block=b, power=P, sketch=sketch,
-                                           p=p, zeta=zeta, seed=1000 + r, a_dtype=storage))
+                                           p=p, zeta=zeta, seed=1000 + r, a_dtype=storage,
+                                           layout=LAYOUTS.get(wl, "row")))
              for r in range(nruns)]
     work, U, S, V, eh = fp.alloc_outputs(plans[0], dev)
     if args.copy_probe:
@@ -469,15 +481,31 @@ def main():
         alg_per_launch = a_bytes + 4.0 * m * b
     else:
         alg_per_launch = a_bytes if storage == "bf16" else gemm_flops
+    layout = LAYOUTS.get(wl, "row")
     traffic_key = dom if storage == "f32" else f"{dom}_bf16"
     roof.update({"avg_launch_ms": a_ms, "launches": cnt, "algorithmic_per_launch": alg_per_launch,
-                 "traffic": measured_traffic(traffic_key)})
+                 "traffic": measured_traffic(traffic_key) if layout == "row" else None})
+    if layout == "col" and dom != "sketch":
+        # A^T row-major: the logical A^T Y runs on the NN kernel, A G on the TN one
+        roof["kernel"] = f"{dom} as the {'NN' if dom == 'gemm_tn' else 'TN'} kernel on A^T"
+    if layout == "col" and dom == "sketch":
+        roof["kernel"] = "sketch_cols_kernel"
+        alg_per_launch = 4.0 * m * (p * n * b) + 4.0 * m * b
+        roof["algorithmic_per_launch"] = alg_per_launch
+        roof["achieved"] = alg_per_launch / (a_ms * 1e-3) / 1e9
+        roof["frac"] = roof["achieved"] / PEAK_HBM_GBPS
     classes = {}
     for c, (tot, cnt) in prof.items():
         classes[c] = {"total_ms_per_solve": tot / args.steps, "launches": cnt,
                       "avg_launch_ms": (tot / cnt if cnt else None)}
     sk_ms, _ = avg("sketch")
-    sketch_gbps = (a_bytes + 4.0 * m * b) / (sk_ms * 1e-3) / 1e9 if sk_ms else None
+    # algorithmic bytes of one sketch: all of A row-major; column-major, the
+    # columns Omega_j touches (expected nnz(Omega_j) = p n b for the i.i.d. kinds)
+    if layout == "col" and zeta == 0 and sketch != "gaussian":
+        sk_bytes = 4.0 * m * (p * n * b) + 4.0 * m * b
+    else:
+        sk_bytes = a_bytes + 4.0 * m * b
+    sketch_gbps = sk_bytes / (sk_ms * 1e-3) / 1e9 if sk_ms else None
     for c in ("gemm_tn", "gemm_nn"):
         if classes[c]["avg_launch_ms"]:
             classes[c]["tflops"] = gemm_flops / (classes[c]["avg_launch_ms"] * 1e-3) / 1e12
@@ -499,7 +527,8 @@ def main():
         "dtype": "f32" if storage == "f32" else "bf16",
         "data": "synthetic",
         "config": {"workload": wl, "m": m, "n": n, "tol": tol, "rank": rank, "block": b, "power": P,
-                   "sketch": sketch, "zeta": zeta, "p": p, "a_storage": storage, "blocks": sorted(set(blocks)), "l": sorted(set(ls)),
+                   "sketch": sketch, "zeta": zeta, "p": p, "a_storage": storage, "a_layout": layout,
+                   "blocks": sorted(set(blocks)), "l": sorted(set(ls)),
                    "parallelism": "single GPU"},
         "roofline": roof,
         "kernels": classes,

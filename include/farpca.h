@@ -57,8 +57,20 @@ extern "C" {
  * by the storage error ||A - A_bf16||_F / ||A||_F (unit roundoff 2^-8; about 2e-3 for generic data). */
 #define FARPCA_DTYPE_BF16 1
 
+/* Storage order of A */
+#define FARPCA_LAYOUT_ROW 0  /* row-major: element (i, k) at dA[i * lda + k], lda >= n             */
+/* Column-major (A^T row-major): element (i, k) at dA[k * lda + i], lda >= m; FP32 only.  The
+ * sparse sketch then gathers whole columns of A: it reads the columns that Omega_j touches,
+ * nnz(Omega_j) m elements rather than m n (Section 3, the cost of A B_j), which is the layout the
+ * paper's sparse test matrices with p near 1e-3 pay off in.  The sketch reads each column of A
+ * once per nonzero in its row of Omega_j, so this layout suits few nonzeros per row (a sparse
+ * sign matrix with zeta = 8 reads A 8 times over).  The A-passes and the setup run as the
+ * transposed products / column sums of the stored matrix; the results equal the row-major
+ * path's up to FP32 accumulation order. */
+#define FARPCA_LAYOUT_COL 1
+
 typedef struct farpca_params {
-  int64_t m, n, lda;   /* A is m x n, row-major, leading dimension lda >= n                  */
+  int64_t m, n, lda;   /* A is m x n, leading dimension lda (>= n row-major, >= m column-major) */
   int32_t a_dtype;     /* FARPCA_DTYPE_F32 or FARPCA_DTYPE_BF16                              */
   int32_t sketch;      /* FARPCA_GAUSSIAN ... FARPCA_BERNOULLI                               */
   double tol;          /* relative Frobenius tolerance eps > 0 (fixed precision, Section 5.2):
@@ -71,7 +83,7 @@ typedef struct farpca_params {
                           FARPCA_STD_BERNOULLI, p2 = max(1e-3, 10/N) otherwise, N = max(m,n) */
   int32_t sketch_zeta; /* FARPCA_SPARSE_SIGN: zeta in [1, b] nonzeros +-1/sqrt(zeta) per row
                           of Omega_j; 0 = i.i.d. entries of Definition 2.2                   */
-  int32_t reserved0;
+  int32_t a_layout;    /* FARPCA_LAYOUT_ROW (0) or FARPCA_LAYOUT_COL                         */
   uint64_t seed;       /* key of the counter-based generator (Philox4x64-10)                 */
 } farpca_params;
 

@@ -54,6 +54,7 @@ static constexpr double kFinalEigRel = 1e-8;
 struct farpca_plan_s {
   farpca_params prm;
   bool bf16;            // A holds BF16 bit patterns (precision form)
+  bool colmajor;        // A stored column-major (FARPCA_LAYOUT_COL)
   int b;
   int P;
   int kind;
@@ -70,7 +71,7 @@ struct farpca_plan_s {
   size_t off_q, off_ct, off_s, off_y, off_x, off_g, off_om, off_mask, off_neg, off_colptr,
       off_ent, off_z, off_rowsum, off_r, off_part, off_gpart, off_g64, off_rinv, off_w64,
       off_v64, off_setup, off_sq, off_scal, off_ehist, off_kbig, off_eig, off_wfin, off_vfin,
-      off_u32, off_gbig, off_xt, total;
+      off_u32, off_gbig, off_xt, off_flat, off_colcnt, total;
   size_t gbig_bytes;
   int64_t part_floats;  // capacity of the K-split partial buffer
   // K splits the partial buffer holds for an M-row product
@@ -124,8 +125,11 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   if (!prm || !out) return FARPCA_E_INVALID;
   *out = nullptr;
   const farpca_params &q = *prm;
-  if (q.m < 1 || q.n < 1 || q.lda < q.n) return FARPCA_E_INVALID;
+  if (q.a_layout != FARPCA_LAYOUT_ROW && q.a_layout != FARPCA_LAYOUT_COL) return FARPCA_E_INVALID;
+  const bool colmajor = q.a_layout == FARPCA_LAYOUT_COL;
+  if (q.m < 1 || q.n < 1 || q.lda < (colmajor ? q.m : q.n)) return FARPCA_E_INVALID;
   if (q.a_dtype != FARPCA_DTYPE_F32 && q.a_dtype != FARPCA_DTYPE_BF16) return FARPCA_E_INVALID;
+  if (colmajor && q.a_dtype != FARPCA_DTYPE_F32) return FARPCA_E_INVALID;
   if (q.sketch < FARPCA_GAUSSIAN || q.sketch > FARPCA_BERNOULLI) return FARPCA_E_INVALID;
   if (q.block < 0 || q.block > kMaxBlock || q.power < 0 || q.power > 64) return FARPCA_E_INVALID;
   if (q.rank < 0 || q.max_blocks < 0) return FARPCA_E_INVALID;
@@ -143,6 +147,7 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   if (!pl) return FARPCA_E_INVALID;
   pl->prm = q;
   pl->bf16 = q.a_dtype == FARPCA_DTYPE_BF16;
+  pl->colmajor = colmajor;
   pl->b = b;
   pl->P = q.power;
   pl->kind = q.sketch;
@@ -190,7 +195,7 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   pl->off_colptr = c.take((size_t)pl->nchunks * (kMaxBlock + 1) * 4);
   pl->off_ent = c.take((size_t)pl->nchunks * kEntCap * sizeof(ChunkEntry));
   pl->off_z = c.take((size_t)m * 4);
-  pl->off_rowsum = c.take((size_t)m * 8);
+  pl->off_rowsum = c.take((size_t)imax(m, n) * 8);   // column-major setup: n stored rows
   pl->off_r = c.take((size_t)ldq * kBld * 4);
   pl->part_floats = 16 * mnl * kBld;
   pl->off_part = c.take((size_t)pl->part_floats * 4);
@@ -199,7 +204,7 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   pl->off_rinv = c.take((size_t)kMaxBlock * kMaxBlock * 8);
   pl->off_w64 = c.take((size_t)kMaxBlock * 8);
   pl->off_v64 = c.take((size_t)kMaxBlock * kMaxBlock * 8);
-  pl->off_setup = c.take((size_t)setup_num_partials(m) * 8);
+  pl->off_setup = c.take((size_t)imax(setup_num_partials(m), setup_num_partials(n)) * 8);
   pl->off_sq = c.take((size_t)256 * 8);                               // <= 256 partials for any K
   pl->off_scal = c.take(64);                        // nA2, E, alpha, flags, truncation rank
   pl->off_ehist = c.take((size_t)maxblk * 8);
@@ -212,6 +217,13 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   pl->off_gbig = c.take(gbig);
   pl->gbig_bytes = gbig;
   pl->off_xt = pl->bf16 ? c.take(bf16_pack_bytes(imax(m, n))) : 0;
+  // column-major: one list per column of Omega_j over all n rows
+  pl->off_flat = colmajor ? c.take((size_t)b * n * sizeof(ChunkEntry)) : 0;
+  pl->off_colcnt = colmajor ? c.take((size_t)kMaxBlock * 4) : 0;
+  if (colmajor && (int64_t)colsum_num_splits(m, n) * m * 2 > pl->part_floats) {
+    delete pl;
+    return FARPCA_E_INVALID;
+  }
   pl->total = c.cur;
   *out = pl;
   if (l_max) *l_max = lmax;
@@ -282,11 +294,38 @@ OmegaSpec omega_spec(const farpca_plan_s *pl) {
 void gen_omega(const farpca_plan_s *pl, const Ws &w, int64_t j, hipStream_t st,
                uint64_t *mask = nullptr, uint64_t *neg = nullptr, float *dense = nullptr) {
   const bool lists = pl->kind != FARPCA_GAUSSIAN;
+  // row-major: entry offsets address the sketch's LDS tile; column-major:
+  // rows inside the chunk, flattened into one list per column
   launch_omega(omega_spec(pl), pl->prm.n, j, mask ? mask : w.at<uint64_t>(pl->off_mask),
                neg ? neg : w.at<uint64_t>(pl->off_neg),
                dense ? dense : (lists ? nullptr : w.at<float>(pl->off_om)),   // dense copy: Gaussian product only
                lists ? w.at<uint32_t>(pl->off_colptr) : nullptr,
-               lists ? w.at<ChunkEntry>(pl->off_ent) : nullptr, sketch_lds_row_stride_bytes(), st);
+               lists ? w.at<ChunkEntry>(pl->off_ent) : nullptr,
+               pl->colmajor ? 1 : sketch_lds_row_stride_bytes(), st);
+  if (lists && pl->colmajor)
+    launch_flatten_lists(w.at<uint32_t>(pl->off_colptr), w.at<ChunkEntry>(pl->off_ent), pl->prm.n,
+                         pl->b, w.at<ChunkEntry>(pl->off_flat), w.at<uint32_t>(pl->off_colcnt), st);
+}
+
+// Setup pass over A (step a0): partial sums of squares, finiteness flag and,
+// for the standardized Bernoulli matrix, the row sums of A.  Column-major A is
+// passed to the row-major setup as the n x m stored matrix (same squares and
+// flag); its row sums come from a column-sum pass.
+void setup_pass(const farpca_plan_s *pl, const Ws &w, const void *A, int *flags, hipStream_t st) {
+  const farpca_params &q = pl->prm;
+  double *rowsum = w.at<double>(pl->off_rowsum);
+  if (!pl->colmajor) {
+    launch_setup(A, pl->bf16, q.lda, q.m, q.n, w.at<double>(pl->off_setup), rowsum, flags, st);
+    return;
+  }
+  launch_setup(A, false, q.lda, q.n, q.m, w.at<double>(pl->off_setup), rowsum, flags, st);
+  if (pl->kind == FARPCA_STD_BERNOULLI)
+    launch_colsum(static_cast<const float *>(A), q.lda, q.m, q.n,
+                  reinterpret_cast<double *>(w.at<float>(pl->off_part)), rowsum, st);
+}
+
+int setup_partials(const farpca_plan_s *pl) {
+  return setup_num_partials(pl->colmajor ? pl->prm.n : pl->prm.m);
 }
 
 // One A-pass with the plan's storage type of A, split over K:
@@ -309,9 +348,11 @@ int a_pass(const farpca_plan_s *pl, const Ws &w, bool tn, const void *A, const f
                                          part, xt, st);
   }
   const float *Af = static_cast<const float *>(A);
-  const int ks = gemm_choose_ksplit(M, K, tn, pl->part_splits(M));
-  return tn ? launch_gemm_tn_main(Af, q.lda, X, kBld, C, ldc, M, ncols, K, 1.f, 0.f, ks, part, st)
-            : launch_gemm_nn_main(Af, q.lda, X, kBld, C, ldc, M, ncols, K, 1.f, 0.f, ks, part, st);
+  // column-major A is A^T row-major: A X is its TN product, A^T T its NN one
+  const bool ktn = pl->colmajor ? !tn : tn;
+  const int ks = gemm_choose_ksplit(M, K, ktn, pl->part_splits(M));
+  return ktn ? launch_gemm_tn_main(Af, q.lda, X, kBld, C, ldc, M, ncols, K, 1.f, 0.f, ks, part, st)
+             : launch_gemm_nn_main(Af, q.lda, X, kBld, C, ldc, M, ncols, K, 1.f, 0.f, ks, part, st);
 }
 
 // S = A Omega_j (standardized Bernoulli: A B_j - z), m x kBld.
@@ -329,6 +370,13 @@ void sketch(const farpca_plan_s *pl, const Ws &w, const void *A, float *S, hipSt
   }
   const float *z = (pl->kind == FARPCA_STD_BERNOULLI) ? w.at<float>(pl->off_z) : nullptr;
   const float scale = pl->sketch_scale;
+  if (pl->colmajor) {
+    ProfScope ps(FARPCA_PROF_SKETCH, st);
+    launch_sketch_cols(static_cast<const float *>(A), q.lda, q.m, q.n, pl->b,
+                       w.at<ChunkEntry>(pl->off_flat), w.at<uint32_t>(pl->off_colcnt), S, scale, z,
+                       -1.f, st);
+    return;
+  }
   const int ns = sketch_choose_split(q.m, q.n);
   if (ns <= 1) {
     ProfScope ps(FARPCA_PROF_SKETCH, st);
@@ -419,9 +467,8 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
 
   HIP_OK(hipMemsetAsync(scal, 0, 64, st));
   // a0: ||A||_F^2 in FP64, row sums (z for the standardized Bernoulli matrix), finiteness.
-  launch_setup(A, pl->bf16, q.lda, m, n, w.at<double>(pl->off_setup), w.at<double>(pl->off_rowsum),
-               flags, st);
-  launch_sum_partials(w.at<double>(pl->off_setup), setup_num_partials(m), nA2, st);
+  setup_pass(pl, w, A, flags, st);
+  launch_sum_partials(w.at<double>(pl->off_setup), setup_partials(pl), nA2, st);
   double h_scal[4];
   HIP_OK(hipMemcpyAsync(h_scal, scal, 32, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
@@ -570,8 +617,7 @@ extern "C" int farpca_sketch(farpca_plan_t *plan, const void *dA, int64_t block_
   const farpca_params &q = pl->prm;
   if (pl->kind == FARPCA_STD_BERNOULLI) {
     int *flags = reinterpret_cast<int *>(w.at<double>(pl->off_scal) + 3);
-    launch_setup(dA, pl->bf16, q.lda, q.m, q.n, w.at<double>(pl->off_setup),
-                 w.at<double>(pl->off_rowsum), flags, st);
+    setup_pass(pl, w, dA, flags, st);
     launch_scale_rowsum(w.at<double>(pl->off_rowsum), q.m, pl->p, w.at<float>(pl->off_z), st);
   }
   gen_omega(pl, w, block_j, st);

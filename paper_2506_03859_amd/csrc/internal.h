@@ -56,6 +56,22 @@ int sketch_choose_split(int64_t m, int64_t n);
 int sketch_lds_row_stride_bytes();
 int sketch_rows_per_wg();
 
+// ---- sketch_cols.hip (A stored column-major: element (i, k) at A[k * lda + i])
+// One list per column c < b of Omega_j from the per-chunk lists of
+// launch_omega (generated with row stride 1): flat[c * n + e] = (row of
+// Omega_j, value), ascending row, colcnt[c] entries.
+void launch_flatten_lists(const uint32_t *colptr, const ChunkEntry *entries, int64_t n, int b,
+                          ChunkEntry *flat, uint32_t *colcnt, hipStream_t st);
+// out (m x kBld) = scale * (A Omega_j) + zc * z (z may be null); columns >= b zero.
+void launch_sketch_cols(const float *A, int64_t lda, int64_t m, int64_t n, int b,
+                        const ChunkEntry *flat, const uint32_t *colcnt, float *out, float scale,
+                        const float *z, float zc, hipStream_t st);
+// rowsum[i] = sum_k A[i][k] (FP64) for column-major A (m x n); `part` holds
+// colsum_num_splits(m, n) x m doubles.
+int colsum_num_splits(int64_t m, int64_t n);
+void launch_colsum(const float *A, int64_t lda, int64_t m, int64_t n, double *part, double *rowsum,
+                   hipStream_t st);
+
 // ---- gemm.hip (FP32 MFMA, FP32 accumulation)
 // NN: C[M x N] = A[M x K] * X[K x N]; A row-major (lda), X row-major (ldx).
 // TN: C[M x N] = A^T * Y with A K x M row-major (lda), Y K x N row-major (ldy).

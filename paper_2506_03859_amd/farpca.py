@@ -39,7 +39,7 @@ class FarpcaParams(ctypes.Structure):
                 ("a_dtype", ctypes.c_int32), ("sketch", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("rank", ctypes.c_int64), ("block", ctypes.c_int32), ("power", ctypes.c_int32),
                 ("max_blocks", ctypes.c_int64), ("sketch_p", ctypes.c_double),
-                ("sketch_zeta", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("sketch_zeta", ctypes.c_int32), ("a_layout", ctypes.c_int32),
                 ("seed", ctypes.c_uint64)]
 
 
@@ -144,11 +144,17 @@ def _check(rc: int, what: str) -> int:
     return rc
 
 
+LAYOUT_IDS = {"row": 0, "col": 1}
+
+
 def make_params(m, n, lda=None, *, tol=0.0, rank=0, block=0, power=1, sketch="sparse_sign",
-                p=0.0, zeta=0, seed=0, max_blocks=0, a_dtype="f32") -> FarpcaParams:
-    return FarpcaParams(m=m, n=n, lda=lda if lda is not None else n, a_dtype=DTYPE_IDS[a_dtype],
+                p=0.0, zeta=0, seed=0, max_blocks=0, a_dtype="f32", layout="row") -> FarpcaParams:
+    if lda is None:
+        lda = m if layout == "col" else n
+    return FarpcaParams(m=m, n=n, lda=lda, a_dtype=DTYPE_IDS[a_dtype],
                         sketch=SKETCH_IDS[sketch], tol=tol, rank=rank, block=block, power=power,
-                        max_blocks=max_blocks, sketch_p=p, sketch_zeta=zeta, reserved0=0, seed=seed)
+                        max_blocks=max_blocks, sketch_p=p, sketch_zeta=zeta,
+                        a_layout=LAYOUT_IDS[layout], seed=seed)
 
 
 @dataclass
@@ -289,15 +295,23 @@ def alloc_outputs(plan: Plan, device="cuda"):
 
 def solve(A, *, tol=0.0, rank=0, block=0, power=1, sketch="sparse_sign", p=0.0, zeta=0, seed=0,
           max_blocks=0, stream=None) -> SolveResult:
-    """Run the whole method on a row-major CUDA tensor A (m x n): float32, or
-    bfloat16 for the precision form."""
+    """Run the whole method on a CUDA tensor A (m x n): row-major float32, or
+    bfloat16 for the precision form; or column-major float32 (a transposed
+    view such as B.t() of a contiguous B), which the sparse sketch reads by
+    columns."""
     import torch
-    if A.dtype not in (torch.float32, torch.bfloat16) or not A.is_cuda or A.stride(1) != 1:
-        raise FarpcaError("A must be a row-major float32 or bfloat16 tensor on the GPU")
+    if A.dtype not in (torch.float32, torch.bfloat16) or not A.is_cuda or A.dim() != 2:
+        raise FarpcaError("A must be a 2-D float32 or bfloat16 tensor on the GPU")
     m, n = A.shape
     dt = "bf16" if A.dtype == torch.bfloat16 else "f32"
-    prm = make_params(m, n, A.stride(0), tol=tol, rank=rank, block=block, power=power, sketch=sketch,
-                      p=p, zeta=zeta, seed=seed, max_blocks=max_blocks, a_dtype=dt)
+    if A.stride(1) == 1:
+        layout, lda = "row", A.stride(0)
+    elif A.stride(0) == 1 and dt == "f32":
+        layout, lda = "col", A.stride(1)
+    else:
+        raise FarpcaError("A must be row-major (float32/bfloat16) or column-major (float32)")
+    prm = make_params(m, n, lda, tol=tol, rank=rank, block=block, power=power, sketch=sketch,
+                      p=p, zeta=zeta, seed=seed, max_blocks=max_blocks, a_dtype=dt, layout=layout)
     plan = farpca_plan(prm)
     try:
         work, U, S, V, eh = alloc_outputs(plan, A.device)

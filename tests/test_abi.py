@@ -89,6 +89,23 @@ def test_plan_rejects_invalid(fp, kw):
     assert rc == -1
 
 
+def test_column_major_layout_rules(fp):
+    # column-major A: lda >= m (not n), FP32 only, layout codes 0 and 1 only
+    ok, _, ws_col = plan_or_rc(fp, m=2000, n=1500, tol=0.1, layout="col")
+    assert ok == 0
+    assert plan_or_rc(fp, m=2000, n=1500, lda=1500, tol=0.1, layout="col")[0] == -1
+    assert plan_or_rc(fp, m=1500, n=2000, lda=1500, tol=0.1, layout="col")[0] == 0
+    assert plan_or_rc(fp, m=2000, n=1500, tol=0.1, layout="col", a_dtype="bf16")[0] == -1
+    prm = fp.make_params(2000, 1500, tol=0.1, sketch="sparse_sign")
+    prm.a_layout = 2
+    lib = fp.load_library()
+    h, lmax, ws = ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_size_t()
+    assert lib.farpca_plan(ctypes.byref(prm), ctypes.byref(h), ctypes.byref(lmax), ctypes.byref(ws)) == -1
+    # the per-column lists (b x n entries of 8 bytes) come on top of the row-major workspace
+    _, _, ws_row = plan_or_rc(fp, m=2000, n=1500, tol=0.1)
+    assert ws_col >= ws_row + 20 * 1500 * 8
+
+
 def test_default_rules(fp):
     # b = min(max(20, floor(min(m,n)/100)), 50); cap ceil(min(m,n)/(2b)) blocks
     for m, n in [(2000, 1500), (20000, 15000), (9504, 4752), (300, 500), (5000, 5000)]:

@@ -39,10 +39,13 @@ def fp():
     return fpm
 
 
-def run_both(fp, a32, **kw):
+def run_both(fp, a32, layout="row", **kw):
     import torch
-    print(f"farpca_run m={a32.shape[0]} n={a32.shape[1]} {kw}", flush=True)
-    A = torch.from_numpy(np.ascontiguousarray(a32)).cuda()
+    print(f"farpca_run {layout} m={a32.shape[0]} n={a32.shape[1]} {kw}", flush=True)
+    if layout == "row":
+        A = torch.from_numpy(np.ascontiguousarray(a32)).cuda()
+    else:
+        A = torch.from_numpy(np.ascontiguousarray(a32.T)).cuda().t()    # column-major view
     res = fp.solve(A, **kw)
     torch.cuda.synchronize()
     okw = {k: v for k, v in kw.items() if k in ("tol", "rank", "block", "power", "sketch", "p", "zeta",
@@ -131,6 +134,48 @@ def test_all_sketches_and_powers(fp, a_mid, sketch, p, zeta, power):
     assert res.status == ref.status == 0
     if same_rank_or_tie(res, ref, 1e-6 * ref.norm_a2):
         compare(res, ref, a_mid)
+
+
+@pytest.mark.parametrize("sketch,p,zeta", SKETCHES)
+@pytest.mark.parametrize("power", [0, 2])
+def test_column_major_all_sketches(fp, a_mid, sketch, p, zeta, power):
+    res, ref = run_both(fp, a_mid, layout="col", tol=1e-3, block=32, power=power, sketch=sketch, p=p,
+                        zeta=zeta, seed=3)
+    assert res.status == ref.status == 0
+    if same_rank_or_tie(res, ref, 1e-6 * ref.norm_a2):
+        compare(res, ref, a_mid)
+
+
+@pytest.mark.parametrize("sketch,p", [("sparse_gaussian", 1e-3), ("std_bernoulli", 2e-3), ("bernoulli", 1e-3)])
+def test_column_major_paper_regime(fp, sketch, p):
+    # p near 1e-3, about 5 nonzeros per column of Omega_j; m not a multiple of 4
+    # (the column gather's guarded loads) and wide (m < n)
+    a = synth.spectral(1201, 5000, synth.exp_floor_sigma(1201, decay=30.0), seed=17).astype(np.float32)
+    res, ref = run_both(fp, a, layout="col", tol=1e-2, block=40, power=2, sketch=sketch, p=p, seed=5)
+    assert res.status == ref.status == 0
+    if same_rank_or_tie(res, ref, 1e-4 * ref.norm_a2):
+        compare(res, ref, a)
+
+
+def test_column_major_matches_row_major(fp, a_mid):
+    # the two layouts compute the same quantities in a different FP32 order
+    import torch
+    kw = dict(tol=1e-3, block=32, power=2, sketch="sparse_sign", zeta=8, seed=11)
+    r_row = fp.solve(torch.from_numpy(a_mid).cuda(), **kw)
+    r_col = fp.solve(torch.from_numpy(np.ascontiguousarray(a_mid.T)).cuda().t(), **kw)
+    torch.cuda.synchronize()
+    assert r_row.info.rank_l == r_col.info.rank_l and r_row.status == r_col.status == 0
+    assert abs(r_row.info.norm_a2 - r_col.info.norm_a2) <= 1e-12 * r_row.info.norm_a2
+    s1, s2 = r_row.S.cpu().numpy(), r_col.S.cpu().numpy()
+    assert np.max(np.abs(s1 - s2)) <= 1e-6 * s1[0]
+    assert abs(r_row.info.err_indicator - r_col.info.err_indicator) <= 1e-7 * r_row.info.norm_a2
+
+
+def test_column_major_fixed_rank_tall(fp):
+    a = synth.spectral(6000, 700, synth.exp_floor_sigma(700, decay=20.0), seed=23).astype(np.float32)
+    res, ref = run_both(fp, a, layout="col", rank=100, block=50, power=1, sketch="std_bernoulli", seed=9)
+    assert res.info.rank_out == 100 and ref.rank == 100
+    compare(res, ref, a)
 
 
 def test_fixed_rank_tall(fp):

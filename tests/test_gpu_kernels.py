@@ -105,18 +105,33 @@ SKETCH_CASES = [
 ]
 
 
-@pytest.mark.parametrize("sketch,p,zeta,b,m,n", SKETCH_CASES)
-def test_sketch_bit_exact_integer_A(fp, sketch, p, zeta, b, m, n):
+# column-major A (the column gather): the same cases plus the paper's p near
+# 1e-3 (a few entries per column of Omega, many columns without any) and
+# row counts that are not multiples of 4 (no 16-byte loads).  p is a power of
+# two, so that the scale 1 / sqrt(p) and z = p A 1 stay exact.
+SKETCH_CASES_COL = SKETCH_CASES + [
+    ("sparse_sign", 2.0 ** -10, 0, 64, 3000, 5000),
+    ("std_bernoulli", 2.0 ** -9, 0, 50, 1001, 3333),
+    ("bernoulli", 1e-3, 0, 64, 513, 9000),
+    ("sparse_sign", 2.0 ** -8, 0, 64, 255, 700),
+]
+
+
+@pytest.mark.parametrize("layout,sketch,p,zeta,b,m,n",
+                         [("row",) + c for c in SKETCH_CASES] + [("col",) + c for c in SKETCH_CASES_COL])
+def test_sketch_bit_exact_integer_A(fp, layout, sketch, p, zeta, b, m, n):
     import torch
     a = synth.integer_matrix(m, n, seed=m + n, amax=1000)
-    prm = fp.make_params(m, n, tol=0.1, block=b, power=1, sketch=sketch, p=p, zeta=zeta, seed=77)
+    prm = fp.make_params(m, n, tol=0.1, block=b, power=1, sketch=sketch, p=p, zeta=zeta, seed=77,
+                         layout=layout)
     plan = fp.farpca_plan(prm)
     try:
         work, *_ = fp.alloc_outputs(plan)
         S = torch.full((m, 64), float("nan"), dtype=torch.float32, device="cuda")
-        A = dev(a, torch.float32)
+        # column-major: the buffer holds A^T row-major (lda = m)
+        A = dev(a if layout == "row" else a.T, torch.float32)
         for j in (0, 5):
-            print(f"sketch {sketch} p={p} zeta={zeta} b={b} m={m} n={n} block={j}", flush=True)
+            print(f"sketch {layout} {sketch} p={p} zeta={zeta} b={b} m={m} n={n} block={j}", flush=True)
             fp.farpca_sketch(plan, A, j, work, S)
             got = host(S)
             if sketch == "std_bernoulli":
@@ -130,19 +145,22 @@ def test_sketch_bit_exact_integer_A(fp, sketch, p, zeta, b, m, n):
         plan.free()
 
 
+@pytest.mark.parametrize("layout", ["row", "col"])
 @pytest.mark.parametrize("sketch,p,zeta,b", [("sparse_gaussian", 0.05, 0, 64), ("sparse_sign", 0.0, 8, 64),
-                                             ("gaussian", 0.0, 0, 50), ("std_bernoulli", 0.01, 0, 64)])
-def test_sketch_real_A(fp, sketch, p, zeta, b):
+                                             ("gaussian", 0.0, 0, 50), ("std_bernoulli", 0.01, 0, 64),
+                                             ("sparse_gaussian", 1e-3, 0, 64)])
+def test_sketch_real_A(fp, sketch, p, zeta, b, layout):
     import torch
     m, n = 4000, 2500
     a = synth.gaussian_matrix(m, n, seed=5).astype(np.float32)
-    prm = fp.make_params(m, n, tol=0.1, block=b, power=1, sketch=sketch, p=p, zeta=zeta, seed=91)
+    prm = fp.make_params(m, n, tol=0.1, block=b, power=1, sketch=sketch, p=p, zeta=zeta, seed=91,
+                         layout=layout)
     plan = fp.farpca_plan(prm)
     try:
         work, *_ = fp.alloc_outputs(plan)
         S = torch.zeros((m, 64), dtype=torch.float32, device="cuda")
-        print(f"sketch real {sketch} p={p} zeta={zeta} b={b}", flush=True)
-        fp.farpca_sketch(plan, dev(a), 2, work, S)
+        print(f"sketch real {layout} {sketch} p={p} zeta={zeta} b={b}", flush=True)
+        fp.farpca_sketch(plan, dev(a if layout == "row" else a.T), 2, work, S)
         got = host(S)[:, :b].astype(np.float64)
         a64 = a.astype(np.float64)
         if sketch == "std_bernoulli":
