@@ -126,6 +126,28 @@ int farpca_plan(const farpca_params *params, farpca_plan_t **out, int64_t *l_max
 int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_bytes, void *dU,
                double *dS, void *dV, farpca_info *info, double *dEhist, void *stream);
 
+/* The same run in three calls, for a caller that schedules solves block by block
+ * (for instance one block of each of several requests in turn on one stream).
+ * farpca_run is exactly farpca_begin, farpca_step until it returns 0, farpca_finish:
+ * the same kernels in the same order, so the results are bitwise the same.
+ *  farpca_begin   step a0 (||A||_F^2, finiteness, the standardized Bernoulli row
+ *                 sums); A, dWork and dEhist (may be NULL) must stay valid and
+ *                 untouched until farpca_finish returns.  Returns FARPCA_OK,
+ *                 FARPCA_E_NONFINITE, FARPCA_E_NOMEM or FARPCA_E_INVALID.
+ *  farpca_step    one block of Algorithm 1/2 (test matrix, sketch, power steps,
+ *                 basis extension, indicator update) and the stop test, which reads
+ *                 E back (host-synchronous).  Returns 1 if another block is needed,
+ *                 0 once the tolerance, the rank or the block cap is reached (also on
+ *                 calls after that), FARPCA_E_INVALID before farpca_begin.
+ *  farpca_finish  the final decomposition (U, S, V as farpca_run) and info; returns
+ *                 FARPCA_OK or FARPCA_NOT_CONVERGED, FARPCA_E_INVALID if no block ran.
+ * The run state lives in the plan (host side): one run per plan at a time. */
+int farpca_begin(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_bytes,
+                 double *dEhist, void *stream);
+int farpca_step(farpca_plan_t *plan, void *stream);
+int farpca_finish(farpca_plan_t *plan, void *dU, double *dS, void *dV, farpca_info *info,
+                  void *stream);
+
 void farpca_free(farpca_plan_t *plan);
 const char *farpca_status_str(int status);
 

@@ -74,6 +74,15 @@ struct farpca_plan_s {
       off_u32, off_gbig, off_xt, off_flat, off_colcnt, total;
   size_t gbig_bytes;
   int64_t part_floats;  // capacity of the K-split partial buffer
+  // state of a run between farpca_begin and farpca_finish (host side)
+  int stage = 0;        // 0 idle, 1 blocks running, 2 block loop done
+  const void *run_a = nullptr;
+  char *run_work = nullptr;
+  double *run_ehist = nullptr;
+  double norm_a2 = 0.0, stop_thr = 0.0;   // ||A||_F^2, tol^2 ||A||_F^2
+  int64_t l = 0;
+  int blocks = 0;
+  int status = FARPCA_NOT_CONVERGED;
   // K splits the partial buffer holds for an M-row product
   int64_t part_splits(int64_t M) const { return M > 0 ? part_floats / (M * kBld) : 1; }
 };
@@ -441,33 +450,23 @@ void cholqr(const farpca_plan_s *pl, const Ws &w, float *X, int64_t K, int passe
 
 }  // namespace
 
-extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_bytes,
-                          void *dU, double *dS, void *dV, farpca_info *info, double *dEhist,
-                          void *stream) {
-  if (!plan || !dA || !dWork || !dU || !dS || !dV) return FARPCA_E_INVALID;
+extern "C" int farpca_begin(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_bytes,
+                            double *dEhist, void *stream) {
+  if (!plan || !dA || !dWork) return FARPCA_E_INVALID;
   farpca_plan_s *pl = plan;
+  pl->stage = 0;
   if (work_bytes < pl->total) return FARPCA_E_NOMEM;
   if ((reinterpret_cast<uintptr_t>(dWork) & 255) != 0) return FARPCA_E_INVALID;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const farpca_params &q = pl->prm;
-  const int64_t m = q.m, n = q.n;
-  const int b = pl->b;
-  const void *A = dA;
   Ws w{static_cast<char *>(dWork)};
   double *scal = w.at<double>(pl->off_scal);
-  double *nA2 = scal + 0, *E = scal + 1, *alpha = scal + 2;
+  double *nA2 = scal + 0, *E = scal + 1;
   int *flags = reinterpret_cast<int *>(scal + 3);
-  double *ehist = dEhist ? dEhist : w.at<double>(pl->off_ehist);
-  float *Q = w.at<float>(pl->off_q);
-  float *Ct = w.at<float>(pl->off_ct);
-  float *S = w.at<float>(pl->off_s);
-  float *Yb = w.at<float>(pl->off_y);
-  float *X = w.at<float>(pl->off_x);
-  float *part = w.at<float>(pl->off_part);
 
   HIP_OK(hipMemsetAsync(scal, 0, 64, st));
   // a0: ||A||_F^2 in FP64, row sums (z for the standardized Bernoulli matrix), finiteness.
-  setup_pass(pl, w, A, flags, st);
+  setup_pass(pl, w, dA, flags, st);
   launch_sum_partials(w.at<double>(pl->off_setup), setup_partials(pl), nA2, st);
   double h_scal[4];
   HIP_OK(hipMemcpyAsync(h_scal, scal, 32, hipMemcpyDeviceToHost, st));
@@ -475,77 +474,128 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
   int h_flags = 0;
   std::memcpy(&h_flags, &h_scal[3], sizeof(int));
   if (h_flags & 2) return FARPCA_E_NONFINITE;
-  const double norm_a2 = h_scal[0];
   HIP_OK(hipMemcpyAsync(E, nA2, 8, hipMemcpyDeviceToDevice, st));
   if (pl->kind == FARPCA_STD_BERNOULLI)
-    launch_scale_rowsum(w.at<double>(pl->off_rowsum), m, pl->p, w.at<float>(pl->off_z), st);
-  const double thr = q.tol * q.tol * norm_a2;
+    launch_scale_rowsum(w.at<double>(pl->off_rowsum), q.m, pl->p, w.at<float>(pl->off_z), st);
+  pl->run_a = dA;
+  pl->run_work = static_cast<char *>(dWork);
+  pl->run_ehist = dEhist ? dEhist : w.at<double>(pl->off_ehist);
+  pl->norm_a2 = h_scal[0];
+  pl->stop_thr = q.tol * q.tol * pl->norm_a2;
+  pl->l = 0;
+  pl->blocks = 0;
+  pl->status = FARPCA_NOT_CONVERGED;
+  pl->stage = 1;
+  return FARPCA_OK;
+}
 
-  int64_t l = 0;
-  int status = FARPCA_NOT_CONVERGED;
-  int blocks = 0;
-  double e_host = norm_a2;
-  for (int64_t j = 0; j < pl->maxblk; ++j) {
-    gen_omega(pl, w, j, st);
-    sketch(pl, w, A, S, st);
-    float *Ysrc = S;
-    if (pl->P > 0) {
-      float *G = w.at<float>(pl->off_g);
-      HIP_OK(hipMemsetAsync(alpha, 0, 8, st));
-      float *T = S;
-      for (int k = 1; k <= pl->P; ++k) {
-        project_out(pl, w, l, T, st);
-        int nsp;
-        {
-          ProfScope ps(FARPCA_PROF_GEMM_TN, st);
-          nsp = a_pass(pl, w, true, A, T, b, X, kBld, st);
-        }
-        launch_gemm_finish(part, nsp, n, b, X, kBld, 1.f, 0.f, st);
-        if (k >= 2 && pl->P > 2) launch_axpy_block(X, kBld, G, kBld, n, b, alpha, st);
-        cholqr(pl, w, X, n, kCholqrPasses, pl->P > 2, st);
-        if (k >= 2 && pl->P > 2) launch_alpha_update(w.at<double>(pl->off_w64), b, alpha, st);
-        launch_copy_block(X, kBld, n, b, G, kBld, st);
-        if (k < pl->P) {
-          int nsp2;
-          {
-            ProfScope ps(FARPCA_PROF_GEMM_NN, st);
-            nsp2 = a_pass(pl, w, false, A, G, b, S, kBld, st);
-          }
-          launch_gemm_finish(part, nsp2, m, b, S, kBld, 1.f, 0.f, st);
-          T = S;
-        }
-      }
-      int nsp3;
+extern "C" int farpca_step(farpca_plan_t *plan, void *stream) {
+  if (!plan) return FARPCA_E_INVALID;
+  farpca_plan_s *pl = plan;
+  if (pl->stage == 2) return 0;
+  if (pl->stage != 1) return FARPCA_E_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const farpca_params &q = pl->prm;
+  const int64_t m = q.m, n = q.n;
+  const int b = pl->b;
+  const void *A = pl->run_a;
+  Ws w{pl->run_work};
+  double *scal = w.at<double>(pl->off_scal);
+  double *E = scal + 1, *alpha = scal + 2;
+  float *Q = w.at<float>(pl->off_q);
+  float *Ct = w.at<float>(pl->off_ct);
+  float *S = w.at<float>(pl->off_s);
+  float *Yb = w.at<float>(pl->off_y);
+  float *X = w.at<float>(pl->off_x);
+  float *part = w.at<float>(pl->off_part);
+  const int64_t j = pl->blocks;
+  int64_t l = pl->l;
+
+  gen_omega(pl, w, j, st);
+  sketch(pl, w, A, S, st);
+  float *Ysrc = S;
+  if (pl->P > 0) {
+    float *G = w.at<float>(pl->off_g);
+    HIP_OK(hipMemsetAsync(alpha, 0, 8, st));
+    float *T = S;
+    for (int k = 1; k <= pl->P; ++k) {
+      project_out(pl, w, l, T, st);
+      int nsp;
       {
-        ProfScope ps(FARPCA_PROF_GEMM_NN, st);
-        nsp3 = a_pass(pl, w, false, A, G, b, Yb, kBld, st);
+        ProfScope ps(FARPCA_PROF_GEMM_TN, st);
+        nsp = a_pass(pl, w, true, A, T, b, X, kBld, st);
       }
-      launch_gemm_finish(part, nsp3, m, b, Yb, kBld, 1.f, 0.f, st);
-      Ysrc = Yb;
+      launch_gemm_finish(part, nsp, n, b, X, kBld, 1.f, 0.f, st);
+      if (k >= 2 && pl->P > 2) launch_axpy_block(X, kBld, G, kBld, n, b, alpha, st);
+      cholqr(pl, w, X, n, kCholqrPasses, pl->P > 2, st);
+      if (k >= 2 && pl->P > 2) launch_alpha_update(w.at<double>(pl->off_w64), b, alpha, st);
+      launch_copy_block(X, kBld, n, b, G, kBld, st);
+      if (k < pl->P) {
+        int nsp2;
+        {
+          ProfScope ps(FARPCA_PROF_GEMM_NN, st);
+          nsp2 = a_pass(pl, w, false, A, G, b, S, kBld, st);
+        }
+        launch_gemm_finish(part, nsp2, m, b, S, kBld, 1.f, 0.f, st);
+        T = S;
+      }
     }
-    // Basis extension: Y_j against Q, orthonormalise, append; C_j^T = A^T Q_j.
-    project_out(pl, w, l, Ysrc, st);
-    cholqr(pl, w, Ysrc, m, kCholqrPasses, false, st);
-    launch_copy_block(Ysrc, kBld, m, b, Q + l, pl->ldq, st);
-    int nsp4;
+    int nsp3;
     {
-      ProfScope ps(FARPCA_PROF_GEMM_TN, st);
-      nsp4 = a_pass(pl, w, true, A, Ysrc, b, Ct + l, pl->ldq, st);
+      ProfScope ps(FARPCA_PROF_GEMM_NN, st);
+      nsp3 = a_pass(pl, w, false, A, G, b, Yb, kBld, st);
     }
-    launch_gemm_finish(part, nsp4, n, b, Ct + l, pl->ldq, 1.f, 0.f, st);
-    launch_sqnorm(Ct + l, pl->ldq, n, b, w.at<double>(pl->off_sq), st);
-    launch_indicator_update(w.at<double>(pl->off_sq), sqnorm_num_partials(n), E, ehist, j, st);
-    l += b;
-    blocks = (int)(j + 1);
-    HIP_OK(hipMemcpyAsync(&e_host, E, 8, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
-    if (q.rank > 0) {
-      if (l >= q.rank) { status = FARPCA_OK; break; }
-    } else if (e_host < thr) {
-      status = FARPCA_OK;
-      break;
-    }
+    launch_gemm_finish(part, nsp3, m, b, Yb, kBld, 1.f, 0.f, st);
+    Ysrc = Yb;
   }
+  // Basis extension: Y_j against Q, orthonormalise, append; C_j^T = A^T Q_j.
+  project_out(pl, w, l, Ysrc, st);
+  cholqr(pl, w, Ysrc, m, kCholqrPasses, false, st);
+  launch_copy_block(Ysrc, kBld, m, b, Q + l, pl->ldq, st);
+  int nsp4;
+  {
+    ProfScope ps(FARPCA_PROF_GEMM_TN, st);
+    nsp4 = a_pass(pl, w, true, A, Ysrc, b, Ct + l, pl->ldq, st);
+  }
+  launch_gemm_finish(part, nsp4, n, b, Ct + l, pl->ldq, 1.f, 0.f, st);
+  launch_sqnorm(Ct + l, pl->ldq, n, b, w.at<double>(pl->off_sq), st);
+  launch_indicator_update(w.at<double>(pl->off_sq), sqnorm_num_partials(n), E, pl->run_ehist, j,
+                          st);
+  l += b;
+  pl->l = l;
+  pl->blocks = (int)(j + 1);
+  double e_host = 0.0;
+  HIP_OK(hipMemcpyAsync(&e_host, E, 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  bool done = false;
+  if (q.rank > 0) {
+    if (l >= q.rank) done = true;
+  } else if (e_host < pl->stop_thr) {
+    done = true;
+  }
+  if (done) pl->status = FARPCA_OK;
+  if (done || pl->blocks >= pl->maxblk) {
+    pl->stage = 2;
+    return 0;
+  }
+  return 1;
+}
+
+extern "C" int farpca_finish(farpca_plan_t *plan, void *dU, double *dS, void *dV,
+                             farpca_info *info, void *stream) {
+  if (!plan || !dU || !dS || !dV) return FARPCA_E_INVALID;
+  farpca_plan_s *pl = plan;
+  if (pl->stage == 0 || pl->blocks == 0) return FARPCA_E_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const farpca_params &q = pl->prm;
+  const int64_t m = q.m, n = q.n;
+  Ws w{pl->run_work};
+  double *scal = w.at<double>(pl->off_scal);
+  float *Q = w.at<float>(pl->off_q);
+  float *Ct = w.at<float>(pl->off_ct);
+  float *part = w.at<float>(pl->off_part);
+  const int64_t l = pl->l;
+  const int status = pl->status;
 
   // Final decomposition: K = C C^T = (C^T)^T C^T, eigenpairs descending.
   const int64_t rout = (q.rank > 0) ? imin(q.rank, l) : l;
@@ -580,12 +630,13 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
   HIP_OK(hipStreamSynchronize(st));
   HIP_OK(hipGetLastError());
   if (g_prof.on) prof_resolve();
+  pl->stage = 0;
   if (info) {
     info->rank_l = l;
     info->rank_out = rout;
-    info->blocks = blocks;
+    info->blocks = pl->blocks;
     info->status = status;
-    info->norm_a2 = norm_a2;
+    info->norm_a2 = pl->norm_a2;
     info->err_indicator = h_tail[1];
     info->eig_sweeps = sweeps;
     int fl = 0;
@@ -594,6 +645,21 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
     info->dropped = fl & 1;
   }
   return status;
+}
+
+extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_bytes,
+                          void *dU, double *dS, void *dV, farpca_info *info, double *dEhist,
+                          void *stream) {
+  if (!plan || !dA || !dWork || !dU || !dS || !dV) return FARPCA_E_INVALID;
+  int rc = farpca_begin(plan, dA, dWork, work_bytes, dEhist, stream);
+  if (rc != FARPCA_OK) return rc;
+  while ((rc = farpca_step(plan, stream)) == 1) {
+  }
+  if (rc < 0) {
+    plan->stage = 0;
+    return rc;
+  }
+  return farpca_finish(plan, dU, dS, dV, info, stream);
 }
 
 extern "C" int farpca_omega(farpca_plan_t *plan, int64_t block_j, void *dWork, size_t work_bytes,

@@ -24,7 +24,7 @@ DTYPE_IDS = {"f32": 0, "bf16": 1}
 STATUS_OK = 0
 STATUS_NOT_CONVERGED = 1
 
-EXPORTED = ["farpca_plan", "farpca_run", "farpca_free", "farpca_status_str", "farpca_omega",
+EXPORTED = ["farpca_plan", "farpca_run", "farpca_begin", "farpca_step", "farpca_finish", "farpca_free", "farpca_status_str", "farpca_omega",
             "farpca_sketch", "farpca_gemm_scratch_bytes", "farpca_gemm_nn", "farpca_gemm_tn",
             "farpca_gemm_bf16_scratch_bytes", "farpca_gemm_bf16_nn", "farpca_gemm_bf16_tn",
             "farpca_eig_scratch_bytes", "farpca_eig", "farpca_profile_enable", "farpca_profile_get",
@@ -81,6 +81,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.farpca_plan.restype = ctypes.c_int
     lib.farpca_run.argtypes = [vp, vp, vp, sz, vp, vp, vp, ctypes.POINTER(FarpcaInfo), vp, vp]
     lib.farpca_run.restype = ctypes.c_int
+    lib.farpca_begin.argtypes = [vp, vp, vp, sz, vp, vp]
+    lib.farpca_begin.restype = ctypes.c_int
+    lib.farpca_step.argtypes = [vp, vp]
+    lib.farpca_step.restype = ctypes.c_int
+    lib.farpca_finish.argtypes = [vp, vp, vp, vp, ctypes.POINTER(FarpcaInfo), vp]
+    lib.farpca_finish.restype = ctypes.c_int
     lib.farpca_free.argtypes = [vp]
     lib.farpca_free.restype = None
     lib.farpca_status_str.argtypes = [ctypes.c_int]
@@ -192,6 +198,28 @@ def farpca_run(plan: Plan, A, work, U, S, V, ehist=None, stream=None):
                         _ptr(U), _ptr(S), _ptr(V), ctypes.byref(info),
                         _ptr(ehist) if ehist is not None else None, _stream(stream))
     _check(rc, "farpca_run")
+    return rc, info
+
+
+def farpca_begin(plan: Plan, A, work, ehist=None, stream=None) -> int:
+    """Step a0 of a run driven block by block (see farpca_step / farpca_finish)."""
+    lib = load_library()
+    return _check(lib.farpca_begin(plan.handle, _ptr(A), _ptr(work), work.numel() * work.element_size(),
+                                   _ptr(ehist) if ehist is not None else None, _stream(stream)),
+                  "farpca_begin")
+
+
+def farpca_step(plan: Plan, stream=None) -> int:
+    """One block and the stop test: 1 if another block is needed, else 0."""
+    return _check(load_library().farpca_step(plan.handle, _stream(stream)), "farpca_step")
+
+
+def farpca_finish(plan: Plan, U, S, V, stream=None):
+    """Final decomposition of a run begun with farpca_begin; returns (status, FarpcaInfo)."""
+    lib = load_library()
+    info = FarpcaInfo()
+    rc = lib.farpca_finish(plan.handle, _ptr(U), _ptr(S), _ptr(V), ctypes.byref(info), _stream(stream))
+    _check(rc, "farpca_finish")
     return rc, info
 
 

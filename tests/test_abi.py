@@ -106,6 +106,20 @@ def test_column_major_layout_rules(fp):
     assert ws_col >= ws_row + 20 * 1500 * 8
 
 
+def test_step_entry_points_need_begin(fp):
+    # host-side checks only (no device work): step and finish before begin
+    plan = fp.farpca_plan(fp.make_params(2000, 1500, tol=0.1, sketch="sparse_sign"))
+    lib = fp.load_library()
+    try:
+        assert lib.farpca_step(plan.handle, None) == -1
+        assert lib.farpca_finish(plan.handle, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                 ctypes.c_void_p(16), None, None) == -1
+        assert lib.farpca_begin(plan.handle, None, None, 0, None, None) == -1
+        assert lib.farpca_step(None, None) == -1
+    finally:
+        plan.free()
+
+
 def test_default_rules(fp):
     # b = min(max(20, floor(min(m,n)/100)), 50); cap ceil(min(m,n)/(2b)) blocks
     for m, n in [(2000, 1500), (20000, 15000), (9504, 4752), (300, 500), (5000, 5000)]:

@@ -178,6 +178,104 @@ def test_column_major_fixed_rank_tall(fp):
     compare(res, ref, a)
 
 
+def _run_steps(fp, plan, A, stream=None):
+    import torch
+    work, U, S, V, eh = fp.alloc_outputs(plan, A.device)
+    fp.farpca_begin(plan, A, work, eh, stream)
+    more = 0
+    while fp.farpca_step(plan, stream) == 1:
+        more += 1
+    assert fp.farpca_step(plan, stream) == 0        # further calls do nothing
+    status, info = fp.farpca_finish(plan, U, S, V, stream)
+    torch.cuda.synchronize()
+    return status, info, more, (U, S, V, eh)
+
+
+def _run_whole(fp, plan, A):
+    import torch
+    work, U, S, V, eh = fp.alloc_outputs(plan, A.device)
+    status, info = fp.farpca_run(plan, A, work, U, S, V, eh)
+    torch.cuda.synchronize()
+    return status, info, (U, S, V, eh)
+
+
+def _same_info(a, b):
+    for f in ("rank_l", "rank_out", "blocks", "status", "norm_a2", "err_indicator", "eig_sweeps",
+              "dropped", "rank_trunc"):
+        assert getattr(a, f) == getattr(b, f), f
+
+
+@pytest.mark.parametrize("kw", [dict(tol=1e-3, block=32, power=2, sketch="sparse_sign", zeta=8, seed=11),
+                                dict(rank=70, block=30, power=1, sketch="std_bernoulli", seed=2),
+                                dict(tol=1e-9, block=64, power=1, sketch="gaussian", seed=5, max_blocks=3)])
+def test_step_entry_points_match_run(fp, a_mid, kw):
+    # begin / step ... / finish is farpca_run in three calls: bitwise the same
+    import torch
+    A = torch.from_numpy(a_mid).cuda()
+    m, n = a_mid.shape
+    print(f"step api {kw}", flush=True)
+    p1 = fp.farpca_plan(fp.make_params(m, n, **kw))
+    p2 = fp.farpca_plan(fp.make_params(m, n, **kw))
+    try:
+        st1, info1, outs1 = _run_whole(fp, p1, A)
+        st2, info2, more, outs2 = _run_steps(fp, p2, A)
+        assert st1 == st2
+        _same_info(info1, info2)
+        assert more == info2.blocks - 1
+        k = info1.rank_out
+        for x, y in zip(outs1[:3], outs2[:3]):
+            xs = x[:, :k] if x.dim() == 2 else x[:k]
+            ys = y[:, :k] if y.dim() == 2 else y[:k]
+            assert torch.equal(xs, ys)
+        assert torch.equal(outs1[3][:info1.blocks], outs2[3][:info2.blocks])
+        if "max_blocks" in kw:
+            assert st2 == 1 and info2.blocks == 3          # the cap: not converged
+    finally:
+        p1.free()
+        p2.free()
+
+
+def test_step_entry_points_interleaved(fp, a_mid):
+    # two solves advanced block by block in turn on one stream (distinct plans
+    # and workspaces) give each its own farpca_run result
+    import torch
+    a2 = synth.spectral(900, 1300, synth.matrix2_sigma(900), seed=31).astype(np.float32)
+    mats = [torch.from_numpy(a_mid).cuda(), torch.from_numpy(a2).cuda()]
+    kws = [dict(tol=1e-3, block=32, power=2, sketch="sparse_sign", zeta=8, seed=11),
+           dict(tol=1e-2, block=20, power=1, sketch="sparse_gaussian", p=0.05, seed=4)]
+    print("step api interleaved", flush=True)
+    whole, plans, state = [], [], []
+    try:
+        for A, kw in zip(mats, kws):
+            m, n = A.shape
+            pw = fp.farpca_plan(fp.make_params(m, n, **kw))
+            plans.append(pw)
+            whole.append(_run_whole(fp, pw, A))
+            ps = fp.farpca_plan(fp.make_params(m, n, **kw))
+            plans.append(ps)
+            work, U, S, V, eh = fp.alloc_outputs(ps, A.device)
+            fp.farpca_begin(ps, A, work, eh)
+            state.append((ps, work, U, S, V, eh))
+        active = [True, True]
+        while any(active):
+            for i in range(2):
+                if active[i]:
+                    active[i] = fp.farpca_step(state[i][0]) == 1
+        for i in range(2):
+            ps, work, U, S, V, eh = state[i]
+            st, info = fp.farpca_finish(ps, U, S, V)
+            torch.cuda.synchronize()
+            st1, info1, outs1 = whole[i]
+            assert st == st1
+            _same_info(info1, info)
+            k = info.rank_out
+            assert torch.equal(U[:, :k], outs1[0][:, :k]) and torch.equal(S[:k], outs1[1][:k])
+            assert torch.equal(V[:, :k], outs1[2][:, :k])
+    finally:
+        for p in plans:
+            p.free()
+
+
 def test_fixed_rank_tall(fp):
     # tall rank-20 signal + N(0, 1e-6) noise, fixed rank k = 40, b = 10
     a = synth.tall_lowrank(20000, 400, 20, 1e-6, seed=4).astype(np.float32)
