@@ -106,6 +106,33 @@ def test_alone_mix_direct_bitwise(fp):
         assert r.t_submit <= r.t_admit <= r.t_done
 
 
+def test_column_major_request(fp):
+    # a column-major FP32 request (sparse regime p near 1e-3) served among
+    # row-major ones equals farpca_run on the same storage bitwise
+    import torch
+    a = synth.spectral(1500, 2500, synth.exp_floor_sigma(1500, decay=30.0), seed=41).astype(np.float32)
+    Acol = torch.from_numpy(np.ascontiguousarray(a.T)).cuda()      # A^T row-major = A column-major
+    prm = fp.make_params(1500, 2500, tol=1e-2, block=32, power=2, sketch="sparse_gaussian", p=2e-3,
+                         seed=8, layout="col")
+    reqs = requests_mix()[:3]
+    mats = [device_matrix(x, st) for _, x, _, st in reqs]
+    prms = [fp.make_params(x.shape[0], x.shape[1], a_dtype=st, **kw) for _, x, kw, st in reqs]
+    print("serve: column-major request among 3 row-major ones", flush=True)
+    st_d, Ud, Sd, Vd = direct(fp, Acol, prm)
+    pool = 2 * (fp.farpca_request_footprint(prm) + sum(fp.farpca_request_footprint(p) for p in prms))
+    srv = fp.Server(pool, slots=4)
+    try:
+        srv.submit(prm, Acol, 500)
+        for i in range(len(reqs)):
+            srv.submit(prms[i], mats[i], i)
+        got = drain(fp, srv, len(reqs) + 1)
+    finally:
+        srv.close()
+    r, (U, S, V) = got[500]
+    assert r.status == st_d == 0
+    assert torch.equal(U, Ud) and torch.equal(S, Sd) and torch.equal(V, Vd)
+
+
 def test_admission_respects_pool(fp):
     reqs = requests_mix()
     mats = [device_matrix(a, st) for _, a, _, st in reqs]
