@@ -444,7 +444,8 @@ def main():
     t0 = time.perf_counter()
     for r in range(args.steps):
         status, info = fp.farpca_run(plans[args.warmup + r], A, work, U, S, V, eh)
-        infos.append((status, info.rank_l, info.blocks, info.err_indicator / info.norm_a2))
+        infos.append((status, info.rank_l, info.blocks, info.err_indicator / info.norm_a2,
+                      info.eig_sweeps))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = {c: fp.farpca_profile_get(c) for c in fp.PROF_CLASSES}
@@ -542,7 +543,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roof,
         "kernels": classes,
-        "runs": [{"status": s, "l": l, "blocks": bl, "rel_E": e} for s, l, bl, e in infos],
+        "runs": [{"status": s, "l": l, "blocks": bl, "rel_E": e, "eig_sweeps": sw}
+                 for s, l, bl, e, sw in infos],
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, wl, max(blocks))
