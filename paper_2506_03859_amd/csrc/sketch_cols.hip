@@ -43,7 +43,7 @@ __global__ __launch_bounds__(64) void flatten_lists_kernel(const uint32_t *__res
   for (int64_t g = 0; g < nchunks; g += 64) {
     const int64_t ch = g + lane;
     uint32_t s = 0, e = 0, cnt = 0;
-    const ChunkEntry *ent = entries + ch * (int64_t)kEntCap;
+    const ChunkEntry *ent = entries + (ch < nchunks ? ch : 0) * (int64_t)kEntCap;
     if (ch < nchunks) {
       const uint32_t *cp = colptr + ch * (kMaxBlock + 1);
       s = cp[c];
