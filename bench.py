@@ -137,11 +137,23 @@ def cpu_baseline(a_dev, wl, blocks_gpu, min_seconds=10.0, max_solves=5):
         runs.append(res.blocks)
     dt = time.perf_counter() - t0
     per_solve = dt / len(runs)
+    # one more solve on a single BLAS thread (the oracle's serial cost)
+    single_ms, blas = None, None
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        blas = sorted({f"{i.get('internal_api')} {i.get('version')}" for i in threadpool_info()})
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            farpca(a, FarpcaParams(tol=tol, rank=(200 if tol == 0.0 else 0), block=b, power=P,
+                                   sketch=sketch, p=p, zeta=zeta, seed=1000))
+            single_ms = (time.perf_counter() - t1) * 1e3
+    except Exception as e:        # threadpoolctl missing or unable to limit: report none
+        log(f"cpu baseline: no single-thread run ({e})")
     return {"value": len(runs) / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
             "sample": f"{len(runs)} whole oracle solves (NumPy FP64, seeds 1000..) on the same {m}x{n} "
                       f"matrix upcast to FP64, {sorted(set(runs))} blocks each, {dt:.1f} s in total; "
                       f"{per_solve * 1e3:.0f} ms per solve (GPU solves: {blocks_gpu} blocks)",
-            "ms_per_solve": per_solve * 1e3}
+            "ms_per_solve": per_solve * 1e3, "single_thread_ms_per_solve": single_ms, "blas": blas}
 
 
 def kernel_probe(wl, dev, reps=3):
@@ -442,12 +454,16 @@ def main():
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    t_done = []
     for r in range(args.steps):
+        # farpca_run returns once the solve's results are on the device
         status, info = fp.farpca_run(plans[args.warmup + r], A, work, U, S, V, eh)
+        t_done.append(time.perf_counter())
         infos.append((status, info.rank_l, info.blocks, info.err_indicator / info.norm_a2,
                       info.eig_sweeps))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    per_solve_ms = [(b_ - a_) * 1e3 for a_, b_ in zip([t0] + t_done[:-1], t_done)]
     prof = {c: fp.farpca_profile_get(c) for c in fp.PROF_CLASSES}
     fp.farpca_profile_enable(False)
     log(f"timed {args.steps} solves")
@@ -531,6 +547,8 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms,
         "time_to_tolerance_ms": ms,
+        "solve_ms": {"median": float(sorted(per_solve_ms)[len(per_solve_ms) // 2]),
+                     "min": min(per_solve_ms), "max": max(per_solve_ms)},
         "sketch_hbm_GBps": sketch_gbps,
         "higher_is_better": True,
         "scaling": "weak",
