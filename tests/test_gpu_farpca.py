@@ -171,6 +171,19 @@ def test_column_major_matches_row_major(fp, a_mid):
     assert abs(r_row.info.err_indicator - r_col.info.err_indicator) <= 1e-7 * r_row.info.norm_a2
 
 
+@pytest.mark.parametrize("layout", ["row", "col"])
+@pytest.mark.parametrize("m,n", [(7, 300), (300, 7), (3, 3)])
+def test_tiny_shapes(fp, layout, m, n):
+    # fewer rows or columns than one lane's 4 rows, one tile, one chunk
+    a = synth.spectral(m, n, synth.exp_floor_sigma(min(m, n), decay=2.0), seed=m + n).astype(np.float32)
+    b = min(2, min(m, n))
+    # zeta = b: every row of Omega holds b signs (no empty column at these sizes)
+    res, ref = run_both(fp, a, layout=layout, rank=b, block=b, power=1, sketch="sparse_sign",
+                        zeta=b, seed=3)
+    assert res.status == 0 and res.info.rank_out == b and ref.rank == b
+    compare(res, ref, a)
+
+
 def test_column_major_fixed_rank_tall(fp):
     a = synth.spectral(6000, 700, synth.exp_floor_sigma(700, decay=20.0), seed=23).astype(np.float32)
     res, ref = run_both(fp, a, layout="col", rank=100, block=50, power=1, sketch="std_bernoulli", seed=9)
