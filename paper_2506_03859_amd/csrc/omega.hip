@@ -33,9 +33,14 @@ __global__ __launch_bounds__(64) void omega_kernel(OmegaSpec s, int64_t n, int64
     if (s.kind == SK_SPARSE_SIGN && s.zeta > 0) {
       // Floyd's sampling of zeta distinct columns out of b.
       uint64_t chosen = 0;
+      // 32-bit draw q is half of word (q / 2) % 4 of call q / 8: one call
+      // serves 8 draws
+      u64x4 w8 = philox4x64_10(row, blk, 0, 0, s.seed, 0);
       for (int q = 0; q < s.zeta; ++q) {
         const uint32_t jj = (uint32_t)(b - s.zeta + q);
-        const uint32_t u = draw32(s.seed, row, blk, 0, (uint32_t)q);
+        if (q > 0 && (q & 7) == 0) w8 = philox4x64_10(row, blk, 0, (uint64_t)(q >> 3), s.seed, 0);
+        const uint64_t word = pick64(w8, (uint32_t)(q >> 1) & 3u);
+        const uint32_t u = (q & 1) ? (uint32_t)(word >> 32) : (uint32_t)(word & 0xFFFFFFFFull);
         const uint32_t tt = (uint32_t)(((uint64_t)u * (uint64_t)(jj + 1u)) >> 32);
         if ((chosen >> tt) & 1ull) chosen |= 1ull << jj; else chosen |= 1ull << tt;
       }

@@ -50,10 +50,17 @@ __device__ __forceinline__ uint32_t draw32(uint64_t seed, uint64_t row, uint64_t
   return (q & 1u) ? (uint32_t)(w >> 32) : (uint32_t)(w & 0xFFFFFFFFull);
 }
 
+__device__ __forceinline__ uint64_t pick64(const u64x4 &w, uint32_t s) {
+  return s == 0 ? w.v[0] : (s == 1 ? w.v[1] : (s == 2 ? w.v[2] : w.v[3]));
+}
+
 // Box-Muller standard normal for entry (row, col) of block `block`, in FP64.
+// Its two 64-bit draws 2 col and 2 col + 1 are words 2 (col % 2) and
+// 2 (col % 2) + 1 of one call (t = col / 2).
 __device__ __forceinline__ double gaussian_entry(uint64_t seed, uint64_t row, uint64_t block, uint32_t col) {
-  const uint64_t w1 = draw64(seed, row, block, 2, 2u * col);
-  const uint64_t w2 = draw64(seed, row, block, 2, 2u * col + 1u);
+  const u64x4 w = philox4x64_10(row, block, 2, col >> 1, seed, 0);
+  const uint64_t w1 = (col & 1u) ? w.v[2] : w.v[0];
+  const uint64_t w2 = (col & 1u) ? w.v[3] : w.v[1];
   const double u1 = ((double)(w1 >> 11) + 1.0) * 0x1.0p-53;
   const double u2 = (double)(w2 >> 11) * 0x1.0p-53;
   return sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
