@@ -160,7 +160,8 @@ const char *farpca_status_str(int status);
  *          form of Algorithm 2); columns >= b are zero.
  * farpca_sketch: dS (m x 64 FP32, columns >= b zero) = A * dDense, computed by
  *   the sparse gather kernel (dense GEMM for FARPCA_GAUSSIAN); standardized
- *   Bernoulli: A B_j - z with z = A (p 1_n) (Section 3.1).
+ *   Bernoulli: A B_j - z with z = A (p 1_n) (Section 3.1).  dA in the plan's
+ *   storage (a_dtype, a_layout): column-major A is gathered by columns.
  * Both need the workspace of farpca_plan. */
 int farpca_omega(farpca_plan_t *plan, int64_t block_j, void *dWork, size_t work_bytes,
                  uint64_t *dMask, uint64_t *dNeg, float *dDense, void *stream);
