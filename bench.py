@@ -170,9 +170,10 @@ def kernel_probe(wl, dev, reps=3):
     skinny_m = torch.randn(m, 64, device=dev)
     Cm = torch.zeros(m, 64, device=dev)
     Cn = torch.zeros(n, 64, device=dev)
+    layout = LAYOUTS.get(wl, "row")
     plan = fp.farpca_plan(fp.make_params(m, n, tol=tol, rank=(200 if tol == 0.0 else 0), block=b,
                                          power=P, sketch=sketch, p=p, zeta=zeta, seed=1000,
-                                         a_dtype=storage))
+                                         a_dtype=storage, layout=layout))
     work, _, _, _, _ = fp.alloc_outputs(plan, dev)
     if storage == "bf16":
         nb = fp.farpca_gemm_bf16_scratch_bytes(max(m, n), max(m, n))
@@ -186,7 +187,8 @@ def kernel_probe(wl, dev, reps=3):
     for r in range(reps):
         gemm_tn(A, skinny_m, Cn, n, b, m, scratch)
         gemm_nn(A, skinny_n, Cm, m, b, n, scratch)
-        fp.farpca_sketch(plan, A, r, work, Cm)
+        # column-major workloads: the sketch reads A^T row-major (same buffer, n x m)
+        fp.farpca_sketch(plan, A if layout == "row" else A.reshape(n, m), r, work, Cm)
     torch.cuda.synchronize()
     plan.free()
     del A
