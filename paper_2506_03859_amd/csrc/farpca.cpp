@@ -11,7 +11,7 @@
 //     X   = A^T T - alpha G          = A^T(AG) - W Z^{-1} W^T G - alpha G of
 //                                   Algorithm 1, evaluated with the orthonormal
 //                                   basis Q of Y (W Z^{-1} W^T = A^T Q Q^T A)
-//     G   = orth(X)                  CholeskyQR (3 passes, FP64 Gram); the shift
+//     G   = orth(X)                  CholeskyQR (2 passes, FP64 Gram); the shift
 //                                   update uses the block's smallest singular
 //                                   value (P > 2)
 //   Y_j = A G (P >= 1) or S (P = 0)
@@ -665,6 +665,8 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
 extern "C" int farpca_omega(farpca_plan_t *plan, int64_t block_j, void *dWork, size_t work_bytes,
                             uint64_t *dMask, uint64_t *dNeg, float *dDense, void *stream) {
   if (!plan || !dWork || !dMask || !dNeg || !dDense || block_j < 0) return FARPCA_E_INVALID;
+  // the workspace of a run between farpca_begin and farpca_finish is in use
+  if (plan->stage != 0) return FARPCA_E_INVALID;
   if (work_bytes < plan->total) return FARPCA_E_NOMEM;
   Ws w{static_cast<char *>(dWork)};
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -676,16 +678,25 @@ extern "C" int farpca_omega(farpca_plan_t *plan, int64_t block_j, void *dWork, s
 extern "C" int farpca_sketch(farpca_plan_t *plan, const void *dA, int64_t block_j, void *dWork,
                              size_t work_bytes, float *dS, void *stream) {
   if (!plan || !dA || !dWork || !dS || block_j < 0) return FARPCA_E_INVALID;
+  if (plan->stage != 0) return FARPCA_E_INVALID;     // workspace held by a run
   if (work_bytes < plan->total) return FARPCA_E_NOMEM;
+  if ((reinterpret_cast<uintptr_t>(dWork) & 255) != 0) return FARPCA_E_INVALID;
   farpca_plan_s *pl = plan;
   Ws w{static_cast<char *>(dWork)};
   hipStream_t st = static_cast<hipStream_t>(stream);
   const farpca_params &q = pl->prm;
-  if (pl->kind == FARPCA_STD_BERNOULLI) {
-    int *flags = reinterpret_cast<int *>(w.at<double>(pl->off_scal) + 3);
-    setup_pass(pl, w, dA, flags, st);
+  // the setup pass of the run (finiteness flag; row sums for the standardized
+  // Bernoulli matrix): a sketch of A with NaN / Inf is rejected as by farpca_begin
+  double *scal = w.at<double>(pl->off_scal);
+  int *flags = reinterpret_cast<int *>(scal + 3);
+  HIP_OK(hipMemsetAsync(scal, 0, 64, st));
+  setup_pass(pl, w, dA, flags, st);
+  int h_flags = 0;
+  HIP_OK(hipMemcpyAsync(&h_flags, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  if (h_flags & 2) return FARPCA_E_NONFINITE;
+  if (pl->kind == FARPCA_STD_BERNOULLI)
     launch_scale_rowsum(w.at<double>(pl->off_rowsum), q.m, pl->p, w.at<float>(pl->off_z), st);
-  }
   gen_omega(pl, w, block_j, st);
   sketch(pl, w, dA, dS, st);
   HIP_OK(hipGetLastError());

@@ -110,7 +110,11 @@ struct farpca_server_s {
   std::condition_variable cv_work, cv_done;
   std::deque<Request> queue;
   std::vector<farpca_result> done;
-  std::map<uint64_t, std::pair<size_t, size_t>> held;   // tag -> (offset, bytes) until released
+  // tag -> pool range of a finished request until released, with the events
+  // recorded after the caller's fetch copies (the range is reused only once
+  // they have completed)
+  struct Held { size_t off = 0, bytes = 0; std::vector<hipEvent_t> fetches; };
+  std::map<uint64_t, Held> held;
   std::vector<std::thread> workers;
   int running = 0;
   bool stop = false;
@@ -183,7 +187,10 @@ void worker_main(farpca_server_s *s) {
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->running -= 1;
-      s->held[r.tag] = std::make_pair(r.off, r.footprint);
+      farpca_server_s::Held h;
+      h.off = r.off;
+      h.bytes = r.footprint;
+      s->held[r.tag] = h;
       s->done.push_back(res);
     }
     s->cv_done.notify_all();
@@ -266,11 +273,28 @@ extern "C" int farpca_server_poll(farpca_server_t *s, farpca_result *out, int ma
 
 extern "C" int farpca_server_release(farpca_server_t *s, uint64_t tag) {
   if (!s) return FARPCA_E_INVALID;
+  std::vector<hipEvent_t> fetches;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->held.find(tag);
     if (it == s->held.end()) return FARPCA_E_INVALID;
-    s->pool->release(it->second.first, it->second.second);
+    fetches.swap(it->second.fetches);
+  }
+  // copies enqueued by farpca_server_fetch on the caller's streams finish
+  // before the range can be handed to another request
+  for (hipEvent_t ev : fetches) {
+    hipEventSynchronize(ev);
+    hipEventDestroy(ev);
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->held.find(tag);
+    if (it == s->held.end()) return FARPCA_E_INVALID;
+    for (hipEvent_t ev : it->second.fetches) {     // a fetch that raced this release
+      hipEventSynchronize(ev);
+      hipEventDestroy(ev);
+    }
+    s->pool->release(it->second.off, it->second.bytes);
     s->held.erase(it);
   }
   s->cv_work.notify_all();
@@ -295,6 +319,22 @@ extern "C" int farpca_server_fetch(farpca_server_t *s, const farpca_result *r, f
     return FARPCA_E_DEVICE;
   if (dV && hipMemcpy2DAsync(dV, ldv * 4, r->dV, r->ld * 4, k * 4, n, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return FARPCA_E_DEVICE;
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return FARPCA_E_DEVICE;
+  if (hipEventRecord(ev, st) != hipSuccess) {
+    hipEventDestroy(ev);
+    return FARPCA_E_DEVICE;
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->held.find(r->tag);
+    if (it == s->held.end()) {          // released meanwhile: wait here instead
+      hipEventSynchronize(ev);
+      hipEventDestroy(ev);
+      return FARPCA_E_INVALID;
+    }
+    it->second.fetches.push_back(ev);
+  }
   return FARPCA_OK;
 }
 
@@ -317,6 +357,11 @@ extern "C" int farpca_server_destroy(farpca_server_t *s) {
   s->cv_work.notify_all();
   for (auto &t : s->workers) t.join();
   for (auto &r : s->queue) farpca_free(r.plan);
+  for (auto &h : s->held)
+    for (hipEvent_t ev : h.second.fetches) {
+      hipEventSynchronize(ev);
+      hipEventDestroy(ev);
+    }
   hipFree(s->pool_base);
   delete s->pool;
   delete s;

@@ -51,6 +51,7 @@ def run_both(fp, a32, layout="row", **kw):
     okw = {k: v for k, v in kw.items() if k in ("tol", "rank", "block", "power", "sketch", "p", "zeta",
                                                   "seed", "max_blocks")}
     ref = farpca(a32.astype(np.float64), FarpcaParams(**okw), keep_bases=True)
+    ref.okw = okw
     return res, ref
 
 
@@ -94,13 +95,29 @@ def compare(res, ref, a32, tol_rec=2e-5, v_rel=1e-5):
     assert d <= tol_rec
 
 
-def same_rank_or_tie(res, ref, thr):
+TIES = []
+
+
+def tie_ref(res, ref, thr, a64):
+    """The oracle run to compare the GPU result with.  Same rank: the oracle's
+    own run.  Otherwise the two stop tests fell on either side of a tie (the
+    oracle's indicator within 1 % of the threshold at the deciding block, where
+    both stops are correct): the oracle is run again to the GPU's rank (fixed
+    rank l, the same blocks and test matrices) and the whole comparison is made
+    against that run."""
     if res.info.rank_l == ref.rank:
-        return True
+        return ref
     j = min(res.info.blocks, ref.blocks) - 1
     e = ref.e_history[j]
     assert abs(e - thr) <= 0.01 * thr, (res.info.rank_l, ref.rank, e, thr)
-    return False
+    TIES.append((res.info.rank_l, ref.rank, e / thr))
+    print(f"  TIE #{len(TIES)}: gpu l={res.info.rank_l} oracle l={ref.rank} E_or/thr={e / thr:.5f}; "
+          f"comparing with the oracle run to l={res.info.rank_l}", flush=True)
+    okw = {k: v for k, v in ref.okw.items() if k not in ("tol", "max_blocks")}
+    okw["rank"] = int(res.info.rank_l)
+    r2 = farpca(np.asarray(a64, dtype=np.float64), FarpcaParams(**okw), keep_bases=True)
+    assert r2.rank == res.info.rank_l
+    return r2
 
 
 @pytest.fixture(scope="module")
@@ -114,8 +131,7 @@ def a_c1():
 def test_c1_workload(fp, a_c1, tol, sketch, p):
     res, ref = run_both(fp, a_c1, tol=tol, block=20, power=1, sketch=sketch, p=p, seed=1)
     assert res.status == 0 and ref.status == 0
-    if same_rank_or_tie(res, ref, tol * tol * ref.norm_a2):
-        compare(res, ref, a_c1)
+    compare(res, tie_ref(res, ref, tol * tol * ref.norm_a2, a_c1), a_c1)
 
 
 @pytest.fixture(scope="module")
@@ -132,8 +148,7 @@ SKETCHES = [("std_bernoulli", 0.0, 0), ("sparse_sign", 0.0, 8), ("sparse_sign", 
 def test_all_sketches_and_powers(fp, a_mid, sketch, p, zeta, power):
     res, ref = run_both(fp, a_mid, tol=1e-3, block=32, power=power, sketch=sketch, p=p, zeta=zeta, seed=3)
     assert res.status == ref.status == 0
-    if same_rank_or_tie(res, ref, 1e-6 * ref.norm_a2):
-        compare(res, ref, a_mid)
+    compare(res, tie_ref(res, ref, 1e-6 * ref.norm_a2, a_mid), a_mid)
 
 
 @pytest.mark.parametrize("sketch,p,zeta", SKETCHES)
@@ -142,8 +157,7 @@ def test_column_major_all_sketches(fp, a_mid, sketch, p, zeta, power):
     res, ref = run_both(fp, a_mid, layout="col", tol=1e-3, block=32, power=power, sketch=sketch, p=p,
                         zeta=zeta, seed=3)
     assert res.status == ref.status == 0
-    if same_rank_or_tie(res, ref, 1e-6 * ref.norm_a2):
-        compare(res, ref, a_mid)
+    compare(res, tie_ref(res, ref, 1e-6 * ref.norm_a2, a_mid), a_mid)
 
 
 @pytest.mark.parametrize("sketch,p", [("sparse_gaussian", 1e-3), ("std_bernoulli", 2e-3), ("bernoulli", 1e-3)])
@@ -153,8 +167,7 @@ def test_column_major_paper_regime(fp, sketch, p):
     a = synth.spectral(1201, 5000, synth.exp_floor_sigma(1201, decay=30.0), seed=17).astype(np.float32)
     res, ref = run_both(fp, a, layout="col", tol=1e-2, block=40, power=2, sketch=sketch, p=p, seed=5)
     assert res.status == ref.status == 0
-    if same_rank_or_tie(res, ref, 1e-4 * ref.norm_a2):
-        compare(res, ref, a)
+    compare(res, tie_ref(res, ref, 1e-4 * ref.norm_a2, a), a)
 
 
 def test_column_major_matches_row_major(fp, a_mid):
@@ -306,8 +319,7 @@ def test_wide_matrix(fp):
     a = synth.spectral(700, 1800, synth.matrix2_sigma(700), seed=9).astype(np.float32)
     res, ref = run_both(fp, a, tol=1e-3, block=24, power=1, sketch="sparse_gaussian", p=0.05, seed=4)
     assert res.status == 0
-    if same_rank_or_tie(res, ref, 1e-6 * ref.norm_a2):
-        compare(res, ref, a)
+    compare(res, tie_ref(res, ref, 1e-6 * ref.norm_a2, a), a)
 
 
 def test_ragged_block_and_single_block(fp):
@@ -384,6 +396,7 @@ def run_both_bf16(fp, a32, **kw):
     okw = {k: v for k, v in kw.items() if k in ("tol", "rank", "block", "power", "sketch", "p", "zeta",
                                                   "seed", "max_blocks")}
     ref = farpca(ab.astype(np.float64), FarpcaParams(**okw), keep_bases=True)
+    ref.okw = okw
     return res, ref, ab
 
 
@@ -394,8 +407,7 @@ def test_bf16_sketches(fp, a_mid, sketch, p, zeta, power):
     res, ref, ab = run_both_bf16(fp, a_mid, tol=1e-2, block=32, power=power, sketch=sketch, p=p,
                                  zeta=zeta, seed=3)
     assert res.status == ref.status == 0
-    if same_rank_or_tie(res, ref, 1e-4 * ref.norm_a2):
-        compare(res, ref, ab)
+    compare(res, tie_ref(res, ref, 1e-4 * ref.norm_a2, ab), ab)
 
 
 def test_bf16_precision_workload_small(fp):
@@ -405,8 +417,7 @@ def test_bf16_precision_workload_small(fp):
     res, ref, ab = run_both_bf16(fp, a, tol=1e-2, block=64, power=2, sketch="sparse_gaussian",
                                  p=0.05, seed=1000)
     assert res.status == ref.status == 0
-    if same_rank_or_tie(res, ref, 1e-4 * ref.norm_a2):
-        compare(res, ref, ab)
+    compare(res, tie_ref(res, ref, 1e-4 * ref.norm_a2, ab), ab)
 
 
 def test_bf16_matches_fp32_path_on_same_values(fp, a_mid):
