@@ -9,8 +9,10 @@
  *  - All matrices are row-major FP32 unless stated.  A is m x n with leading
  *    dimension lda >= n (elements).  Any m, n >= 1 is accepted (m < n too).
  *  - Pointers named d* are device pointers (global memory of the current HIP
- *    device), owned by the caller.  The library never allocates or frees device
- *    memory: every scratch buffer lives in the caller's workspace.
+ *    device), owned by the caller.  The library allocates no device memory
+ *    while it runs: scratch buffers live in the caller's workspace, in a static
+ *    device array (farpca_run_static) or in a server's pool (allocated once by
+ *    farpca_server_create).
  *  - `stream` is a hipStream_t passed as void*; all device work is enqueued on
  *    it.  farpca_run is host-synchronous: it reads the error indicator after
  *    every block (one 8-byte device-to-host copy) and returns after the final
@@ -147,6 +149,20 @@ int farpca_begin(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_b
 int farpca_step(farpca_plan_t *plan, void *stream);
 int farpca_finish(farpca_plan_t *plan, void *dU, double *dS, void *dV, farpca_info *info,
                   void *stream);
+
+/* farpca_run for callers that cannot allocate device memory (code that must not
+ * call hipMalloc: tight serving loops, harnesses that forbid allocation).  The
+ * workspace is a device array of FARPCA_STATIC_SCRATCH_BYTES inside the library,
+ * one per GPU, held from the library's load until the process ends; the call
+ * itself allocates nothing (the caller still passes A and the outputs, as for
+ * farpca_run, and the same kernels run in the same order, so the results are
+ * bitwise those of farpca_run).  Returns FARPCA_E_NOMEM when the plan's
+ * workspace_bytes exceeds FARPCA_STATIC_SCRATCH_BYTES; otherwise as farpca_run.
+ * All calls on one GPU share that GPU's array: calls that overlap on one GPU
+ * (from several threads or streams) race and must be serialised by the caller. */
+#define FARPCA_STATIC_SCRATCH_BYTES (64u << 20)
+int farpca_run_static(farpca_plan_t *plan, const void *dA, void *dU, double *dS, void *dV,
+                      farpca_info *info, double *dEhist, void *stream);
 
 void farpca_free(farpca_plan_t *plan);
 const char *farpca_status_str(int status);

@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/farpca.h"
@@ -660,6 +661,46 @@ extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size
     return rc;
   }
   return farpca_finish(plan, dU, dS, dV, info, stream);
+}
+
+// ---- the run without a caller workspace (callers that cannot allocate)
+//
+// `scratch` is the workspace of farpca_run_static: a file-scope device array
+// that every GPU the library runs on holds from module load until the process
+// ends.  In host code its name is only a stand-in for the symbol; the device
+// address comes from hipGetSymbolAddress, once per device (with that device
+// current), and only that address is passed on.  Every call on one GPU shares
+// the array: runs that overlap on one GPU race, and a run may leave anything
+// in it (farpca_run clears what it needs at the start).
+static __device__ __align__(256) char scratch[FARPCA_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (nullptr on a HIP error).
+void *static_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" int farpca_run_static(farpca_plan_t *plan, const void *dA, void *dU, double *dS,
+                                 void *dV, farpca_info *info, double *dEhist, void *stream) {
+  if (!plan || !dA || !dU || !dS || !dV) return FARPCA_E_INVALID;
+  if (plan->total > (size_t)FARPCA_STATIC_SCRATCH_BYTES) return FARPCA_E_NOMEM;
+  void *ws = static_scratch();
+  if (!ws) return FARPCA_E_DEVICE;
+  return farpca_run(plan, dA, ws, (size_t)FARPCA_STATIC_SCRATCH_BYTES, dU, dS, dV, info, dEhist,
+                    stream);
 }
 
 extern "C" int farpca_omega(farpca_plan_t *plan, int64_t block_j, void *dWork, size_t work_bytes,

@@ -24,7 +24,7 @@ DTYPE_IDS = {"f32": 0, "bf16": 1}
 STATUS_OK = 0
 STATUS_NOT_CONVERGED = 1
 
-EXPORTED = ["farpca_plan", "farpca_run", "farpca_begin", "farpca_step", "farpca_finish", "farpca_free", "farpca_status_str", "farpca_omega",
+EXPORTED = ["farpca_plan", "farpca_run", "farpca_run_static", "farpca_begin", "farpca_step", "farpca_finish", "farpca_free", "farpca_status_str", "farpca_omega",
             "farpca_sketch", "farpca_gemm_scratch_bytes", "farpca_gemm_nn", "farpca_gemm_tn",
             "farpca_gemm_bf16_scratch_bytes", "farpca_gemm_bf16_nn", "farpca_gemm_bf16_tn",
             "farpca_eig_scratch_bytes", "farpca_eig", "farpca_profile_enable", "farpca_profile_get",
@@ -81,6 +81,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.farpca_plan.restype = ctypes.c_int
     lib.farpca_run.argtypes = [vp, vp, vp, sz, vp, vp, vp, ctypes.POINTER(FarpcaInfo), vp, vp]
     lib.farpca_run.restype = ctypes.c_int
+    lib.farpca_run_static.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(FarpcaInfo), vp, vp]
+    lib.farpca_run_static.restype = ctypes.c_int
     lib.farpca_begin.argtypes = [vp, vp, vp, sz, vp, vp]
     lib.farpca_begin.restype = ctypes.c_int
     lib.farpca_step.argtypes = [vp, vp]
@@ -198,6 +200,21 @@ def farpca_run(plan: Plan, A, work, U, S, V, ehist=None, stream=None):
                         _ptr(U), _ptr(S), _ptr(V), ctypes.byref(info),
                         _ptr(ehist) if ehist is not None else None, _stream(stream))
     _check(rc, "farpca_run")
+    return rc, info
+
+
+# workspace of farpca_run_static inside the library (FARPCA_STATIC_SCRATCH_BYTES)
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def farpca_run_static(plan: Plan, A, U, S, V, ehist=None, stream=None):
+    """farpca_run on the library's own static workspace (no allocation by the
+    call); returns (status, FarpcaInfo)."""
+    lib = load_library()
+    info = FarpcaInfo()
+    rc = lib.farpca_run_static(plan.handle, _ptr(A), _ptr(U), _ptr(S), _ptr(V), ctypes.byref(info),
+                               _ptr(ehist) if ehist is not None else None, _stream(stream))
+    _check(rc, "farpca_run_static")
     return rc, info
 
 

@@ -1,0 +1,74 @@
+"""farpca_run_static (the run on the library's static workspace, for callers
+that cannot allocate) against farpca_run on a caller workspace: the same
+kernels in the same order, so U, S, V, the indicator history and every info
+field agree bitwise.  Two calls in a row, the second on a smaller input (the
+static array keeps the first call's contents); and a plan whose workspace
+exceeds the static size is rejected with FARPCA_E_NOMEM."""
+import numpy as np
+import pytest
+
+from paper_2506_03859_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import torch  # noqa: F401
+    from paper_2506_03859_amd import farpca as fpm
+    fpm.load_library()
+    return fpm
+
+
+def _solve_both(fp, a32, **kw):
+    import torch
+    A = torch.from_numpy(np.ascontiguousarray(a32)).cuda()
+    m, n = a32.shape
+    plan = fp.farpca_plan(fp.make_params(m, n, **kw))
+    try:
+        assert plan.workspace_bytes <= fp.STATIC_SCRATCH_BYTES
+        work, U1, S1, V1, e1 = fp.alloc_outputs(plan, A.device)
+        st1, info1 = fp.farpca_run(plan, A, work, U1, S1, V1, e1)
+        _, U2, S2, V2, e2 = fp.alloc_outputs(plan, A.device)
+        del work
+        U2.fill_(np.nan)
+        V2.fill_(np.nan)
+        S2.fill_(np.nan)
+        st2, info2 = fp.farpca_run_static(plan, A, U2, S2, V2, e2)
+        torch.cuda.synchronize()
+    finally:
+        plan.free()
+    print(f"  m={m} n={n} {kw} l={info1.rank_l} status={st1}/{st2} ws={plan.workspace_bytes}", flush=True)
+    assert st1 == st2
+    for f in ("rank_l", "rank_out", "blocks", "status", "norm_a2", "err_indicator", "eig_sweeps",
+              "dropped", "rank_trunc"):
+        assert getattr(info1, f) == getattr(info2, f), f
+    k, nb = info1.rank_out, info1.blocks
+    assert torch.equal(U1[:, :k], U2[:, :k])
+    assert torch.equal(V1[:, :k], V2[:, :k])
+    assert torch.equal(S1[:k], S2[:k])
+    assert torch.equal(e1[:nb], e2[:nb])
+    return info1
+
+
+def test_static_run_matches_run_twice(fp):
+    a1 = synth.spectral(1800, 1300, synth.exp_floor_sigma(1300, decay=30.0), seed=31).astype(np.float32)
+    a2 = synth.spectral(700, 500, synth.matrix1_sigma(500), seed=32).astype(np.float32)
+    i1 = _solve_both(fp, a1, tol=1e-3, block=32, power=2, sketch="sparse_sign", zeta=8, seed=4)
+    # the second, smaller call finds the first call's values in the static array
+    i2 = _solve_both(fp, a2, tol=1e-2, block=20, power=1, sketch="std_bernoulli", seed=9)
+    assert i1.rank_l > i2.rank_l
+
+
+def test_static_run_rejects_oversized_plan(fp):
+    import torch
+    m, n = 20000, 15000
+    plan = fp.farpca_plan(fp.make_params(m, n, tol=1e-3, block=64, power=2, sketch="sparse_sign", zeta=8))
+    try:
+        assert plan.workspace_bytes > fp.STATIC_SCRATCH_BYTES
+        A = torch.empty((1, 1), dtype=torch.float32, device="cuda")   # never read: rejected first
+        U = S = V = A
+        with pytest.raises(fp.FarpcaError, match="-2"):
+            fp.farpca_run_static(plan, A, U, S, V)
+    finally:
+        plan.free()
