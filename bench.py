@@ -58,6 +58,12 @@ WORKLOADS = {
 LAYOUTS = {"col_exp50_20000x15000_sg1e-3": "col"}
 
 
+def counter_profiled():
+    """True inside a rocprofv3 --pmc run (the profiler's counter settings are in the environment)."""
+    v = os.environ.get("ROCPROF_COUNTER_COLLECTION", "")
+    return v not in ("", "0", "false", "False") or bool(os.environ.get("ROCPROF_COUNTERS"))
+
+
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -156,6 +162,58 @@ def cpu_baseline(a_dev, wl, blocks_gpu, min_seconds=10.0, max_solves=5):
             "ms_per_solve": per_solve * 1e3, "single_thread_ms_per_solve": single_ms, "blas": blas}
 
 
+def time_solves(wl, A, steps, warmup, dev):
+    """Whole solves of workload `wl` on the device matrix A: warm-up, then
+    `steps` timed solves with HIP-event timing of the kernel classes.  Returns
+    a summary (ms per solve, the A-pass and sketch rates, ranks)."""
+    import torch
+    from paper_2506_03859_amd import farpca as fp
+    m, n, _, _, tol, b, P, sketch, zeta, p, storage = WORKLOADS[wl]
+    rank = 200 if tol == 0.0 else 0
+    plans = [fp.farpca_plan(fp.make_params(m, n, tol=tol, rank=rank, block=b, power=P, sketch=sketch,
+                                           p=p, zeta=zeta, seed=1000 + r, a_dtype=storage,
+                                           layout=LAYOUTS.get(wl, "row")))
+             for r in range(warmup + steps)]
+    work, U, S, V, eh = fp.alloc_outputs(plans[0], dev)
+    for r in range(warmup):
+        fp.farpca_run(plans[r], A, work, U, S, V, eh)
+    torch.cuda.synchronize()
+    fp.farpca_profile_enable(True)
+    t0 = time.perf_counter()
+    infos = []
+    for r in range(steps):
+        st, info = fp.farpca_run(plans[warmup + r], A, work, U, S, V, eh)
+        infos.append((st, info.rank_l, info.blocks, info.eig_sweeps))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    prof = {c: fp.farpca_profile_get(c) for c in fp.PROF_CLASSES}
+    fp.farpca_profile_enable(False)
+    for pl in plans:
+        pl.free()
+    elem = 2.0 if storage == "bf16" else 4.0
+    out = {"workload": wl, "m": m, "n": n, "tol": tol, "rank": rank, "block": b, "power": P,
+           "sketch": sketch, "zeta": zeta, "p": p, "a_storage": storage, "steps": steps,
+           "ms_per_solve": ms, "solves_per_s": 1e3 / ms,
+           "l": sorted({i[1] for i in infos}), "blocks": sorted({i[2] for i in infos}),
+           "status": sorted({i[0] for i in infos})}
+    for c in ("gemm_tn", "gemm_nn", "sketch", "eig"):
+        tot, cnt = prof[c]
+        if not cnt:
+            continue
+        a_ms = tot / cnt
+        rec = {"avg_launch_ms": a_ms, "total_ms_per_solve": tot / steps}
+        if c.startswith("gemm"):
+            rec["tflops"] = 2.0 * m * n * b / (a_ms * 1e-3) / 1e12
+            rec["a_GBps"] = elem * m * n / (a_ms * 1e-3) / 1e9
+            rec["mfma_frac"] = rec["tflops"] / PEAK_FP32_MFMA_TFLOPS if storage == "f32" else None
+            rec["hbm_frac"] = rec["a_GBps"] / PEAK_HBM_GBPS
+        elif c == "sketch":
+            rec["GBps"] = (elem * m * n + 4.0 * m * b) / (a_ms * 1e-3) / 1e9
+            rec["hbm_frac"] = rec["GBps"] / PEAK_HBM_GBPS
+        out[c] = rec
+    return out
+
+
 def kernel_probe(wl, dev, reps=3):
     """The kernels that stream A, each launched `reps` times on a random matrix
     of the workload's shape, then a 1 GiB device-to-device copy (a plain read +
@@ -244,10 +302,15 @@ def serve_matrix(spec, device):
     return a.to(torch.float32).contiguous()
 
 
-def serve_bench(args, dev):
-    """Open-loop replay of the serving trace through farpca_server_*; prints
-    one JSON line with solves/s and latency percentiles for the mixed-storage
-    trace and for the same trace with every request in FP32."""
+def serve_bench(args, dev, emit=True):
+    """Open-loop replay of the serving trace through farpca_server_*: the
+    mixed-storage trace (BF16 where eligible) and the same trace all in FP32,
+    `serve_repeats` times each in alternation, and the BF16-eligible requests as
+    one burst in each storage (alternating, the same number of times).  For the
+    bursts every result's relative error ||A - U S V^T||_F / ||A||_F against the
+    FP32 matrix is measured (torch FP64 on the device), and for `serve_oracle`
+    of them the FP64 oracle runs on the stored values (BF16 values for the BF16
+    form) on the host, so that the two forms are compared at their accuracy."""
     import threading
 
     import numpy as np
@@ -267,7 +330,7 @@ def serve_bench(args, dev):
     def eligible(q):
         return q["bf16"] and q["tol"] >= 4 * floor[q["mat"]]
 
-    def replay(mode, sub=None):
+    def replay(mode, sub=None, keep=False):
         # sub: (requests, storage) replayed as one burst (all submitted at once)
         rq = reqs if sub is None else sub[0]
         srv = fp.Server(pool, slots=args.serve_slots, starve_s=0.25)
@@ -278,7 +341,7 @@ def serve_bench(args, dev):
             prms.append(fp.make_params(m, n, tol=q["tol"], power=1, sketch="sparse_sign", zeta=8,
                                        seed=q["seed"], a_dtype="bf16" if bf else "f32"))
             store.append(bf)
-        results = {}
+        results, kept = {}, {}
         t_start = time.perf_counter()
 
         def submitter():
@@ -294,8 +357,17 @@ def serve_bench(args, dev):
         while len(results) < len(rq):
             for r in srv.poll(64, wait_ms=50):
                 results[r.tag] = (r.status, r.t_submit, r.t_admit, r.t_done, r.info.rank_l)
+                if keep and r.status >= 0 and r.info.rank_out > 0:
+                    k = r.info.rank_out
+                    U = torch.empty((r.m, k), dtype=torch.float32, device=dev)
+                    S = torch.empty((k,), dtype=torch.float64, device=dev)
+                    V = torch.empty((r.n, k), dtype=torch.float32, device=dev)
+                    srv.fetch(r, U, S, V)
+                    torch.cuda.synchronize()
+                    kept[r.tag] = (U, S, V)
                 srv.release(r.tag)
         th.join()
+        mem = srv.memory()
         srv.close()
         lat = np.array([v[3] - v[1] for v in results.values()])
         t_first = min(v[1] for v in results.values())
@@ -305,30 +377,107 @@ def serve_bench(args, dev):
                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                "mean_ms": float(lat.mean() * 1e3), "converged": int(sum(1 for x in st if x == 0)),
                "capped": int(sum(1 for x in st if x == 1)), "errors": int(sum(1 for x in st if x < 0)),
-               "bf16_requests": int(sum(store))}
+               "bf16_requests": int(sum(store)), "peak_pool_GiB": mem[1] / (1 << 30),
+               "grows": mem[2], "preemptions": mem[3]}
         log(f"serve {mode}: {out}")
-        return out
+        return (out, kept, rq, store) if keep else out
 
-    mixed = replay("mixed")
-    f32 = replay("fp32")
-    # the requests the BF16 form may serve, alone, as one burst in each storage
+    def spread(runs, key="solves_per_s"):
+        v = [r[key] for r in runs]
+        return {"runs": v, "mean": float(np.mean(v)), "min": float(np.min(v)), "max": float(np.max(v))}
+
+    reps = max(1, args.serve_repeats)
+    mixed, f32 = [], []
+    for _ in range(reps):
+        mixed.append(replay("mixed"))
+        f32.append(replay("fp32"))
     elig = [q for q in reqs if eligible(q)]
-    sub_bf16 = replay("burst_bf16", (elig, "bf16")) if elig else None
-    sub_f32 = replay("burst_fp32", (elig, "f32")) if elig else None
+    burst = {"requests": len(elig)}
+    if elig:
+        b16, b32 = [], []
+        acc = {}
+        for r in range(reps):
+            keep = r == 0
+            o16 = replay("burst_bf16", (elig, "bf16"), keep=keep)
+            o32 = replay("burst_fp32", (elig, "f32"), keep=keep)
+            if keep:
+                acc = {"bf16": o16[1:], "fp32": o32[1:]}
+                o16, o32 = o16[0], o32[0]
+            b16.append(o16)
+            b32.append(o32)
+        burst["bf16"] = spread(b16)
+        burst["fp32"] = spread(b32)
+        burst["bf16_p99_ms"] = [x["p99_ms"] for x in b16]
+        burst["fp32_p99_ms"] = [x["p99_ms"] for x in b32]
+        # accuracy of each result: relative Frobenius error against the FP32 matrix
+        errs = {}
+        for form, (kept, rq, store) in acc.items():
+            e = []
+            for i, (U, S, V) in kept.items():
+                a = A32[rq[i]["mat"]].double()
+                rec = (U.double() * S) @ V.double().T
+                e.append(float(torch.linalg.norm(a - rec) / torch.linalg.norm(a)))
+            errs[form] = e
+        burst["rel_error_vs_fp32_A"] = {form: {"median": float(np.median(e)), "max": float(np.max(e))}
+                                        for form, e in errs.items() if e}
+        # the FP64 oracle on the stored values, for the first serve_oracle results
+        if args.serve_oracle > 0:
+            from oracle import FarpcaParams, farpca
+            rows = []
+            for form, (kept, rq, store) in acc.items():
+                for i in sorted(kept)[:args.serve_oracle]:
+                    q = rq[i]
+                    A = (A16 if form == "bf16" else A32)[q["mat"]]
+                    a64 = A.double().cpu().numpy()
+                    ref = farpca(a64, FarpcaParams(tol=q["tol"], power=1, sketch="sparse_sign", zeta=8,
+                                                   seed=q["seed"]))
+                    U, S, V = kept[i]
+                    rec = ((U.double() * S) @ V.double().T).cpu().numpy()
+                    na = np.linalg.norm(a64)
+                    eps_g = float(np.linalg.norm(a64 - rec) / na)
+                    eps_o = float(np.linalg.norm(a64 - (ref.U * ref.S) @ ref.V.T) / na)
+                    rows.append({"form": form, "req": i, "tol": q["tol"], "m": a64.shape[0],
+                                 "n": a64.shape[1], "l": int(U.shape[1]), "l_oracle": int(ref.rank),
+                                 "eps_served": eps_g, "eps_oracle": eps_o, "d_eps": abs(eps_g - eps_o)})
+            burst["vs_oracle"] = rows
+            burst["vs_oracle_max_d_eps"] = {f: max((r["d_eps"] for r in rows if r["form"] == f), default=None)
+                                           for f in ("bf16", "fp32")}
     line = {
         "metric": "served solves/s + p99 vs plain FP32",
-        "value": mixed["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "value": float(np.mean([x["solves_per_s"] for x in mixed])), "unit": "solves/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "bf16+f32", "data": "synthetic",
         "config": {"workload": f"serve_{len(reqs)}req_poisson200", "slots": args.serve_slots,
-                   "hw_queues": args.serve_hw_queues or None,
+                   "hw_queues": args.serve_hw_queues or None, "repeats": reps,
                    "pool_GiB": args.serve_pool_gb, "matrices": len(mats), "power": 1, "sketch": "sparse_sign",
                    "zeta": 8, "bf16_floor_median": float(np.median(floor))},
-        "mixed": mixed, "fp32": f32,
-        "bf16_over_fp32_solves_per_s": mixed["solves_per_s"] / f32["solves_per_s"],
-        "eligible_burst": {"requests": len(elig), "bf16": sub_bf16, "fp32": sub_f32},
+        "mixed": spread(mixed), "fp32": spread(f32),
+        "mixed_p99_ms": [x["p99_ms"] for x in mixed], "fp32_p99_ms": [x["p99_ms"] for x in f32],
+        "mixed_runs": mixed, "fp32_runs": f32,
+        "eligible_burst": burst,
         "vs_baseline": None,
     }
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
+
+
+def serve_summary(dev, nreq=512, slots=16):
+    """The serving trace replayed once mixed (BF16 where eligible) and once all
+    FP32, and the BF16-eligible requests as a burst in each storage: the figures
+    of the serving half of the metric, for the default JSON line."""
+    from types import SimpleNamespace
+    args = SimpleNamespace(serve_requests=nreq, serve_slots=slots, serve_pool_gb=80.0,
+                           serve_hw_queues=0, serve_repeats=1, serve_oracle=0)
+    line = serve_bench(args, dev, emit=False)
+    burst = line["eligible_burst"]
+    return {"workload": line["config"]["workload"], "slots": slots,
+            "mixed_solves_per_s": line["mixed"]["mean"], "fp32_solves_per_s": line["fp32"]["mean"],
+            "mixed_p50_ms": line["mixed_runs"][0]["p50_ms"], "mixed_p99_ms": line["mixed_p99_ms"][0],
+            "fp32_p99_ms": line["fp32_p99_ms"][0],
+            "bf16_eligible_requests": burst["requests"],
+            "burst_bf16_solves_per_s": burst.get("bf16", {}).get("mean"),
+            "burst_fp32_solves_per_s": burst.get("fp32", {}).get("mean"),
+            "burst_rel_error_vs_fp32_A": burst.get("rel_error_vs_fp32_A")}
 
 
 def stability_bench(args, dev):
@@ -390,7 +539,13 @@ def main():
                     help="replay the serving trace (Poisson arrivals, mixed shapes / tolerances / "
                          "storage) through farpca_server_* instead of the solve benchmark")
     ap.add_argument("--serve-requests", type=int, default=512)
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-repeats", type=int, default=3,
+                    help="replays of each serving configuration (alternating), for the spread")
+    ap.add_argument("--serve-oracle", type=int, default=0,
+                    help="burst results checked against the FP64 oracle on the host, per storage")
+    ap.add_argument("--no-subrecords", action="store_true",
+                    help="only the 20000 x 15000 solve line (no precision-form, tall and serving records)")
     ap.add_argument("--serve-pool-gb", type=float, default=80.0)
     ap.add_argument("--serve-hw-queues", type=int, default=0,
                     help="hardware queues of the process (GPU_MAX_HW_QUEUES, set before the HIP "
@@ -408,6 +563,13 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
               file=sys.stderr)
+        sys.exit(2)
+    if counter_profiled() and not args.kernel_probe:
+        # a hardware-counter run of this script once ended in a host segmentation
+        # fault inside the FP64 QR that builds the workload's Haar factors; under
+        # counter collection only the probe (random A, no factorisation) runs
+        print("bench.py under hardware-counter collection: use --kernel-probe (the workload's "
+              "input generation does not run in a counter-profiled process)", file=sys.stderr)
         sys.exit(2)
     if args.serve and args.serve_hw_queues > 0:
         # streams of concurrent slots map onto distinct hardware queues only up
@@ -568,6 +730,27 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, wl, max(blocks))
+    if not args.no_subrecords and wl == "exp50_20000x15000_ss8":
+        # the other configurations of the metric, beside the headline: the
+        # precision form (the same matrix stored in BF16) with its FP32 twin,
+        # the tall fixed-rank matrix, and the serving trace
+        import torch
+        sub = {}
+        log("subrecord: precision form")
+        A16 = A.to(torch.bfloat16).contiguous()
+        sub["bf16"] = time_solves("bf16_exp50_20000x15000_sg05", A16, 5, 1, dev)
+        sub["fp32_twin"] = time_solves("exp50_20000x15000_sg05", A, 5, 1, dev)
+        sub["bf16_speedup"] = sub["fp32_twin"]["ms_per_solve"] / sub["bf16"]["ms_per_solve"]
+        out["precision_form"] = sub
+        del A16, A
+        torch.cuda.empty_cache()
+        log("subrecord: tall fixed rank")
+        At = make_matrix("tall_200000x4000_rank200", dev)
+        out["tall_fixed_rank"] = time_solves("tall_200000x4000_rank200", At, 3, 1, dev)
+        del At
+        torch.cuda.empty_cache()
+        log("subrecord: serving")
+        out["serving"] = serve_summary(dev)
     print(json.dumps(out), flush=True)
 
 

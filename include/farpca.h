@@ -81,8 +81,9 @@ typedef struct farpca_params {
   int32_t block;       /* b in [1, 64]; 0 = min(max(20, floor(min(m,n)/100)), 50) (5.2/5.4)  */
   int32_t power;       /* P >= 0 power steps per block (shift active for P > 2)              */
   int64_t max_blocks;  /* 0 = ceil(min(m,n) / (2 b)) (Section 5.2); l is also capped at min(m,n) */
-  double sketch_p;     /* Bernoulli / density p in (0,1); 0 = p1 = max(1e-3, ln N/N) for
-                          FARPCA_STD_BERNOULLI, p2 = max(1e-3, 10/N) otherwise, N = max(m,n) */
+  double sketch_p;     /* Bernoulli / density p in (0,1); 0 = p1 = max(1e-3, ln n/n) for
+                          FARPCA_STD_BERNOULLI, p2 = max(1e-3, 10/n) otherwise (Section 5;
+                          n = rows of Omega_j: about ln n or 10 nonzeros per column)      */
   int32_t sketch_zeta; /* FARPCA_SPARSE_SIGN: zeta in [1, b] nonzeros +-1/sqrt(zeta) per row
                           of Omega_j; 0 = i.i.d. entries of Definition 2.2                   */
   int32_t a_layout;    /* FARPCA_LAYOUT_ROW (0) or FARPCA_LAYOUT_COL                         */
@@ -105,6 +106,12 @@ typedef struct farpca_info {
                             E + sum_{i >= r} S_i^2 < tol^2 ||A||_F^2 (S descending; the rank-r
                             truncation error, since A - Q Q^T A is orthogonal to range(Q)).
                             rank_out when the run did not converge or in fixed-rank use.  */
+  int32_t eig_converged; /* 1 if the final eigensolver met its off-diagonal test
+                            (|k_pq| <= 1e-8 sqrt(k_pp k_qq) after the sweeps, so V is
+                            orthonormal to that level, or stalled below 1e-11 of it);
+                            0 if it stopped at its cap of FARPCA_EIG_MAX_SWEEPS sweeps
+                            (U S V^T = Q Q^T A still holds)                          */
+  int32_t reserved1;
 } farpca_info;
 
 typedef struct farpca_plan_s farpca_plan_t;
@@ -147,6 +154,55 @@ int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_byt
 int farpca_begin(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_bytes,
                  double *dEhist, void *stream);
 int farpca_step(farpca_plan_t *plan, void *stream);
+/* farpca_step in two halves, for a scheduler that keeps blocks of many solves
+ * in flight from one host thread:
+ *  farpca_step_async  enqueues the next block on `stream` (the same kernels as
+ *                     farpca_step) and an asynchronous read-back of E; returns 1
+ *                     when a block was enqueued, 0 if the run needs no further
+ *                     block, FARPCA_E_INVALID before farpca_begin or while a
+ *                     block is still pending (poll it first);
+ *  farpca_step_poll   examines the pending block's E once it is complete:
+ *                     returns 2 if it is still running (wait = 0; wait != 0
+ *                     blocks until it completes), else as farpca_step (1: another
+ *                     block is needed, 0: stop).
+ * farpca_step is farpca_step_async followed by farpca_step_poll(plan, 1).  The
+ * read-back uses a few bytes of pinned host memory and an event held by the
+ * plan (created on the first block, released by farpca_free). */
+int farpca_step_async(farpca_plan_t *plan, void *stream);
+int farpca_step_poll(farpca_plan_t *plan, int wait);
+
+/* Block-granular memory, for callers that grow a solve's memory with its basis
+ * (a serving pool).  The workspace of farpca_run has two parts: the loop part
+ * (everything the blocks need; Q and C^T with room for every block) and the
+ * final part (step a10, sized for l_max).  Instead, a run may start on a loop
+ * part with room for cap_blocks blocks, move to a larger one between blocks,
+ * and take the final part, sized for the l it reached, only at the end:
+ *  farpca_loop_bytes   size of the loop part with room for cap_blocks blocks
+ *                      (1 <= cap_blocks <= l_max / b), 0 if invalid;
+ *  farpca_begin_loop   farpca_begin on such a loop part (device, 256-byte aligned);
+ *  farpca_step_async / farpca_step / farpca_step_poll as above; farpca_step_async
+ *                      returns FARPCA_E_NOMEM when the next block needs more room;
+ *  farpca_grow         between blocks (no block pending): moves the run to a new loop
+ *                      part with room for cap_blocks >= the current capacity: enqueues
+ *                      on `stream` the copies of what the loop carries (Q and C^T, the
+ *                      scalars, the row sums, the E history when it is internal).  The
+ *                      old loop part must stay untouched until those copies have run
+ *                      (stream order; e.g. release it after an event on `stream`);
+ *  farpca_final_bytes  once the block loop has ended: size of the final part for the
+ *                      reached l (outputs not included);
+ *  farpca_finish_final farpca_finish with the final part at dFinal (device, 256-byte
+ *                      aligned, farpca_final_bytes bytes) and outputs U (m x ldu), S,
+ *                      V (n x ldv), ldu, ldv >= info.rank_out.  The loop part and the
+ *                      final part may be released once it returns.
+ * The kernels and their order are those of farpca_run, so the results are bitwise
+ * the same (only the leading dimensions of Q, C^T, U and V differ). */
+size_t farpca_loop_bytes(farpca_plan_t *plan, int64_t cap_blocks);
+int farpca_begin_loop(farpca_plan_t *plan, const void *dA, void *dLoop, size_t bytes,
+                      int64_t cap_blocks, double *dEhist, void *stream);
+int farpca_grow(farpca_plan_t *plan, void *dLoop, size_t bytes, int64_t cap_blocks, void *stream);
+size_t farpca_final_bytes(farpca_plan_t *plan);
+int farpca_finish_final(farpca_plan_t *plan, void *dFinal, size_t bytes, void *dU, int64_t ldu,
+                        double *dS, void *dV, int64_t ldv, farpca_info *info, void *stream);
 int farpca_finish(farpca_plan_t *plan, void *dU, double *dS, void *dV, farpca_info *info,
                   void *stream);
 
@@ -206,30 +262,47 @@ int farpca_gemm_bf16_tn(const uint16_t *dA, int64_t lda, const float *dY, int64_
 
 /* FP64 symmetric eigendecomposition (block Jacobi) of K (l x l, row-major):
  * dW (l) descending, dV (l x l) eigenvectors in columns.  dWork holds
- * farpca_eig_scratch_bytes(l) bytes.  Returns the sweep count (>= 0) or an error. */
+ * farpca_eig_scratch_bytes(l) bytes.  The sweeps stop once every off-diagonal
+ * entry of V^T K V meets |k_pq| <= rel sqrt(|k_pp k_qq|) (rel <= 0: 1e-14; the
+ * final step of farpca_run uses 1e-8) or |k_pq| <= 4e-15 max|k_ii| (the FP64
+ * rounding of the largest entry), or once two sweeps in a row halve neither the
+ * largest ratio |k_pq| / sqrt(|k_pp k_qq|) nor the largest |k_pq| of the failing
+ * entries while the ratio is below 1e-11 or the entry below 1e-12 max|k_ii|
+ * (the rounding level of the rotations).  Returns the sweep count (>= 0) or an error;
+ * *converged (host, may be NULL) is 1 if that happened within
+ * FARPCA_EIG_MAX_SWEEPS sweeps, else 0. */
+#define FARPCA_EIG_MAX_SWEEPS 40
 size_t farpca_eig_scratch_bytes(int64_t l);
-int farpca_eig(const double *dK, int64_t l, double *dW, double *dV, void *dWork, void *stream);
+int farpca_eig(const double *dK, int64_t l, double *dW, double *dV, void *dWork, double rel,
+               int *converged, void *stream);
 
 /* ---- serving: continuous batching of independent solves on one GPU
  * A server owns one device pool of pool_bytes (allocated by
  * farpca_server_create, freed by farpca_server_destroy: the only device
- * allocation the library makes) and `slots` host threads, each with its own
- * stream.  farpca_server_submit queues a request whose A is already resident
- * (caller-owned, read only, valid until the request's result is polled); a
- * request is admitted into a free slot once its footprint
- * (farpca_request_footprint: workspace + U, S, V) fits in the pool.  The queue is
- * scanned in arrival order and the first request that fits is admitted, unless
- * an earlier one has waited more than starve_s seconds (then nothing overtakes
- * it).  Admitted requests run farpca_run on their slot's stream, concurrently
- * with the other slots.  A result (U, S, V inside the pool, leading dimension
- * ld) stays valid until farpca_server_release(tag).  Results are bitwise the
- * same whether a request runs alone or among others.  Tags must be unique
- * among queued, running and unreleased requests.  Times are seconds since
- * the server was created (steady clock).  The kernel-timing switch below must
- * be off while a server runs. */
+ * allocation the library makes), `slots` streams, a scheduler thread and one
+ * finisher thread per stream.  farpca_server_submit queues a request whose A is already
+ * resident (caller-owned, read only, valid until the request's result is
+ * polled).  The scheduler keeps up to `slots` solves in flight, each on its own
+ * stream, and advances them one block at a time (farpca_step_async /
+ * farpca_step_poll), so that the blocks of all admitted solves interleave on the
+ * device.  Memory is granted by blocks: a request is admitted once the loop part
+ * for its first four blocks fits (farpca_loop_bytes), its loop part is moved to
+ * one twice as large whenever its next block needs room (farpca_grow), and the
+ * final part plus the outputs U, S, V, sized for the columns the solve returns,
+ * are granted when its block loop ends (a finisher thread runs the final step).
+ * The queue is scanned in arrival order and the first request that fits is
+ * admitted, unless an earlier one has waited more than starve_s seconds (then
+ * nothing overtakes it).  If every solve in flight waits for memory and nothing
+ * else can free any, the solve admitted last goes back to the head of the queue
+ * and runs again later from its first block.  A result (U, S, V inside the pool,
+ * leading dimension ld = rank_out) stays valid until farpca_server_release(tag).
+ * Results are bitwise the same whether a request runs alone, among others, or
+ * through farpca_run.  Tags must be unique among queued, running and unreleased
+ * requests.  Times are seconds since the server was created (steady clock).
+ * The kernel-timing switch below must be off while a server runs. */
 typedef struct farpca_result {
   uint64_t tag;
-  int32_t status;        /* farpca_run's return value                                  */
+  int32_t status;        /* the solve's status (as farpca_run would return it)          */
   int32_t reserved0;
   farpca_info info;
   double t_submit, t_admit, t_done;
@@ -241,7 +314,9 @@ typedef struct farpca_result {
 typedef struct farpca_server_s farpca_server_t;
 size_t farpca_request_footprint(const farpca_params *params);   /* 0 if the params are invalid */
 int farpca_server_create(size_t pool_bytes, int slots, double starve_s, farpca_server_t **out);
-/* FARPCA_E_NOMEM: the request can never fit the pool; FARPCA_E_INVALID: bad params or tag. */
+/* farpca_request_footprint: the most a request can hold (every block, the final part for
+ * l_max, U S V for l_max columns).  Submit returns FARPCA_E_NOMEM when that can never fit
+ * the pool, FARPCA_E_INVALID for bad params or tag. */
 int farpca_server_submit(farpca_server_t *srv, const farpca_params *params, const void *dA,
                          uint64_t tag);
 /* Up to max_out finished results (waits up to wait_ms for the first); returns the count. */
@@ -252,6 +327,10 @@ int farpca_server_release(farpca_server_t *srv, uint64_t tag);
 int farpca_server_fetch(farpca_server_t *srv, const farpca_result *res, float *dU, int64_t ldu,
                         double *dS, float *dV, int64_t ldv, void *stream);
 int farpca_server_stats(farpca_server_t *srv, int *queued, int *running, size_t *largest_free);
+/* Pool bytes granted now and at most so far, loop parts moved to larger ones,
+ * solves put back in the queue for want of memory (any pointer may be NULL). */
+int farpca_server_memory(farpca_server_t *srv, size_t *in_use, size_t *peak, int64_t *grows,
+                         int64_t *preemptions);
 /* Waits for running requests, drops queued ones, frees the pool (results become invalid). */
 int farpca_server_destroy(farpca_server_t *srv);
 

@@ -52,12 +52,15 @@ def threshold32(p: float) -> int:
 
 
 def default_p(sketch: str, m: int, n: int) -> float:
-    """Section 5.1 / 5.4 rules: p1 = max(1e-3, ln N / N) for the standardized
-    Bernoulli sketch, p2 = max(1e-3, 10 / N) for the others, N = max(m, n)."""
-    big = max(m, n)
+    """Section 5.2 / 5.4 rules: p1 = max(1e-3, ln n / n) for the standardized
+    Bernoulli sketch, p2 = max(1e-3, 10 / n) for the others.  The paper's
+    matrices are square; for an m x n A the n here is the number of rows of the
+    n x b test matrix Omega_j, so that a column of Omega_j holds about ln n
+    (p1) or 10 (p2) nonzeros whatever m is."""
+    del m
     if sketch == "std_bernoulli":
-        return max(1e-3, math.log(big) / big)
-    return max(1e-3, 10.0 / big)
+        return max(1e-3, math.log(n) / n)
+    return max(1e-3, 10.0 / n)
 
 
 def sketch_scale(sketch: str, p: float, zeta: int) -> float:

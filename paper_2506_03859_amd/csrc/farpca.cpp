@@ -66,24 +66,37 @@ struct farpca_plan_s {
   float sketch_scale;   // scale applied to the sketch sums
   int64_t maxblk;
   int64_t lmax;
-  int64_t ldq;          // leading dimension of Q and C^T
   int64_t nchunks;
-  // workspace layout (byte offsets)
+  // Workspace layout (byte offsets).  The loop part holds what the block
+  // loop needs, with Q and C^T sized for `cap` blocks (leading dimension ldq);
+  // the final part (step a10) is sized for the basis the run reached.  A full
+  // workspace (farpca_run) is the loop part for every block, then the final
+  // part for l_max at off_final.
+  int64_t cap;          // blocks Q and C^T have room for in the loop layout
+  int64_t ldq;          // leading dimension of Q and C^T (cap b rounded to 4)
   size_t off_q, off_ct, off_s, off_y, off_x, off_g, off_om, off_mask, off_neg, off_colptr,
       off_ent, off_z, off_rowsum, off_r, off_part, off_gpart, off_g64, off_rinv, off_w64,
-      off_v64, off_setup, off_sq, off_scal, off_ehist, off_kbig, off_eig, off_wfin, off_vfin,
-      off_u32, off_gbig, off_xt, off_flat, off_colcnt, total;
-  size_t gbig_bytes;
+      off_v64, off_setup, off_sq, off_scal, off_ehist, off_xt, off_flat, off_colcnt, loop_bytes;
+  size_t off_final, total;
   int64_t part_floats;  // capacity of the K-split partial buffer
   // state of a run between farpca_begin and farpca_finish (host side)
   int stage = 0;        // 0 idle, 1 blocks running, 2 block loop done
   const void *run_a = nullptr;
-  char *run_work = nullptr;
+  char *run_work = nullptr;     // loop part of the running solve
+  char *run_final = nullptr;    // final part inside a full workspace (null: given at finish)
+  size_t run_work_bytes = 0;
+  bool own_ehist = true;        // the E history lives in the loop part
   double *run_ehist = nullptr;
   double norm_a2 = 0.0, stop_thr = 0.0;   // ||A||_F^2, tol^2 ||A||_F^2
   int64_t l = 0;
   int blocks = 0;
   int status = FARPCA_NOT_CONVERGED;
+  // a block enqueued by farpca_step_async whose E read-back has not been
+  // examined yet; the read-back lands in pinned host memory, its completion is
+  // marked by an event (both created on first use, released by farpca_free)
+  bool step_pending = false;
+  double *h_e = nullptr;
+  hipEvent_t ev_step = nullptr;
   // K splits the partial buffer holds for an M-row product
   int64_t part_splits(int64_t M) const { return M > 0 ? part_floats / (M * kBld) : 1; }
 };
@@ -116,7 +129,75 @@ struct Ws {
   T *at(size_t off) const { return reinterpret_cast<T *>(base + off); }
 };
 
+// Final part (step a10) for an l-column basis: K = C C^T, the eigensolver's
+// scratch, eigenvalues, eigenvectors (FP64 and FP32), the Gram partials.
+struct FinalLayout {
+  size_t kbig, eig, wfin, vfin, u32, gbig, gbig_bytes, total;
+};
+FinalLayout final_layout(int64_t n, int64_t l) {
+  FinalLayout f;
+  Carver c;
+  f.kbig = c.take((size_t)l * l * 8);
+  f.eig = c.take(eig_workspace_bytes(l));
+  f.wfin = c.take((size_t)l * 8);
+  f.vfin = c.take((size_t)l * l * 8);
+  f.u32 = c.take((size_t)l * l * 4);
+  f.gbig_bytes = gram_big_workspace_bytes(n, l);
+  f.gbig = c.take(f.gbig_bytes);
+  f.total = c.cur;
+  return f;
+}
+
 }  // namespace
+
+// Loop part for a capacity of cap blocks: sets ldq and the loop offsets,
+// returns its size.
+static size_t carve_loop(farpca_plan_s *pl, int64_t cap) {
+  const farpca_params &q = pl->prm;
+  const int64_t m = q.m, n = q.n, b = pl->b;
+  pl->cap = cap;
+  pl->ldq = (cap * b + 3) / 4 * 4;
+  const int64_t ldq = pl->ldq;
+  const int64_t mnl = imax(imax(m, n), pl->lmax);
+  Carver c;
+  pl->off_q = c.take((size_t)m * ldq * 4);
+  pl->off_ct = c.take((size_t)n * ldq * 4);
+  pl->off_s = c.take((size_t)m * kBld * 4);
+  pl->off_y = c.take((size_t)m * kBld * 4);
+  pl->off_x = c.take((size_t)n * kBld * 4);
+  pl->off_g = c.take((size_t)n * kBld * 4);
+  pl->off_om = c.take((size_t)n * kBld * 4);
+  pl->off_mask = c.take((size_t)n * 8);
+  pl->off_neg = c.take((size_t)n * 8);
+  pl->off_colptr = c.take((size_t)pl->nchunks * (kMaxBlock + 1) * 4);
+  pl->off_ent = c.take((size_t)pl->nchunks * kEntCap * sizeof(ChunkEntry));
+  pl->off_z = c.take((size_t)m * 4);
+  pl->off_rowsum = c.take((size_t)imax(m, n) * 8);   // column-major setup: n stored rows
+  pl->off_r = c.take((size_t)ldq * kBld * 4);
+  pl->part_floats = 16 * mnl * kBld;
+  pl->off_part = c.take((size_t)pl->part_floats * 4);
+  pl->off_gpart = c.take((size_t)gram_max_partials() * kMaxBlock * kMaxBlock * 8);
+  pl->off_g64 = c.take((size_t)kMaxBlock * kMaxBlock * 8);
+  pl->off_rinv = c.take((size_t)kMaxBlock * kMaxBlock * 8);
+  pl->off_w64 = c.take((size_t)kMaxBlock * 8);
+  pl->off_v64 = c.take((size_t)kMaxBlock * kMaxBlock * 8);
+  pl->off_setup = c.take((size_t)imax(setup_num_partials(m), setup_num_partials(n)) * 8);
+  pl->off_sq = c.take((size_t)256 * 8);                               // <= 256 partials for any K
+  pl->off_scal = c.take(64);                        // nA2, E, alpha, flags, truncation rank
+  pl->off_ehist = c.take((size_t)pl->maxblk * 8);
+  pl->off_xt = pl->bf16 ? c.take(bf16_pack_bytes(imax(m, n))) : 0;
+  // column-major: one list per column of Omega_j over all n rows
+  pl->off_flat = pl->colmajor ? c.take((size_t)b * n * sizeof(ChunkEntry)) : 0;
+  pl->off_colcnt = pl->colmajor ? c.take((size_t)kMaxBlock * 4) : 0;
+  pl->loop_bytes = c.cur;
+  return c.cur;
+}
+
+// The layout of a full workspace (every block, final part for l_max).
+static void carve_full(farpca_plan_s *pl) {
+  pl->off_final = carve_loop(pl, pl->maxblk);
+  pl->total = pl->off_final + final_layout(pl->prm.n, pl->lmax).total;
+}
 
 extern "C" const char *farpca_status_str(int status) {
   switch (status) {
@@ -145,7 +226,7 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   if (q.rank < 0 || q.max_blocks < 0) return FARPCA_E_INVALID;
   if (q.rank == 0 && !(q.tol > 0.0 && std::isfinite(q.tol))) return FARPCA_E_INVALID;
   if (!(q.sketch_p >= 0.0 && q.sketch_p < 1.0)) return FARPCA_E_INVALID;
-  const int64_t mn = imin(q.m, q.n), big = imax(q.m, q.n);
+  const int64_t mn = imin(q.m, q.n);
   int b = q.block ? q.block : (int)imin(imax(20, mn / 100), 50);
   if (b > mn) {
     if (q.block) return FARPCA_E_INVALID;
@@ -164,8 +245,11 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   pl->zeta = (q.sketch == FARPCA_SPARSE_SIGN) ? q.sketch_zeta : 0;
   double p = q.sketch_p;
   if (p == 0.0) {
-    p = (q.sketch == FARPCA_STD_BERNOULLI) ? std::fmax(1e-3, std::log((double)big) / (double)big)
-                                           : std::fmax(1e-3, 10.0 / (double)big);
+    // Section 5's rules with N the number of rows of Omega_j (the columns of A):
+    // about ln N (p1) or 10 (p2) nonzeros per column of the test matrix
+    const double N = (double)q.n;
+    p = (q.sketch == FARPCA_STD_BERNOULLI) ? std::fmax(1e-3, std::log(N) / N)
+                                           : std::fmax(1e-3, 10.0 / N);
   }
   pl->p = p;
   const double tp = std::floor(p * 4294967296.0);
@@ -187,61 +271,35 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   if (maxblk < 1) maxblk = 1;
   pl->maxblk = maxblk;
   pl->lmax = maxblk * b;
-  pl->ldq = (pl->lmax + 3) / 4 * 4;
   pl->nchunks = (q.n + kChunk - 1) / kChunk;
-
-  const int64_t m = q.m, n = q.n, lmax = pl->lmax, ldq = pl->ldq;
-  const int64_t mnl = imax(imax(m, n), ldq);
-  Carver c;
-  pl->off_q = c.take((size_t)m * ldq * 4);
-  pl->off_ct = c.take((size_t)n * ldq * 4);
-  pl->off_s = c.take((size_t)m * kBld * 4);
-  pl->off_y = c.take((size_t)m * kBld * 4);
-  pl->off_x = c.take((size_t)n * kBld * 4);
-  pl->off_g = c.take((size_t)n * kBld * 4);
-  pl->off_om = c.take((size_t)n * kBld * 4);
-  pl->off_mask = c.take((size_t)n * 8);
-  pl->off_neg = c.take((size_t)n * 8);
-  pl->off_colptr = c.take((size_t)pl->nchunks * (kMaxBlock + 1) * 4);
-  pl->off_ent = c.take((size_t)pl->nchunks * kEntCap * sizeof(ChunkEntry));
-  pl->off_z = c.take((size_t)m * 4);
-  pl->off_rowsum = c.take((size_t)imax(m, n) * 8);   // column-major setup: n stored rows
-  pl->off_r = c.take((size_t)ldq * kBld * 4);
-  pl->part_floats = 16 * mnl * kBld;
-  pl->off_part = c.take((size_t)pl->part_floats * 4);
-  pl->off_gpart = c.take((size_t)gram_max_partials() * kMaxBlock * kMaxBlock * 8);
-  pl->off_g64 = c.take((size_t)kMaxBlock * kMaxBlock * 8);
-  pl->off_rinv = c.take((size_t)kMaxBlock * kMaxBlock * 8);
-  pl->off_w64 = c.take((size_t)kMaxBlock * 8);
-  pl->off_v64 = c.take((size_t)kMaxBlock * kMaxBlock * 8);
-  pl->off_setup = c.take((size_t)imax(setup_num_partials(m), setup_num_partials(n)) * 8);
-  pl->off_sq = c.take((size_t)256 * 8);                               // <= 256 partials for any K
-  pl->off_scal = c.take(64);                        // nA2, E, alpha, flags, truncation rank
-  pl->off_ehist = c.take((size_t)maxblk * 8);
-  pl->off_kbig = c.take((size_t)lmax * lmax * 8);
-  pl->off_eig = c.take(eig_workspace_bytes(lmax));
-  pl->off_wfin = c.take((size_t)lmax * 8);
-  pl->off_vfin = c.take((size_t)lmax * lmax * 8);
-  pl->off_u32 = c.take((size_t)lmax * lmax * 4);
-  const size_t gbig = gram_big_workspace_bytes(n, lmax);
-  pl->off_gbig = c.take(gbig);
-  pl->gbig_bytes = gbig;
-  pl->off_xt = pl->bf16 ? c.take(bf16_pack_bytes(imax(m, n))) : 0;
-  // column-major: one list per column of Omega_j over all n rows
-  pl->off_flat = colmajor ? c.take((size_t)b * n * sizeof(ChunkEntry)) : 0;
-  pl->off_colcnt = colmajor ? c.take((size_t)kMaxBlock * 4) : 0;
-  if (colmajor && (int64_t)colsum_num_splits(m, n) * m * 2 > pl->part_floats) {
+  carve_full(pl);
+  if (colmajor && (int64_t)colsum_num_splits(q.m, q.n) * q.m * 2 > pl->part_floats) {
     delete pl;
     return FARPCA_E_INVALID;
   }
-  pl->total = c.cur;
   *out = pl;
-  if (l_max) *l_max = lmax;
+  if (l_max) *l_max = pl->lmax;
   if (workspace_bytes) *workspace_bytes = pl->total;
   return FARPCA_OK;
 }
 
-extern "C" void farpca_free(farpca_plan_t *plan) { delete plan; }
+namespace farpca_int {
+int64_t plan_max_blocks(const ::farpca_plan_s *plan) { return plan ? plan->maxblk : 0; }
+int64_t plan_rank_out(const ::farpca_plan_s *plan) {
+  if (!plan || plan->blocks == 0) return 0;
+  return plan->prm.rank > 0 ? imin(plan->prm.rank, plan->l) : plan->l;
+}
+}  // namespace farpca_int
+
+extern "C" void farpca_free(farpca_plan_t *plan) {
+  if (!plan) return;
+  if (plan->ev_step) {
+    hipEventSynchronize(plan->ev_step);
+    hipEventDestroy(plan->ev_step);
+  }
+  if (plan->h_e) hipHostFree(plan->h_e);
+  delete plan;
+}
 
 namespace {
 
@@ -451,14 +509,23 @@ void cholqr(const farpca_plan_s *pl, const Ws &w, float *X, int64_t K, int passe
 
 }  // namespace
 
-extern "C" int farpca_begin(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_bytes,
-                            double *dEhist, void *stream) {
-  if (!plan || !dA || !dWork) return FARPCA_E_INVALID;
-  farpca_plan_s *pl = plan;
+// Step a0 on a workspace that is either full (cap < 0: every block and the
+// final part) or a loop part with room for cap blocks.
+static int begin_impl(farpca_plan_s *pl, const void *dA, void *dWork, size_t work_bytes,
+                      int64_t cap, double *dEhist, hipStream_t st) {
+  if (pl->step_pending) {            // a pending block of an abandoned run
+    hipEventSynchronize(pl->ev_step);
+    pl->step_pending = false;
+  }
   pl->stage = 0;
-  if (work_bytes < pl->total) return FARPCA_E_NOMEM;
   if ((reinterpret_cast<uintptr_t>(dWork) & 255) != 0) return FARPCA_E_INVALID;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (cap < 0) {
+    carve_full(pl);
+    if (work_bytes < pl->total) return FARPCA_E_NOMEM;
+  } else {
+    if (cap < 1 || cap > pl->maxblk) return FARPCA_E_INVALID;
+    if (work_bytes < carve_loop(pl, cap)) return FARPCA_E_NOMEM;
+  }
   const farpca_params &q = pl->prm;
   Ws w{static_cast<char *>(dWork)};
   double *scal = w.at<double>(pl->off_scal);
@@ -480,6 +547,9 @@ extern "C" int farpca_begin(farpca_plan_t *plan, const void *dA, void *dWork, si
     launch_scale_rowsum(w.at<double>(pl->off_rowsum), q.m, pl->p, w.at<float>(pl->off_z), st);
   pl->run_a = dA;
   pl->run_work = static_cast<char *>(dWork);
+  pl->run_work_bytes = work_bytes;
+  pl->run_final = cap < 0 ? pl->run_work + pl->off_final : nullptr;
+  pl->own_ehist = dEhist == nullptr;
   pl->run_ehist = dEhist ? dEhist : w.at<double>(pl->off_ehist);
   pl->norm_a2 = h_scal[0];
   pl->stop_thr = q.tol * q.tol * pl->norm_a2;
@@ -490,12 +560,74 @@ extern "C" int farpca_begin(farpca_plan_t *plan, const void *dA, void *dWork, si
   return FARPCA_OK;
 }
 
-extern "C" int farpca_step(farpca_plan_t *plan, void *stream) {
-  if (!plan) return FARPCA_E_INVALID;
+extern "C" int farpca_begin(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_bytes,
+                            double *dEhist, void *stream) {
+  if (!plan || !dA || !dWork) return FARPCA_E_INVALID;
+  return begin_impl(plan, dA, dWork, work_bytes, -1, dEhist, static_cast<hipStream_t>(stream));
+}
+
+extern "C" size_t farpca_loop_bytes(farpca_plan_t *plan, int64_t cap_blocks) {
+  if (!plan || cap_blocks < 1 || cap_blocks > plan->maxblk) return 0;
+  // sizing only: the layout of a running solve is left as it is
+  farpca_plan_s probe = *plan;
+  probe.h_e = nullptr;
+  probe.ev_step = nullptr;
+  return carve_loop(&probe, cap_blocks);
+}
+
+extern "C" int farpca_begin_loop(farpca_plan_t *plan, const void *dA, void *dLoop, size_t bytes,
+                                 int64_t cap_blocks, double *dEhist, void *stream) {
+  if (!plan || !dA || !dLoop) return FARPCA_E_INVALID;
+  if (cap_blocks < 1 || cap_blocks > plan->maxblk) return FARPCA_E_INVALID;
+  return begin_impl(plan, dA, dLoop, bytes, cap_blocks, dEhist, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int farpca_grow(farpca_plan_t *plan, void *dLoop, size_t bytes, int64_t cap_blocks,
+                           void *stream) {
+  if (!plan || !dLoop) return FARPCA_E_INVALID;
   farpca_plan_s *pl = plan;
-  if (pl->stage == 2) return 0;
-  if (pl->stage != 1) return FARPCA_E_INVALID;
+  if (pl->stage != 1 || pl->step_pending || pl->run_final) return FARPCA_E_INVALID;
+  if (cap_blocks < pl->cap || cap_blocks > pl->maxblk) return FARPCA_E_INVALID;
+  if ((reinterpret_cast<uintptr_t>(dLoop) & 255) != 0) return FARPCA_E_INVALID;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const farpca_params &q = pl->prm;
+  // offsets of the current layout, then the new one
+  farpca_plan_s old = *pl;
+  old.h_e = nullptr;
+  old.ev_step = nullptr;
+  if (bytes < carve_loop(pl, cap_blocks)) {
+    carve_loop(pl, old.cap);
+    return FARPCA_E_NOMEM;
+  }
+  Ws wo{pl->run_work}, wn{static_cast<char *>(dLoop)};
+  const int64_t l = pl->l;
+  // the state the block loop carries: Q and C^T (l columns each), the
+  // scalars (||A||^2, E, alpha, flags), the row sums z, the E history
+  if (l > 0) {
+    HIP_OK(hipMemcpy2DAsync(wn.at<float>(pl->off_q), pl->ldq * 4, wo.at<float>(old.off_q), old.ldq * 4,
+                            l * 4, q.m, hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpy2DAsync(wn.at<float>(pl->off_ct), pl->ldq * 4, wo.at<float>(old.off_ct),
+                            old.ldq * 4, l * 4, q.n, hipMemcpyDeviceToDevice, st));
+  }
+  HIP_OK(hipMemcpyAsync(wn.at<char>(pl->off_scal), wo.at<char>(old.off_scal), 64,
+                        hipMemcpyDeviceToDevice, st));
+  if (pl->kind == FARPCA_STD_BERNOULLI)
+    HIP_OK(hipMemcpyAsync(wn.at<char>(pl->off_z), wo.at<char>(old.off_z), (size_t)q.m * 4,
+                          hipMemcpyDeviceToDevice, st));
+  if (pl->own_ehist) {
+    HIP_OK(hipMemcpyAsync(wn.at<char>(pl->off_ehist), wo.at<char>(old.off_ehist),
+                          (size_t)pl->maxblk * 8, hipMemcpyDeviceToDevice, st));
+    pl->run_ehist = wn.at<double>(pl->off_ehist);
+  }
+  pl->run_work = static_cast<char *>(dLoop);
+  pl->run_work_bytes = bytes;
+  return FARPCA_OK;
+}
+
+// One block of the method (Algorithm 1/2: test matrix, sketch, power steps,
+// basis extension, indicator update), enqueued on `st`, followed by an
+// asynchronous read-back of E into pinned host memory and an event.
+static int enqueue_block(farpca_plan_s *pl, hipStream_t st) {
   const farpca_params &q = pl->prm;
   const int64_t m = q.m, n = q.n;
   const int b = pl->b;
@@ -511,6 +643,13 @@ extern "C" int farpca_step(farpca_plan_t *plan, void *stream) {
   float *part = w.at<float>(pl->off_part);
   const int64_t j = pl->blocks;
   int64_t l = pl->l;
+  if (l + b > pl->cap * b) return FARPCA_E_NOMEM;   // grow the loop part first
+  if (!pl->h_e) {
+    void *h = nullptr;
+    HIP_OK(hipHostMalloc(&h, 64, hipHostMallocDefault));
+    pl->h_e = static_cast<double *>(h);
+  }
+  if (!pl->ev_step) HIP_OK(hipEventCreateWithFlags(&pl->ev_step, hipEventDisableTiming));
 
   gen_omega(pl, w, j, st);
   sketch(pl, w, A, S, st);
@@ -565,12 +704,38 @@ extern "C" int farpca_step(farpca_plan_t *plan, void *stream) {
   l += b;
   pl->l = l;
   pl->blocks = (int)(j + 1);
-  double e_host = 0.0;
-  HIP_OK(hipMemcpyAsync(&e_host, E, 8, hipMemcpyDeviceToHost, st));
-  HIP_OK(hipStreamSynchronize(st));
+  HIP_OK(hipMemcpyAsync(pl->h_e, E, 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipEventRecord(pl->ev_step, st));
+  return FARPCA_OK;
+}
+
+extern "C" int farpca_step_async(farpca_plan_t *plan, void *stream) {
+  if (!plan) return FARPCA_E_INVALID;
+  farpca_plan_s *pl = plan;
+  if (pl->stage == 2 && !pl->step_pending) return 0;
+  if (pl->stage != 1 || pl->step_pending) return FARPCA_E_INVALID;
+  const int rc = enqueue_block(pl, static_cast<hipStream_t>(stream));
+  if (rc != FARPCA_OK) return rc;
+  pl->step_pending = true;
+  return 1;
+}
+
+extern "C" int farpca_step_poll(farpca_plan_t *plan, int wait) {
+  if (!plan) return FARPCA_E_INVALID;
+  farpca_plan_s *pl = plan;
+  if (!pl->step_pending) return pl->stage == 2 ? 0 : (pl->stage == 1 ? 1 : FARPCA_E_INVALID);
+  if (wait) {
+    HIP_OK(hipEventSynchronize(pl->ev_step));
+  } else {
+    const hipError_t e = hipEventQuery(pl->ev_step);
+    if (e == hipErrorNotReady) return 2;
+    if (e != hipSuccess) return FARPCA_E_DEVICE;
+  }
+  pl->step_pending = false;
+  const double e_host = *pl->h_e;
   bool done = false;
-  if (q.rank > 0) {
-    if (l >= q.rank) done = true;
+  if (pl->prm.rank > 0) {
+    if (pl->l >= pl->prm.rank) done = true;
   } else if (e_host < pl->stop_thr) {
     done = true;
   }
@@ -582,12 +747,17 @@ extern "C" int farpca_step(farpca_plan_t *plan, void *stream) {
   return 1;
 }
 
-extern "C" int farpca_finish(farpca_plan_t *plan, void *dU, double *dS, void *dV,
-                             farpca_info *info, void *stream) {
-  if (!plan || !dU || !dS || !dV) return FARPCA_E_INVALID;
-  farpca_plan_s *pl = plan;
-  if (pl->stage == 0 || pl->blocks == 0) return FARPCA_E_INVALID;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+extern "C" int farpca_step(farpca_plan_t *plan, void *stream) {
+  const int rc = farpca_step_async(plan, stream);
+  if (rc != 1) return rc;
+  return farpca_step_poll(plan, 1);
+}
+
+
+// Step a10 with the final part at dFinal (sized for the reached l) and the
+// outputs U (m x ldu), S, V (n x ldv).
+static int finish_impl(farpca_plan_s *pl, char *dFinal, void *dU, int64_t ldu, double *dS,
+                       void *dV, int64_t ldv, farpca_info *info, hipStream_t st) {
   const farpca_params &q = pl->prm;
   const int64_t m = q.m, n = q.n;
   Ws w{pl->run_work};
@@ -597,18 +767,22 @@ extern "C" int farpca_finish(farpca_plan_t *plan, void *dU, double *dS, void *dV
   float *part = w.at<float>(pl->off_part);
   const int64_t l = pl->l;
   const int status = pl->status;
+  // the final part is laid out for l columns (for l_max inside a full workspace)
+  const FinalLayout fl = final_layout(n, pl->run_final ? pl->lmax : l);
+  Ws wf{dFinal};
 
   // Final decomposition: K = C C^T = (C^T)^T C^T, eigenpairs descending.
   const int64_t rout = (q.rank > 0) ? imin(q.rank, l) : l;
-  double *Kbig = w.at<double>(pl->off_kbig);
-  double *wfin = w.at<double>(pl->off_wfin);
-  double *vfin = w.at<double>(pl->off_vfin);
-  float *u32 = w.at<float>(pl->off_u32);
-  launch_gram_big(Ct, pl->ldq, n, l, Kbig, w.at<void>(pl->off_gbig), pl->gbig_bytes, st);
+  double *Kbig = wf.at<double>(fl.kbig);
+  double *wfin = wf.at<double>(fl.wfin);
+  double *vfin = wf.at<double>(fl.vfin);
+  float *u32 = wf.at<float>(fl.u32);
+  launch_gram_big(Ct, pl->ldq, n, l, Kbig, wf.at<void>(fl.gbig), fl.gbig_bytes, st);
   int sweeps;
+  bool eig_ok = false;
   {
     ProfScope ps(FARPCA_PROF_EIG, st);
-    sweeps = eig_sym(Kbig, l, wfin, vfin, w.at<void>(pl->off_eig), kFinalEigRel, st);
+    sweeps = eig_sym(Kbig, l, wfin, vfin, wf.at<void>(fl.eig), kFinalEigRel, st, &eig_ok);
   }
   launch_sqrt_clip(wfin, rout, dS, st);
   launch_trunc_rank(dS, rout, scal, q.tol, q.rank > 0, reinterpret_cast<int64_t *>(scal + 4), st);
@@ -616,14 +790,14 @@ extern "C" int farpca_finish(farpca_plan_t *plan, void *dU, double *dS, void *dV
   launch_convert_f64_f32(vfin, l, rout, l, nullptr, u32, rout, st);
   for (int64_t c0 = 0; c0 < rout; c0 += kBld) {
     const int64_t nc = imin(kBld, rout - c0);
-    launch_gemm_nn(Q, pl->ldq, u32 + c0, rout, static_cast<float *>(dU) + c0, pl->lmax, m, nc, l,
+    launch_gemm_nn(Q, pl->ldq, u32 + c0, rout, static_cast<float *>(dU) + c0, ldu, m, nc, l,
                    1.f, 0.f, 1, part, st);
   }
   // V = C^T U~ Sigma^{-1}
   launch_convert_f64_f32(vfin, l, rout, l, dS, u32, rout, st);
   for (int64_t c0 = 0; c0 < rout; c0 += kBld) {
     const int64_t nc = imin(kBld, rout - c0);
-    launch_gemm_nn(Ct, pl->ldq, u32 + c0, rout, static_cast<float *>(dV) + c0, pl->lmax, n, nc, l,
+    launch_gemm_nn(Ct, pl->ldq, u32 + c0, rout, static_cast<float *>(dV) + c0, ldv, n, nc, l,
                    1.f, 0.f, 1, part, st);
   }
   double h_tail[5];
@@ -640,12 +814,44 @@ extern "C" int farpca_finish(farpca_plan_t *plan, void *dU, double *dS, void *dV
     info->norm_a2 = pl->norm_a2;
     info->err_indicator = h_tail[1];
     info->eig_sweeps = sweeps;
-    int fl = 0;
-    std::memcpy(&fl, &h_tail[3], sizeof(int));
+    int fg = 0;
+    std::memcpy(&fg, &h_tail[3], sizeof(int));
     std::memcpy(&info->rank_trunc, &h_tail[4], sizeof(int64_t));
-    info->dropped = fl & 1;
+    info->dropped = fg & 1;
+    info->eig_converged = eig_ok ? 1 : 0;
+    info->reserved1 = 0;
   }
   return status;
+}
+
+extern "C" int farpca_finish(farpca_plan_t *plan, void *dU, double *dS, void *dV,
+                             farpca_info *info, void *stream) {
+  if (!plan || !dU || !dS || !dV) return FARPCA_E_INVALID;
+  farpca_plan_s *pl = plan;
+  if (pl->stage == 0 || pl->blocks == 0 || pl->step_pending || !pl->run_final)
+    return FARPCA_E_INVALID;
+  return finish_impl(pl, pl->run_final, dU, pl->lmax, dS, dV, pl->lmax, info,
+                     static_cast<hipStream_t>(stream));
+}
+
+extern "C" size_t farpca_final_bytes(farpca_plan_t *plan) {
+  if (!plan || plan->blocks == 0) return 0;
+  return final_layout(plan->prm.n, plan->l).total;
+}
+
+extern "C" int farpca_finish_final(farpca_plan_t *plan, void *dFinal, size_t bytes, void *dU,
+                                   int64_t ldu, double *dS, void *dV, int64_t ldv,
+                                   farpca_info *info, void *stream) {
+  if (!plan || !dFinal || !dU || !dS || !dV) return FARPCA_E_INVALID;
+  farpca_plan_s *pl = plan;
+  if (pl->stage == 0 || pl->blocks == 0 || pl->step_pending) return FARPCA_E_INVALID;
+  if ((reinterpret_cast<uintptr_t>(dFinal) & 255) != 0) return FARPCA_E_INVALID;
+  const int64_t rout = (pl->prm.rank > 0) ? imin(pl->prm.rank, pl->l) : pl->l;
+  if (ldu < rout || ldv < rout) return FARPCA_E_INVALID;
+  if (bytes < final_layout(pl->prm.n, pl->l).total) return FARPCA_E_NOMEM;
+  pl->run_final = nullptr;             // laid out for the reached l
+  return finish_impl(pl, static_cast<char *>(dFinal), dU, ldu, dS, dV, ldv, info,
+                     static_cast<hipStream_t>(stream));
 }
 
 extern "C" int farpca_run(farpca_plan_t *plan, const void *dA, void *dWork, size_t work_bytes,
@@ -708,6 +914,7 @@ extern "C" int farpca_omega(farpca_plan_t *plan, int64_t block_j, void *dWork, s
   if (!plan || !dWork || !dMask || !dNeg || !dDense || block_j < 0) return FARPCA_E_INVALID;
   // the workspace of a run between farpca_begin and farpca_finish is in use
   if (plan->stage != 0) return FARPCA_E_INVALID;
+  carve_full(plan);
   if (work_bytes < plan->total) return FARPCA_E_NOMEM;
   Ws w{static_cast<char *>(dWork)};
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -720,6 +927,7 @@ extern "C" int farpca_sketch(farpca_plan_t *plan, const void *dA, int64_t block_
                              size_t work_bytes, float *dS, void *stream) {
   if (!plan || !dA || !dWork || !dS || block_j < 0) return FARPCA_E_INVALID;
   if (plan->stage != 0) return FARPCA_E_INVALID;     // workspace held by a run
+  carve_full(plan);
   if (work_bytes < plan->total) return FARPCA_E_NOMEM;
   if ((reinterpret_cast<uintptr_t>(dWork) & 255) != 0) return FARPCA_E_INVALID;
   farpca_plan_s *pl = plan;
@@ -818,10 +1026,12 @@ extern "C" int farpca_gemm_bf16_tn(const uint16_t *dA, int64_t lda, const float 
 extern "C" size_t farpca_eig_scratch_bytes(int64_t l) { return eig_workspace_bytes(l); }
 
 extern "C" int farpca_eig(const double *dK, int64_t l, double *dW, double *dV, void *dWork,
-                          void *stream) {
-  if (!dK || !dW || !dV || !dWork || l < 1) return FARPCA_E_INVALID;
-  const int sweeps = eig_sym(dK, l, dW, dV, dWork, 0.0, static_cast<hipStream_t>(stream));
+                          double rel, int *converged, void *stream) {
+  if (!dK || !dW || !dV || !dWork || l < 1 || !(rel < 1.0)) return FARPCA_E_INVALID;
+  bool ok = false;
+  const int sweeps = eig_sym(dK, l, dW, dV, dWork, rel, static_cast<hipStream_t>(stream), &ok);
   HIP_OK(hipGetLastError());
+  if (converged) *converged = ok ? 1 : 0;
   return sweeps;
 }
 

@@ -473,12 +473,6 @@ void launch_gemm_finish(const float *part, int nsp, int64_t M, int64_t N, float 
                                       nullptr, 0.f, st);
 }
 
-// Waves along the output dimension: 4 once there are enough 256-row tiles
-// and K is long enough to keep them busy; short products (the basis products
-// Q r, K = l) take one 64-row tile per workgroup, four times as many
-// workgroups, with K interleaved over the waves.
-static int gemm_wm(int64_t M, int64_t K) { return (M >= 8192 && K >= 1024) ? 4 : 1; }
-
 // Workgroups of the aligned kernel for (TN, WM) that are resident on the
 // current device at once (compute units x occupancy); queried once per device.
 static int64_t gemm_slots(int is_tn, int wm) {
@@ -504,29 +498,58 @@ static int64_t gemm_slots(int is_tn, int wm) {
   return slots;
 }
 
-// Number of K splits: all workgroups should run in as few rounds of resident
-// workgroups as possible, each split long enough (>= 256 K rows), and the
-// partial tiles (written and read once more) cheap next to A.  Time is
-// modelled as rounds x (K / s) x (1 + 128 s / K).
-int gemm_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split) {
-  if (M < 1 || K < 1) return 1;
-  const int wm = gemm_wm(M, K);
+// Modelled time of the layout WM with sp K splits, in units of one wave's
+// MFMA work on one 64-row tile per K row: rounds of resident workgroups x the
+// K rows each wave walks (K / sp, or K / (4 sp) when the four waves
+// interleave K) x the cost of the partial tiles (written and read once more)
+// x the bytes staged per byte of A (the skinny chunk feeds 4 tiles at WM = 4,
+// one at WM = 1) x the padding of the last tile.
+static double gemm_cost(int64_t M, int64_t K, int wm, int64_t sp, int64_t slots) {
   const int64_t tiles = (M + 64 * wm - 1) / (64 * wm);
-  const int64_t slots = gemm_slots(is_tn, wm);
-  int64_t smax = K / 256;
-  if (smax > max_split) smax = max_split;
+  const int64_t rounds = (tiles * sp + slots - 1) / slots;
+  const double depth = (double)K / (double)sp / (wm == 4 ? 1.0 : 4.0);
+  const double staged = wm == 4 ? 1.25 : 2.0;
+  const double pad = (double)(tiles * 64 * wm) / (double)M;
+  return (double)rounds * depth * (1.0 + 128.0 * (double)sp / (double)K) * staged * pad;
+}
+
+// Best split count of layout wm for at most smax splits (and its cost).
+static int gemm_best_split(int64_t M, int64_t K, int wm, int64_t smax, int64_t slots, double *cost) {
+  if (smax > K / 256) smax = K / 256;
   if (smax > 64) smax = 64;
+  if (smax < 1) smax = 1;
   int best = 1;
   double best_cost = 0.0;
-  for (int64_t sp = 1; sp <= (smax < 1 ? 1 : smax); ++sp) {
-    const int64_t rounds = (tiles * sp + slots - 1) / slots;
-    const double cost = (double)rounds / (double)sp * (1.0 + 128.0 * (double)sp / (double)K);
-    if (sp == 1 || cost < best_cost * (1.0 - 1e-9)) {
+  for (int64_t sp = 1; sp <= smax; ++sp) {
+    const double c = gemm_cost(M, K, wm, sp, slots);
+    if (sp == 1 || c < best_cost * (1.0 - 1e-9)) {
       best = (int)sp;
-      best_cost = cost;
+      best_cost = c;
     }
   }
+  if (cost) *cost = best_cost;
   return best;
+}
+
+// Waves along the output dimension: the cheaper layout under the model
+// (short products, K < 1024 - the basis products Q r, K = l - always take
+// WM = 1).  The choice does not depend on the caller's split limit, so that
+// launch and split choice agree.
+static int gemm_wm(int64_t M, int64_t K, int is_tn) {
+  if (K < 1024) return 1;
+  double c1 = 0.0, c4 = 0.0;
+  gemm_best_split(M, K, 1, 64, gemm_slots(is_tn, 1), &c1);
+  gemm_best_split(M, K, 4, 64, gemm_slots(is_tn, 4), &c4);
+  return c4 < c1 ? 4 : 1;
+}
+
+// Number of K splits for the chosen layout: all workgroups in as few rounds
+// of resident workgroups as possible, each split at least 256 K rows, the
+// partial tiles cheap next to A.
+int gemm_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split) {
+  if (M < 1 || K < 1) return 1;
+  const int wm = gemm_wm(M, K, is_tn);
+  return gemm_best_split(M, K, wm, max_split, gemm_slots(is_tn, wm), nullptr);
 }
 
 static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -537,7 +560,7 @@ static int launch_main(const float *A, int64_t lda, const float *X, int64_t ldx,
                        int ksplit, float *part, hipStream_t st) {
   if (M <= 0 || N <= 0) return 1;
   if (ksplit < 1) ksplit = 1;
-  const int wm = gemm_wm(M, K);
+  const int wm = gemm_wm(M, K, TN ? 1 : 0);
   const int64_t kc = (wm == 4) ? 32 : 64;        // K rows per chunk (KC)
   int64_t kps = (K + ksplit - 1) / ksplit;
   kps = (kps + 63) / 64 * 64;                    // whole chunks per split

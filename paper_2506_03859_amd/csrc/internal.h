@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+struct farpca_plan_s;   // the plan (farpca.cpp)
+
 namespace farpca_int {
 
 constexpr int kMaxBlock = 64;   // block size b <= 64 (one 64-bit mask per row of Omega)
@@ -168,12 +170,15 @@ size_t eig_workspace_bytes(int64_t l);
 // eigenvalues descending in w[l], eigenvectors in Vout (l x l row-major, column
 // i <-> w[i]).  Returns number of sweeps used (host-synchronous).
 // Off-diagonal entries are reduced until |a_pq| <= rel sqrt(|a_pp a_qq|) (or
-// an absolute floor); rel <= 0 selects the default 1e-14.
+// an absolute floor); rel <= 0 selects the default 1e-14.  *converged (if
+// given) is false when the test still failed after kEigMaxSweeps sweeps.
+constexpr int kEigMaxSweeps = 40;
 int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, double rel,
-            hipStream_t st);
+            hipStream_t st, bool *converged = nullptr);
 // Single-workgroup Jacobi for s <= 64 (used for the b x b Gram in the shift).
+// conv (device, may be null): 1 if the sweeps converged, 0 if they hit the cap.
 void launch_eig_small(const double *K, int s, int ldk, double *w, double *Vout, int ldv,
-                      hipStream_t st);
+                      hipStream_t st, int *conv = nullptr);
 // Y[r][c] = (float)(X[r][c] * f(c)), f(c) = 1 (s null) or 1/s[c] (0 if s[c] == 0).
 void launch_convert_f64_f32(const double *X, int64_t rows, int64_t cols, int64_t ldx,
                             const double *s, float *Y, int64_t ldy, hipStream_t st);
@@ -187,5 +192,11 @@ size_t gram_big_workspace_bytes(int64_t n, int64_t l);
 // `work_bytes` bounds the partial buffers (the split count is reduced to fit).
 void launch_gram_big(const float *X, int64_t ldx, int64_t n, int64_t l, double *K,
                      void *work, size_t work_bytes, hipStream_t st);
+
+// ---- farpca.cpp (plan accessors for the server)
+// blocks a run may reach (l_max / b)
+int64_t plan_max_blocks(const ::farpca_plan_s *plan);
+// columns the final step writes (the fixed rank k, else the reached l; 0 before any block)
+int64_t plan_rank_out(const ::farpca_plan_s *plan);
 
 }  // namespace farpca_int

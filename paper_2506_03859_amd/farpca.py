@@ -24,13 +24,15 @@ DTYPE_IDS = {"f32": 0, "bf16": 1}
 STATUS_OK = 0
 STATUS_NOT_CONVERGED = 1
 
-EXPORTED = ["farpca_plan", "farpca_run", "farpca_run_static", "farpca_begin", "farpca_step", "farpca_finish", "farpca_free", "farpca_status_str", "farpca_omega",
+EXPORTED = ["farpca_plan", "farpca_run", "farpca_run_static", "farpca_begin", "farpca_step",
+            "farpca_step_async", "farpca_step_poll", "farpca_loop_bytes", "farpca_begin_loop",
+            "farpca_grow", "farpca_final_bytes", "farpca_finish_final", "farpca_finish", "farpca_free", "farpca_status_str", "farpca_omega",
             "farpca_sketch", "farpca_gemm_scratch_bytes", "farpca_gemm_nn", "farpca_gemm_tn",
             "farpca_gemm_bf16_scratch_bytes", "farpca_gemm_bf16_nn", "farpca_gemm_bf16_tn",
             "farpca_eig_scratch_bytes", "farpca_eig", "farpca_profile_enable", "farpca_profile_get",
             "farpca_request_footprint", "farpca_server_create", "farpca_server_submit",
             "farpca_server_poll", "farpca_server_release", "farpca_server_fetch",
-            "farpca_server_stats", "farpca_server_destroy"]
+            "farpca_server_stats", "farpca_server_memory", "farpca_server_destroy"]
 PROF_CLASSES = {"sketch": 0, "gemm_tn": 1, "gemm_nn": 2, "eig": 3}
 
 
@@ -48,7 +50,8 @@ class FarpcaInfo(ctypes.Structure):
                 ("blocks", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("norm_a2", ctypes.c_double), ("err_indicator", ctypes.c_double),
                 ("eig_sweeps", ctypes.c_int32), ("dropped", ctypes.c_int32),
-                ("rank_trunc", ctypes.c_int64)]
+                ("rank_trunc", ctypes.c_int64), ("eig_converged", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32)]
 
 
 class FarpcaResult(ctypes.Structure):
@@ -87,6 +90,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.farpca_begin.restype = ctypes.c_int
     lib.farpca_step.argtypes = [vp, vp]
     lib.farpca_step.restype = ctypes.c_int
+    lib.farpca_step_async.argtypes = [vp, vp]
+    lib.farpca_step_async.restype = ctypes.c_int
+    lib.farpca_step_poll.argtypes = [vp, ctypes.c_int]
+    lib.farpca_step_poll.restype = ctypes.c_int
+    lib.farpca_loop_bytes.argtypes = [vp, i64]
+    lib.farpca_loop_bytes.restype = sz
+    lib.farpca_begin_loop.argtypes = [vp, vp, vp, sz, i64, vp, vp]
+    lib.farpca_begin_loop.restype = ctypes.c_int
+    lib.farpca_grow.argtypes = [vp, vp, sz, i64, vp]
+    lib.farpca_grow.restype = ctypes.c_int
+    lib.farpca_final_bytes.argtypes = [vp]
+    lib.farpca_final_bytes.restype = sz
+    lib.farpca_finish_final.argtypes = [vp, vp, sz, vp, i64, vp, vp, i64, ctypes.POINTER(FarpcaInfo), vp]
+    lib.farpca_finish_final.restype = ctypes.c_int
     lib.farpca_finish.argtypes = [vp, vp, vp, vp, ctypes.POINTER(FarpcaInfo), vp]
     lib.farpca_finish.restype = ctypes.c_int
     lib.farpca_free.argtypes = [vp]
@@ -107,7 +124,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         f.restype = ctypes.c_int
     lib.farpca_eig_scratch_bytes.argtypes = [i64]
     lib.farpca_eig_scratch_bytes.restype = sz
-    lib.farpca_eig.argtypes = [vp, i64, vp, vp, vp, vp]
+    lib.farpca_eig.argtypes = [vp, i64, vp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int), vp]
     lib.farpca_eig.restype = ctypes.c_int
     lib.farpca_profile_enable.argtypes = [ctypes.c_int]
     lib.farpca_profile_enable.restype = None
@@ -129,6 +146,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.farpca_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(sz)]
     lib.farpca_server_stats.restype = ctypes.c_int
+    lib.farpca_server_memory.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz),
+                                         ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.farpca_server_memory.restype = ctypes.c_int
     lib.farpca_server_destroy.argtypes = [vp]
     lib.farpca_server_destroy.restype = ctypes.c_int
     _lib = lib
@@ -231,6 +251,50 @@ def farpca_step(plan: Plan, stream=None) -> int:
     return _check(load_library().farpca_step(plan.handle, _stream(stream)), "farpca_step")
 
 
+def farpca_step_async(plan: Plan, stream=None) -> int:
+    """Enqueue the next block (1), or 0 if the run needs none."""
+    return _check(load_library().farpca_step_async(plan.handle, _stream(stream)), "farpca_step_async")
+
+
+def farpca_step_poll(plan: Plan, wait: bool = False) -> int:
+    """2 while the pending block runs (wait=False), else 1 (another block) or 0 (stop)."""
+    return _check(load_library().farpca_step_poll(plan.handle, 1 if wait else 0), "farpca_step_poll")
+
+
+def farpca_loop_bytes(plan: Plan, cap_blocks: int) -> int:
+    return int(load_library().farpca_loop_bytes(plan.handle, cap_blocks))
+
+
+def farpca_begin_loop(plan: Plan, A, loop, cap_blocks: int, ehist=None, stream=None) -> int:
+    """farpca_begin on a loop part with room for cap_blocks blocks."""
+    return _check(load_library().farpca_begin_loop(plan.handle, _ptr(A), _ptr(loop),
+                                                   loop.numel() * loop.element_size(), cap_blocks,
+                                                   _ptr(ehist) if ehist is not None else None,
+                                                   _stream(stream)), "farpca_begin_loop")
+
+
+def farpca_grow(plan: Plan, loop, cap_blocks: int, stream=None) -> int:
+    """Move a run (between blocks) to a larger loop part."""
+    return _check(load_library().farpca_grow(plan.handle, _ptr(loop), loop.numel() * loop.element_size(),
+                                             cap_blocks, _stream(stream)), "farpca_grow")
+
+
+def farpca_final_bytes(plan: Plan) -> int:
+    return int(load_library().farpca_final_bytes(plan.handle))
+
+
+def farpca_finish_final(plan: Plan, final, U, S, V, stream=None):
+    """farpca_finish with a separate final part; U, V row-major with any leading dimension
+    >= rank_out; returns (status, FarpcaInfo)."""
+    lib = load_library()
+    info = FarpcaInfo()
+    rc = lib.farpca_finish_final(plan.handle, _ptr(final), final.numel() * final.element_size(),
+                                 _ptr(U), U.stride(0), _ptr(S), _ptr(V), V.stride(0),
+                                 ctypes.byref(info), _stream(stream))
+    _check(rc, "farpca_finish_final")
+    return rc, info
+
+
 def farpca_finish(plan: Plan, U, S, V, stream=None):
     """Final decomposition of a run begun with farpca_begin; returns (status, FarpcaInfo)."""
     lib = load_library()
@@ -295,10 +359,14 @@ def farpca_eig_scratch_bytes(l: int) -> int:
     return int(load_library().farpca_eig_scratch_bytes(l))
 
 
-def farpca_eig(K, W, V, work, stream=None) -> int:
+def farpca_eig(K, W, V, work, rel=0.0, stream=None):
+    """(sweeps, converged) of the FP64 block-Jacobi eigensolver on K (relative
+    off-diagonal test rel; 0 selects 1e-14)."""
     lib = load_library()
-    return _check(lib.farpca_eig(_ptr(K), K.shape[0], _ptr(W), _ptr(V), _ptr(work), _stream(stream)),
-                  "farpca_eig")
+    conv = ctypes.c_int()
+    sweeps = _check(lib.farpca_eig(_ptr(K), K.shape[0], _ptr(W), _ptr(V), _ptr(work), rel,
+                                   ctypes.byref(conv), _stream(stream)), "farpca_eig")
+    return sweeps, bool(conv.value)
 
 
 def farpca_profile_enable(on: bool) -> None:
@@ -414,6 +482,14 @@ class Server:
         _check(self._lib.farpca_server_stats(self.handle, ctypes.byref(q), ctypes.byref(r), ctypes.byref(f)),
                "farpca_server_stats")
         return q.value, r.value, f.value
+
+    def memory(self):
+        """(bytes granted now, most granted so far, loop parts grown, solves put back)."""
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        g, p = ctypes.c_int64(), ctypes.c_int64()
+        _check(self._lib.farpca_server_memory(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                              ctypes.byref(g), ctypes.byref(p)), "farpca_server_memory")
+        return a.value, b.value, g.value, p.value
 
     def close(self) -> None:
         if self.handle:

@@ -116,6 +116,11 @@ def test_step_entry_points_need_begin(fp):
                                  ctypes.c_void_p(16), None, None) == -1
         assert lib.farpca_begin(plan.handle, None, None, 0, None, None) == -1
         assert lib.farpca_step(None, None) == -1
+        # the two halves of a step: nothing to enqueue or poll before begin
+        assert lib.farpca_step_async(plan.handle, None) == -1
+        assert lib.farpca_step_poll(plan.handle, 0) == -1
+        assert lib.farpca_step_async(None, None) == -1
+        assert lib.farpca_step_poll(None, 1) == -1
     finally:
         plan.free()
 

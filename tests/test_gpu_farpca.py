@@ -59,6 +59,7 @@ def compare(res, ref, a32, tol_rec=2e-5, v_rel=1e-5):
     a = a32.astype(np.float64)
     nA = np.linalg.norm(a)
     assert abs(res.info.norm_a2 - ref.norm_a2) <= 1e-12 * ref.norm_a2
+    assert res.info.eig_converged == 1
     U = res.U.cpu().double().numpy()
     S = res.S.cpu().numpy()
     V = res.V.cpu().double().numpy()
@@ -227,7 +228,7 @@ def _run_whole(fp, plan, A):
 
 def _same_info(a, b):
     for f in ("rank_l", "rank_out", "blocks", "status", "norm_a2", "err_indicator", "eig_sweeps",
-              "dropped", "rank_trunc"):
+              "dropped", "rank_trunc", "eig_converged"):
         assert getattr(a, f) == getattr(b, f), f
 
 
@@ -298,6 +299,126 @@ def test_step_entry_points_interleaved(fp, a_mid):
             assert torch.equal(U[:, :k], outs1[0][:, :k]) and torch.equal(S[:k], outs1[1][:k])
             assert torch.equal(V[:, :k], outs1[2][:, :k])
     finally:
+        for p in plans:
+            p.free()
+
+
+def _aligned_bytes(nbytes, device="cuda"):
+    import torch
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes]
+
+
+@pytest.mark.parametrize("kw", [dict(tol=1e-3, block=32, power=2, sketch="sparse_sign", zeta=8, seed=11),
+                                dict(rank=70, block=30, power=1, sketch="std_bernoulli", seed=2),
+                                dict(tol=1e-9, block=64, power=1, sketch="gaussian", seed=5, max_blocks=3)])
+def test_block_granular_memory_matches_run(fp, a_mid, kw):
+    # a run that starts on a loop part with room for one block, moves to one
+    # twice as large whenever the next block needs room (farpca_grow), and
+    # takes its final part sized for the l it reached (outputs with leading
+    # dimension rank_out) gives farpca_run's results bitwise
+    import torch
+    A = torch.from_numpy(a_mid).cuda()
+    m, n = a_mid.shape
+    print(f"block-granular memory {kw}", flush=True)
+    p1 = fp.farpca_plan(fp.make_params(m, n, **kw))
+    p2 = fp.farpca_plan(fp.make_params(m, n, **kw))
+    try:
+        st1, info1, outs1 = _run_whole(fp, p1, A)
+        cap = 1
+        loop = _aligned_bytes(fp.farpca_loop_bytes(p2, cap))
+        assert fp.farpca_loop_bytes(p2, cap) < p2.workspace_bytes
+        fp.farpca_begin_loop(p2, A, loop, cap)
+        grows = 0
+        max_cap = p2.l_max // kw["block"]
+        lib = fp.load_library()
+        while True:
+            rc = lib.farpca_step_async(p2.handle, fp._stream(None))    # raw status codes
+            if rc == -2:                                                # FARPCA_E_NOMEM: no room
+                cap = min(2 * cap, max_cap)
+                bigger = _aligned_bytes(fp.farpca_loop_bytes(p2, cap))
+                fp.farpca_grow(p2, bigger, cap)
+                torch.cuda.synchronize()          # the copies have run: the old part may go
+                loop = bigger
+                grows += 1
+                continue
+            assert rc in (0, 1), rc
+            if rc == 0 or fp.farpca_step_poll(p2, wait=True) == 0:
+                break
+        fb = fp.farpca_final_bytes(p2)
+        assert 0 < fb
+        final = _aligned_bytes(fb)
+        k = info1.rank_out
+        U = torch.empty((m, k), dtype=torch.float32, device="cuda")
+        S = torch.empty((k,), dtype=torch.float64, device="cuda")
+        V = torch.empty((n, k), dtype=torch.float32, device="cuda")
+        st2, info2 = fp.farpca_finish_final(p2, final, U, S, V)
+        torch.cuda.synchronize()
+        print(f"  blocks={info2.blocks} grows={grows} loop bytes {loop.numel()} final {fb} "
+              f"(full workspace {p2.workspace_bytes})", flush=True)
+        assert st1 == st2 and grows >= 1
+        _same_info(info1, info2)
+        assert torch.equal(U, outs1[0][:, :k]) and torch.equal(S, outs1[1][:k])
+        assert torch.equal(V, outs1[2][:, :k])
+    finally:
+        p1.free()
+        p2.free()
+
+
+def test_step_async_many_streams(fp, a_mid):
+    # blocks of three solves kept in flight from one host thread on three
+    # streams (farpca_step_async enqueues, farpca_step_poll examines E without
+    # waiting) give each solve its own farpca_run result, bitwise
+    import torch
+    a2 = synth.spectral(900, 1300, synth.matrix2_sigma(900), seed=31).astype(np.float32)
+    a3 = synth.spectral(2500, 700, synth.exp_floor_sigma(700, decay=25.0), seed=32).astype(np.float32)
+    mats = [torch.from_numpy(a_mid).cuda(), torch.from_numpy(a2).cuda(), torch.from_numpy(a3).cuda()]
+    kws = [dict(tol=1e-3, block=32, power=2, sketch="sparse_sign", zeta=8, seed=11),
+           dict(tol=1e-2, block=20, power=1, sketch="sparse_gaussian", p=0.05, seed=4),
+           dict(rank=90, block=30, power=1, sketch="std_bernoulli", seed=2)]
+    print("step api async, 3 streams", flush=True)
+    whole, plans, state = [], [], []
+    streams = [torch.cuda.Stream() for _ in mats]
+    try:
+        for A, kw, st in zip(mats, kws, streams):
+            m, n = A.shape
+            pw = fp.farpca_plan(fp.make_params(m, n, **kw))
+            plans.append(pw)
+            whole.append(_run_whole(fp, pw, A))
+            ps = fp.farpca_plan(fp.make_params(m, n, **kw))
+            plans.append(ps)
+            work, U, S, V, eh = fp.alloc_outputs(ps, A.device)
+            torch.cuda.synchronize()
+            fp.farpca_begin(ps, A, work, eh, st)
+            assert fp.farpca_step_async(ps, st) == 1
+            with pytest.raises(fp.FarpcaError):
+                fp.farpca_step_async(ps, st)          # a block is already pending
+            state.append([ps, work, U, S, V, eh, True])
+        polls = 0
+        while any(x[6] for x in state):
+            for i, x in enumerate(state):
+                if not x[6]:
+                    continue
+                r = fp.farpca_step_poll(x[0], wait=False)
+                polls += 1
+                if r == 1:
+                    assert fp.farpca_step_async(x[0], streams[i]) == 1
+                elif r == 0:
+                    x[6] = False
+        print(f"  {polls} polls", flush=True)
+        for i, x in enumerate(state):
+            ps, work, U, S, V, eh, _ = x
+            st, info = fp.farpca_finish(ps, U, S, V, streams[i])
+            torch.cuda.synchronize()
+            st1, info1, outs1 = whole[i]
+            assert st == st1
+            _same_info(info1, info)
+            k = info.rank_out
+            assert torch.equal(U[:, :k], outs1[0][:, :k]) and torch.equal(S[:k], outs1[1][:k])
+            assert torch.equal(V[:, :k], outs1[2][:, :k])
+    finally:
+        torch.cuda.synchronize()
         for p in plans:
             p.free()
 

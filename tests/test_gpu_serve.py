@@ -1,9 +1,10 @@
 """Serving through the C-ABI (farpca_server_*): continuous batching of
-independent solves on one GPU.  Every request completes; the footprints of
-requests that run at the same time never exceed the pool; a request that does
-not fit waits and is admitted once memory is released; and each result is
-bitwise the same alone, in a mix of other requests (FP32 and BF16, other
-shapes) and from farpca_run called directly."""
+independent solves on one GPU, advanced block by block by one scheduler, with
+memory granted by blocks.  Every request completes; the memory granted never
+exceeds the pool, also when it is so small that solves must wait for memory
+or be put back in the queue; each result is bitwise the same alone, in a mix
+of other requests (FP32 and BF16, other shapes), under a tight pool and from
+farpca_run called directly; and a served result matches the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -101,8 +102,11 @@ def test_alone_mix_direct_bitwise(fp):
     for r, (U, S, V) in [alone, mix[x]]:
         assert r.status == st_d
         assert torch.equal(U, Ud) and torch.equal(S, Sd) and torch.equal(V, Vd)
-    for i, (r, _) in mix.items():
-        assert r.status >= 0 and r.info.rank_out > 0, reqs[i][0]
+    # every request of the mix equals its own direct run
+    for i, (r, (U, S, V)) in mix.items():
+        st_i, Ui, Si, Vi = direct(fp, mats[i], prms[i])
+        assert r.status == st_i and r.status >= 0 and r.info.rank_out > 0, reqs[i][0]
+        assert torch.equal(U, Ui) and torch.equal(S, Si) and torch.equal(V, Vi), reqs[i][0]
         assert r.t_submit <= r.t_admit <= r.t_done
 
 
@@ -133,26 +137,68 @@ def test_column_major_request(fp):
     assert torch.equal(U, Ud) and torch.equal(S, Sd) and torch.equal(V, Vd)
 
 
-def test_admission_respects_pool(fp):
+@pytest.mark.parametrize("factor", [1.3, 1.02])
+def test_tight_pool_grows_and_matches(fp, factor):
+    # a pool in which the largest request only fits alone (its worst case times
+    # `factor`): solves start on the memory of two blocks, grow their loop part
+    # as their basis grows, wait for memory or go back to the queue; the memory
+    # granted never exceeds the pool, every request completes, and every result
+    # equals its direct farpca_run bitwise
+    import torch
     reqs = requests_mix()
     mats = [device_matrix(a, st) for _, a, _, st in reqs]
     prms = [fp.make_params(a.shape[0], a.shape[1], a_dtype=st, **kw) for _, a, kw, st in reqs]
     foot = [fp.farpca_request_footprint(p) for p in prms]
-    pool = int(max(foot) * 1.3)            # the largest request only fits alone
-    print(f"serve: admission, pool {pool >> 20} MiB, footprints {[f >> 20 for f in foot]} MiB", flush=True)
+    pool = int(max(foot) * factor)
+    print(f"serve: tight pool {pool >> 20} MiB, worst-case footprints {[f >> 20 for f in foot]} MiB",
+          flush=True)
     srv = fp.Server(pool, slots=4, starve_s=0.05)
     try:
         for rep in range(2):
             for i in range(len(reqs)):
                 srv.submit(prms[i], mats[i], 10 * rep + i)
         got = drain(fp, srv, 2 * len(reqs))
+        in_use, peak, grows, preempted = srv.memory()
     finally:
         srv.close()
-    iv = [(r.t_admit, r.t_done, foot[tag % 10]) for tag, (r, _) in got.items()]
-    for t, _, _ in iv:
-        live = sum(f for a, d, f in iv if a <= t < d)
-        assert live <= pool
+    print(f"  peak granted {peak >> 20} MiB of {pool >> 20}, {grows} loop parts grown, "
+          f"{preempted} solves put back", flush=True)
+    assert peak <= pool and in_use == 0 and grows > 0
     assert all(r.status >= 0 for r, _ in got.values())
+    for tag, (r, (U, S, V)) in got.items():
+        st_i, Ui, Si, Vi = direct(fp, mats[tag % 10], prms[tag % 10])
+        assert r.status == st_i
+        assert torch.equal(U, Ui) and torch.equal(S, Si) and torch.equal(V, Vi), (tag, reqs[tag % 10][0])
+
+
+def test_served_result_matches_oracle(fp):
+    # one served request against the FP64 oracle on the same input (the
+    # whole-path tolerances of the parity tests)
+    from oracle import FarpcaParams, farpca, projection_svd
+    name, a32, kw, _ = requests_mix()[0]
+    A = device_matrix(a32, "f32")
+    prm = fp.make_params(a32.shape[0], a32.shape[1], **kw)
+    print(f"serve: {name} {kw} against the oracle", flush=True)
+    srv = fp.Server(4 * fp.farpca_request_footprint(prm), slots=2)
+    try:
+        srv.submit(prm, A, 3)
+        r, (U, S, V) = drain(fp, srv, 1)[3]
+    finally:
+        srv.close()
+    ref = farpca(a32.astype(np.float64), FarpcaParams(**kw), keep_bases=True)
+    assert r.status == ref.status == 0 and r.info.rank_l == ref.rank
+    a = a32.astype(np.float64)
+    U, S, V = U.cpu().double().numpy(), S.cpu().numpy(), V.cpu().double().numpy()
+    eps_g = np.linalg.norm(a - (U * S) @ V.T) / np.linalg.norm(a)
+    eps_o = np.linalg.norm(a - (ref.U * ref.S) @ ref.V.T) / np.linalg.norm(a)
+    s_def = projection_svd(a, ref.Y)
+    true_e = np.linalg.norm(a - U @ (U.T @ a)) ** 2
+    print(f"  l={r.info.rank_l} eps served={eps_g:.6e} oracle={eps_o:.6e} "
+          f"sigma diff={np.max(np.abs(S - s_def[:S.size])) / s_def[0]:.2e}", flush=True)
+    assert abs(eps_g - eps_o) <= 1e-6
+    assert np.max(np.abs(S - s_def[:S.size])) <= 1e-6 * s_def[0]
+    assert abs(r.info.err_indicator - true_e) <= 1e-7 * ref.norm_a2 + 1e-3 * true_e
+    assert np.abs(U.T @ U - np.eye(U.shape[1])).max() < 1e-5
 
 
 def test_submit_errors(fp):

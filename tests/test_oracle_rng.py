@@ -158,3 +158,18 @@ def test_blocks_and_seeds_independent_streams():
     c = om.omega_dense(500, 16, 0, "sparse_sign", seed=2, zeta=4)
     assert not np.array_equal(a, b) and not np.array_equal(a, c)
     assert np.array_equal(a, om.omega_dense(500, 16, 0, "sparse_sign", seed=1, zeta=4))
+
+
+def test_default_p_rules():
+    # Section 5's rules for the paper's n x n matrices: p1 = max(1e-3, ln n / n)
+    # (standardized Bernoulli), p2 = max(1e-3, 10 / n) (the other sparse matrices)
+    from oracle import default_p
+    assert default_p("std_bernoulli", 5000, 5000) == pytest.approx(math.log(5000) / 5000, rel=1e-15)
+    assert default_p("sparse_sign", 5000, 5000) == pytest.approx(2e-3, rel=1e-15)
+    assert default_p("std_bernoulli", 30000, 30000) == 1e-3      # ln n / n = 3.4e-4 < 1e-3
+    assert default_p("sparse_gaussian", 30000, 30000) == 1e-3
+    # for m x n A the rule follows the n rows of Omega_j: the expected number of
+    # nonzeros in a column of Omega_j, p n, is at least ln n (p1) or 10 (p2) for any m
+    for m in (300, 4000, 200000):
+        assert default_p("std_bernoulli", m, 4000) * 4000 >= math.log(4000) * (1 - 1e-12)
+        assert default_p("bernoulli", m, 4000) * 4000 >= 10 * (1 - 1e-12)
