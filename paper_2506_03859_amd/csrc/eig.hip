@@ -18,8 +18,6 @@
 // entry is negligible relative to its diagonal pair.  Padding rows/columns are
 // exactly zero and never couple (their rotations are the identity).
 #include <cmath>
-#include <cstdio>
-#include <cstdlib>
 #include <cstring>
 
 #include "internal.h"
@@ -565,9 +563,6 @@ int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, dou
     int h_count = 0;
     std::memcpy(&h_count, &h_stat[0], sizeof(int));
     const double diag = h_stat[2], ratio = h_stat[3], offa = h_stat[4];
-    if (std::getenv("FARPCA_EIG_TRACE"))
-      std::fprintf(stderr, "eig l=%ld sweep %d: failing %d ratio %.3e offa/diag %.3e\n", (long)l, sweeps,
-                   h_count, ratio, offa / (diag > 0 ? diag : 1.0));
     if (h_count == 0) { conv = true; break; }
     // a sweep improves when it halves either measure's best value so far;
     // two sweeps in a row without improvement count as a stall

@@ -74,7 +74,7 @@ __device__ __forceinline__ const float *a_base(const float *__restrict__ A, int6
                                                int64_t M, int64_t t0, int li, int lk) {
   if (!TN) return A + 4 * lk;                       // + row * lda + k0 per load
   int64_t col = t0 + 4 * li;
-  if (AVEC) col = col < M - 4 ? col : M - 4;        // AVEC: M % 4 == 0, M >= 4
+  if (AVEC) col = col < M - 4 ? col : M - 4;        // AVEC: here M % 4 == 0, M >= 4
   return A + 4 * lk * lda + col;                    // + (k0 + q) * lda per load
 }
 
@@ -249,6 +249,7 @@ __global__ __launch_bounds__(256, (AVEC && (TN || WM != 4)) ? 3 : 2) void gemm_k
                                                       float *__restrict__ C, int64_t ldc,
                                                       int64_t M, int64_t N, int64_t K,
                                                       int64_t kps, int64_t tiles, int64_t total,
+                                                      int64_t mload,
                                                       float alpha, float beta,
                                                       float *__restrict__ part) {
   constexpr int WK = 4 / WM;
@@ -271,7 +272,10 @@ __global__ __launch_bounds__(256, (AVEC && (TN || WM != 4)) ? 3 : 2) void gemm_k
   const int64_t kb = split * kps;
   const int64_t ke = (kb + kps < K) ? kb + kps : K;
   const int64_t nfull = (ke - kb) / KC;            // chunks entirely inside [kb, ke)
-  const float *ab = a_base<TN, AVEC>(A, lda, M, t0, li, lk);
+  // TN: 16-byte column loads are clamped into the first mload columns (M, or
+  // M rounded up to 4 when the row padding up to lda may be read: its
+  // columns only feed outputs that are never stored)
+  const float *ab = a_base<TN, AVEC>(A, lda, TN ? mload : M, t0, li, lk);
 
   floatx4 acc[16];
 #pragma unroll
@@ -536,7 +540,9 @@ static int gemm_best_split(int64_t M, int64_t K, int wm, int64_t smax, int64_t s
 // WM = 1).  The choice does not depend on the caller's split limit, so that
 // launch and split choice agree.
 static int gemm_wm(int64_t M, int64_t K, int is_tn) {
-  if (K < 1024) return 1;
+  // short NN products over many rows (Q r: K = l, M = m): each wave walks the
+  // whole K range of its own 64 rows, with no cross-wave reduction at the end
+  if (K < 1024) return (!is_tn && M >= 8192) ? 4 : 1;
   double c1 = 0.0, c4 = 0.0;
   gemm_best_split(M, K, 1, 64, gemm_slots(is_tn, 1), &c1);
   gemm_best_split(M, K, 4, 64, gemm_slots(is_tn, 4), &c4);
@@ -569,12 +575,14 @@ static int launch_main(const float *A, int64_t lda, const float *X, int64_t ldx,
   float *p = (nsp > 1) ? part : nullptr;
   const int64_t tiles = (M + 64 * wm - 1) / (64 * wm);
   const int64_t total = tiles * nsp;
-  const bool avec = (lda % 4 == 0) && aligned16(A) && (!TN || (M % 4 == 0 && M >= 4));
+  const int64_t m4 = (M + 3) / 4 * 4;
+  const int64_t mload = (M % 4 == 0) ? M : (m4 <= lda ? m4 : 0);
+  const bool avec = (lda % 4 == 0) && aligned16(A) && (!TN || mload >= 4);
   const bool xvec = (ldx % 4 == 0) && aligned16(X) && N == 64;
   dim3 grid((unsigned)total), blk(256);
 #define FARPCA_GEMM_LAUNCH(WMV, AV, XV)                                                            \
   hipLaunchKernelGGL((gemm_kernel<TN, WMV, AV, XV>), grid, blk, 0, st, A, lda, X, ldx, C, ldc, M, \
-                     N, K, kps, tiles, total, alpha, beta, p)
+                     N, K, kps, tiles, total, mload, alpha, beta, p)
 #define FARPCA_GEMM_LAUNCH_WM(WMV)                  \
   do {                                              \
     if (avec && xvec) FARPCA_GEMM_LAUNCH(WMV, true, true);          \

@@ -38,6 +38,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -177,6 +178,8 @@ struct farpca_server_s {
   // only once they have completed)
   struct Held { Range r; std::vector<hipEvent_t> fetches; };
   std::map<uint64_t, Held> held;
+  // tags from submit to release: queued, running, finished or failed
+  std::set<uint64_t> live;
   std::vector<hipStream_t> streams;
   std::vector<int> free_slots;
   std::deque<FinishJob> fin_jobs;
@@ -607,12 +610,11 @@ extern "C" int farpca_server_submit(farpca_server_t *s, const farpca_params *prm
   r.footprint = round_up(ws) + outputs_bytes(prm->m, prm->n, r.lmax);
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop || r.footprint > s->pool_bytes || s->held.count(tag)) {
+    if (s->stop || r.footprint > s->pool_bytes || s->live.count(tag)) {
       farpca_free(r.plan);
       return r.footprint > s->pool_bytes ? FARPCA_E_NOMEM : FARPCA_E_INVALID;
     }
-    for (const auto &q : s->queue)
-      if (q.tag == tag) { farpca_free(r.plan); return FARPCA_E_INVALID; }
+    s->live.insert(tag);
     r.t_submit = now_s(s->t0);
     s->queue.push_back(r);
   }
@@ -659,6 +661,7 @@ extern "C" int farpca_server_release(farpca_server_t *s, uint64_t tag) {
     }
     give_back(s, it->second.r);
     s->held.erase(it);
+    s->live.erase(tag);
   }
   s->cv_work.notify_all();
   return FARPCA_OK;

@@ -218,8 +218,14 @@ def test_submit_errors(fp):
         srv.submit(prm, a, 7)
         with pytest.raises(fp.FarpcaError, match="invalid"):
             srv.submit(prm, a, 7)            # tag already queued or running
-        got = drain(fp, srv, 1)
+        got = drain(fp, srv, 1)             # releases tag 7
         # all-zero A: zero norm, the loop stops at once with E = 0 < tol^2 * 0 false -> the cap
         assert got[7][0].status >= 0
+        srv.submit(prm, a, 7)                # a released tag may be used again
+        with pytest.raises(fp.FarpcaError, match="invalid"):
+            srv.submit(prm, a, 7)
+        assert drain(fp, srv, 1)[7][0].status >= 0
+        with pytest.raises(fp.FarpcaError, match="invalid"):
+            srv.release(7)                   # already released
     finally:
         srv.close()
