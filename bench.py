@@ -308,9 +308,9 @@ def serve_bench(args, dev, emit=True):
     `serve_repeats` times each in alternation, and the BF16-eligible requests as
     one burst in each storage (alternating, the same number of times).  For the
     bursts every result's relative error ||A - U S V^T||_F / ||A||_F against the
-    FP32 matrix is measured (torch FP64 on the device), and for `serve_oracle`
-    of them the FP64 oracle runs on the stored values (BF16 values for the BF16
-    form) on the host, so that the two forms are compared at their accuracy."""
+    FP32 matrix is measured (torch FP64 on the device), so that the two forms
+    are compared at their accuracy (served results against the FP64 oracle:
+    tests/test_gpu_serve.py)."""
     import threading
 
     import numpy as np
@@ -420,28 +420,6 @@ def serve_bench(args, dev, emit=True):
             errs[form] = e
         burst["rel_error_vs_fp32_A"] = {form: {"median": float(np.median(e)), "max": float(np.max(e))}
                                         for form, e in errs.items() if e}
-        # the FP64 oracle on the stored values, for the first serve_oracle results
-        if args.serve_oracle > 0:
-            from oracle import FarpcaParams, farpca
-            rows = []
-            for form, (kept, rq, store) in acc.items():
-                for i in sorted(kept)[:args.serve_oracle]:
-                    q = rq[i]
-                    A = (A16 if form == "bf16" else A32)[q["mat"]]
-                    a64 = A.double().cpu().numpy()
-                    ref = farpca(a64, FarpcaParams(tol=q["tol"], power=1, sketch="sparse_sign", zeta=8,
-                                                   seed=q["seed"]))
-                    U, S, V = kept[i]
-                    rec = ((U.double() * S) @ V.double().T).cpu().numpy()
-                    na = np.linalg.norm(a64)
-                    eps_g = float(np.linalg.norm(a64 - rec) / na)
-                    eps_o = float(np.linalg.norm(a64 - (ref.U * ref.S) @ ref.V.T) / na)
-                    rows.append({"form": form, "req": i, "tol": q["tol"], "m": a64.shape[0],
-                                 "n": a64.shape[1], "l": int(U.shape[1]), "l_oracle": int(ref.rank),
-                                 "eps_served": eps_g, "eps_oracle": eps_o, "d_eps": abs(eps_g - eps_o)})
-            burst["vs_oracle"] = rows
-            burst["vs_oracle_max_d_eps"] = {f: max((r["d_eps"] for r in rows if r["form"] == f), default=None)
-                                           for f in ("bf16", "fp32")}
     line = {
         "metric": "served solves/s + p99 vs plain FP32",
         "value": float(np.mean([x["solves_per_s"] for x in mixed])), "unit": "solves/s", "n_gpus": 1,
@@ -467,7 +445,7 @@ def serve_summary(dev, nreq=512, slots=16):
     of the serving half of the metric, for the default JSON line."""
     from types import SimpleNamespace
     args = SimpleNamespace(serve_requests=nreq, serve_slots=slots, serve_pool_gb=80.0,
-                           serve_hw_queues=0, serve_repeats=1, serve_oracle=0)
+                           serve_hw_queues=0, serve_repeats=1)
     line = serve_bench(args, dev, emit=False)
     burst = line["eligible_burst"]
     return {"workload": line["config"]["workload"], "slots": slots,
@@ -560,8 +538,6 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-repeats", type=int, default=3,
                     help="replays of each serving configuration (alternating), for the spread")
-    ap.add_argument("--serve-oracle", type=int, default=0,
-                    help="burst results checked against the FP64 oracle on the host, per storage")
     ap.add_argument("--no-subrecords", action="store_true",
                     help="only the 20000 x 15000 solve line (no precision-form, tall and serving records)")
     ap.add_argument("--serve-pool-gb", type=float, default=80.0)

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfarpca.so")
 ARCH = os.environ.get("FARPCA_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["omega.hip", "sketch.hip", "sketch_cols.hip", "gemm.hip", "gemm_bf16.hip", "dense64.hip", "eig.hip",
+SOURCES = ["omega.hip", "sketch.hip", "sketch_cols.hip", "gemm.hip", "gemm_bf16.hip", "dense64.hip", "cpass64.hip", "eig.hip",
            "farpca.cpp", "serve.cpp"]
 
 COMMON = [

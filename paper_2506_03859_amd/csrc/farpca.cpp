@@ -15,7 +15,8 @@
 //                                   update uses the block's smallest singular
 //                                   value (P > 2)
 //   Y_j = A G (P >= 1) or S (P = 0)
-//   Y_j <- (I - Q Q^T) Y_j (twice), Q_j = orth(Y_j), Q = [Q, Q_j]
+//   Y_j <- (I - Q Q^T) Y_j (twice), one CholeskyQR pass, (I - Q Q^T) once
+//   more, a second pass: Q_j = orth(Y_j), Q = [Q, Q_j]
 //   C_j^T = A^T Q_j, E = E - ||C_j||_F^2   (E = ||A||^2 - tr(T Z^{-1}) of
 //                                   Algorithm 1, since tr(T Z^{-1}) = ||Q^T A||_F^2)
 //   stop when E < tol^2 ||A||_F^2 (Section 5.2), l >= k (Section 5.1) or at the cap.
@@ -39,6 +40,11 @@ using namespace farpca_int;
 
 // squared relative pivot below which a block direction counts as dependent
 static constexpr double kDropRel = 1e-10;
+// Below this tolerance the stop test (E < tol^2 ||A||^2) is within about two
+// orders of magnitude of the error that FP32 accumulation leaves in
+// sum ||C_j||^2 (1e-8 .. 1e-7 of ||A||^2), and C_j^T = A^T Q_j is formed with
+// FP64 products and sums instead.
+static constexpr double kC64Tol = 1e-3;
 static constexpr int kCholqrPasses = 2;
 // a repeated CholeskyQR pass is skipped when the Gram of its input deviates
 // from the identity by at most this much (orthonormal far beyond what the
@@ -56,6 +62,7 @@ struct farpca_plan_s {
   farpca_params prm;
   bool bf16;            // A holds BF16 bit patterns (precision form)
   bool colmajor;        // A stored column-major (FARPCA_LAYOUT_COL)
+  bool c64;             // C_j^T = A^T Q_j with FP64 accumulation (tol below kC64Tol)
   int b;
   int P;
   int kind;
@@ -239,6 +246,7 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   pl->prm = q;
   pl->bf16 = q.a_dtype == FARPCA_DTYPE_BF16;
   pl->colmajor = colmajor;
+  pl->c64 = q.tol > 0.0 && q.tol < kC64Tol;
   pl->b = b;
   pl->P = q.power;
   pl->kind = q.sketch;
@@ -464,23 +472,23 @@ void sketch(const farpca_plan_s *pl, const Ws &w, const void *A, float *S, hipSt
   }
 }
 
-// T <- (I - Q Q^T) T, applied twice (block classical Gram-Schmidt with
-// reorthogonalisation), Q = first l columns of the basis.
-void project_out(const farpca_plan_s *pl, const Ws &w, int64_t l, float *T, hipStream_t st) {
+// T <- (I - Q Q^T) T, applied `passes` times (block classical Gram-Schmidt,
+// twice for reorthogonalisation), Q = first l columns of the basis.
+void project_out(const farpca_plan_s *pl, const Ws &w, int64_t l, float *T, int passes, hipStream_t st) {
   if (l == 0) return;
   const farpca_params &q = pl->prm;
   float *Q = w.at<float>(pl->off_q);
   float *r = w.at<float>(pl->off_r);
   float *part = w.at<float>(pl->off_part);
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0; pass < passes; ++pass) {
     launch_gemm_tn(Q, pl->ldq, T, kBld, r, kBld, l, pl->b, q.m, 1.f, 0.f,
                    gemm_choose_ksplit(l, q.m, 1, pl->part_splits(l)), part, st);
     launch_gemm_nn(Q, pl->ldq, r, kBld, T, kBld, q.m, pl->b, l, -1.f, 1.f, 1, part, st);
   }
 }
 
-// X (K x b) <- orthonormal basis of its range, CholeskyQR with `passes`
-// passes (FP64 Gram and factor, FP32 storage); numerically dependent columns
+// X (K x b) <- orthonormal basis of its range, CholeskyQR passes
+// first_pass .. end_pass - 1 (FP64 Gram and factor, FP32 storage); numerically dependent columns
 // (residual below 1e-5 of the column, i.e. rounding noise of the FP32 data)
 // become exactly zero.  Two passes suffice: the first leaves an orthogonality
 // error of about u64 cond(X)^2, the second brings it to the FP32 rounding of
@@ -489,14 +497,14 @@ void project_out(const farpca_plan_s *pl, const Ws &w, int64_t l, float *T, hipS
 // conditioned X: the first pass reached that level) applies nothing: its
 // factor and solve are skipped on the device.  If gram_eig, the eigenvalues of
 // the first Gram go to w64 (descending).
-void cholqr(const farpca_plan_s *pl, const Ws &w, float *X, int64_t K, int passes, bool gram_eig,
-            hipStream_t st) {
+void cholqr(const farpca_plan_s *pl, const Ws &w, float *X, int64_t K, int first_pass, int end_pass,
+            bool gram_eig, hipStream_t st) {
   double *gpart = w.at<double>(pl->off_gpart);
   double *G = w.at<double>(pl->off_g64);
   double *Rf = w.at<double>(pl->off_rinv);
   int *flags = reinterpret_cast<int *>(w.at<double>(pl->off_scal) + 3);
   int *apply = flags + 1;
-  for (int pass = 0; pass < passes; ++pass) {
+  for (int pass = first_pass; pass < end_pass; ++pass) {
     launch_gram(X, kBld, K, pl->b, gpart, G, st);
     if (pass == 0 && gram_eig)
       launch_eig_small(G, pl->b, kMaxBlock, w.at<double>(pl->off_w64), w.at<double>(pl->off_v64),
@@ -659,7 +667,7 @@ static int enqueue_block(farpca_plan_s *pl, hipStream_t st) {
     HIP_OK(hipMemsetAsync(alpha, 0, 8, st));
     float *T = S;
     for (int k = 1; k <= pl->P; ++k) {
-      project_out(pl, w, l, T, st);
+      project_out(pl, w, l, T, 2, st);
       int nsp;
       {
         ProfScope ps(FARPCA_PROF_GEMM_TN, st);
@@ -667,7 +675,7 @@ static int enqueue_block(farpca_plan_s *pl, hipStream_t st) {
       }
       launch_gemm_finish(part, nsp, n, b, X, kBld, 1.f, 0.f, st);
       if (k >= 2 && pl->P > 2) launch_axpy_block(X, kBld, G, kBld, n, b, alpha, st);
-      cholqr(pl, w, X, n, kCholqrPasses, pl->P > 2, st);
+      cholqr(pl, w, X, n, 0, kCholqrPasses, pl->P > 2, st);
       if (k >= 2 && pl->P > 2) launch_alpha_update(w.at<double>(pl->off_w64), b, alpha, st);
       launch_copy_block(X, kBld, n, b, G, kBld, st);
       if (k < pl->P) {
@@ -689,16 +697,32 @@ static int enqueue_block(farpca_plan_s *pl, hipStream_t st) {
     Ysrc = Yb;
   }
   // Basis extension: Y_j against Q, orthonormalise, append; C_j^T = A^T Q_j.
-  project_out(pl, w, l, Ysrc, st);
-  cholqr(pl, w, Ysrc, m, kCholqrPasses, false, st);
+  // The first CholeskyQR pass multiplies by R^{-1}, which magnifies what the
+  // projections leave of span(Q) (FP32 rounding, about u ||Y_j||) by up to
+  // cond(Y_j): for blocks that fall almost inside span(Q) (sparse test
+  // matrices on a matrix whose right singular vectors are sparse, Section
+  // 5.5) that reaches 1e-3..1e-2, Q loses orthogonality and the indicator
+  // counts directions twice.  One more projection after that pass removes the
+  // magnified part; the second pass restores unit columns.
+  project_out(pl, w, l, Ysrc, 2, st);
+  cholqr(pl, w, Ysrc, m, 0, 1, false, st);
+  project_out(pl, w, l, Ysrc, 1, st);
+  cholqr(pl, w, Ysrc, m, 1, kCholqrPasses, false, st);
   launch_copy_block(Ysrc, kBld, m, b, Q + l, pl->ldq, st);
-  int nsp4;
-  {
-    ProfScope ps(FARPCA_PROF_GEMM_TN, st);
-    nsp4 = a_pass(pl, w, true, A, Ysrc, b, Ct + l, pl->ldq, st);
+  if (pl->c64) {
+    // small tol: the indicator needs ||C_j||^2 below the FP32 accumulation error
+    const int ns64 = cpass64_choose_split(n, m, pl->part_floats / 2 / (n * kBld));
+    launch_cpass64(A, pl->bf16, pl->colmajor, q.lda, Ysrc, kBld, n, m, b, ns64,
+                   reinterpret_cast<double *>(part), Ct + l, pl->ldq, w.at<double>(pl->off_sq), st);
+  } else {
+    int nsp4;
+    {
+      ProfScope ps(FARPCA_PROF_GEMM_TN, st);
+      nsp4 = a_pass(pl, w, true, A, Ysrc, b, Ct + l, pl->ldq, st);
+    }
+    launch_gemm_finish(part, nsp4, n, b, Ct + l, pl->ldq, 1.f, 0.f, st);
+    launch_sqnorm(Ct + l, pl->ldq, n, b, w.at<double>(pl->off_sq), st);
   }
-  launch_gemm_finish(part, nsp4, n, b, Ct + l, pl->ldq, 1.f, 0.f, st);
-  launch_sqnorm(Ct + l, pl->ldq, n, b, w.at<double>(pl->off_sq), st);
   launch_indicator_update(w.at<double>(pl->off_sq), sqnorm_num_partials(n), E, pl->run_ehist, j,
                           st);
   l += b;

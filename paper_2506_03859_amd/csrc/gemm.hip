@@ -139,8 +139,10 @@ __device__ __forceinline__ void load_a_tail(const float *__restrict__ A, int64_t
 
 // Skinny chunk rows [kc, kc + 16 NX) into registers: thread tid holds float4
 // number f = tid + 256 j (chunk row f / 16, columns 4 (f % 16) .. +3).
-// XVEC (N == 64, rows 16-byte aligned) and rows inside K: one 16-byte load;
-// otherwise clamped scalar loads, zero outside K x N.
+// XVEC (rows 16-byte aligned with 64 readable floats: N == 64 or ldx >= 64)
+// and rows inside K: one 16-byte load, columns >= N set to zero (the last
+// row of the range is read that way only when N == 64: a caller's buffer may
+// end at its N-th column); otherwise clamped scalar loads, zero outside K x N.
 // NN with WM = 4 (the A-passes A G): a wave's 64 rows x 32 K of a chunk are
 // read as 8 rows x 128 contiguous bytes per instruction (lane l: row
 // 8 q + l / 8, K 4 (l % 8) .. + 3) - twice the row piece of the MFMA operand
@@ -188,8 +190,15 @@ __device__ __forceinline__ void load_x(const float *__restrict__ X, int64_t ldx,
     const int f = tid + 256 * j;
     const int64_t k = kc + (f >> 4);
     const int col = 4 * (f & 15);
-    if (XVEC && full) {
-      xr[j] = *reinterpret_cast<const float4 *>(X + k * ldx + col);
+    if (XVEC && full && (N == 64 || k + 1 < ke)) {
+      float4 v = *reinterpret_cast<const float4 *>(X + k * ldx + col);
+      if (N < 64) {
+        v.x = col < N ? v.x : 0.0f;
+        v.y = col + 1 < N ? v.y : 0.0f;
+        v.z = col + 2 < N ? v.z : 0.0f;
+        v.w = col + 3 < N ? v.w : 0.0f;
+      }
+      xr[j] = v;
     } else {
       const float *p = X + clampi(k, ke - 1) * ldx;
       float v[4];
@@ -578,7 +587,7 @@ static int launch_main(const float *A, int64_t lda, const float *X, int64_t ldx,
   const int64_t m4 = (M + 3) / 4 * 4;
   const int64_t mload = (M % 4 == 0) ? M : (m4 <= lda ? m4 : 0);
   const bool avec = (lda % 4 == 0) && aligned16(A) && (!TN || mload >= 4);
-  const bool xvec = (ldx % 4 == 0) && aligned16(X) && N == 64;
+  const bool xvec = (ldx % 4 == 0) && aligned16(X) && (N == 64 || ldx >= 64);
   dim3 grid((unsigned)total), blk(256);
 #define FARPCA_GEMM_LAUNCH(WMV, AV, XV)                                                            \
   hipLaunchKernelGGL((gemm_kernel<TN, WMV, AV, XV>), grid, blk, 0, st, A, lda, X, ldx, C, ldc, M, \

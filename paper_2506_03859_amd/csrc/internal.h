@@ -152,6 +152,16 @@ void launch_scale_rowsum(const double *rowsum, int64_t m, double p, float *z, hi
 // ||X||_F^2 of X (K x b, FP32) into partials (one double per block) for the indicator.
 int sqnorm_num_partials(int64_t K);
 void launch_sqnorm(const float *X, int64_t ldx, int64_t K, int b, double *part, hipStream_t st);
+
+// ---- cpass64.hip
+// C (M x b, FP32, ldc) = A^T Q (row-major A: m x n, M = n, K = m; colmajor:
+// A stored as A^T row-major) with FP64 products and sums; part holds
+// nsplit x M x kBld doubles; sq gets sqnorm_num_partials(M) FP64 partials of
+// ||C||_F^2 taken before the rounding to FP32.
+int cpass64_choose_split(int64_t M, int64_t K, int64_t max_split);
+void launch_cpass64(const void *A, bool bf16, bool colmajor, int64_t lda, const float *Q, int64_t ldq,
+                    int64_t M, int64_t K, int b, int nsplit, double *part, float *C, int64_t ldc,
+                    double *sq, hipStream_t st);
 // E_hist[j] = E_prev - sum(part); E_cur updated (single thread).
 void launch_indicator_update(const double *part, int count, double *E, double *E_hist,
                              int64_t j, hipStream_t st);

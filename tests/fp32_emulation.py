@@ -6,7 +6,11 @@ storage precisions, on the host:
 * the power iterate deflated in the m-space, T <- (I - Q Q^T) T applied twice
   with FP32 products (the explicit orthonormal basis Q of span(Y));
 * orth() as CholeskyQR in two passes: FP64 Gram of the FP32 block, FP64
-  Cholesky factor, X R^-1 formed in FP64 and stored in FP32;
+  Cholesky factor (a column whose pivot falls to 1e-10 of its diagonal is
+  dropped: zero), X R^-1 formed in FP64 and stored in FP32; the second pass
+  is left out when the Gram is the identity to 1e-8;
+* the new basis block: two projections, one CholeskyQR pass, one more
+  projection, the second pass;
 * the indicator E = ||A||^2 - sum_j ||C_j||_F^2 with C_j^T = A^T Q_j (FP32) and
   the sums in FP64;
 * the final step as the FP64 eigendecomposition of K = C C^T, U = Q U~ and
@@ -26,21 +30,61 @@ from oracle.omega import bernoulli_mask, default_p, omega_dense
 F32 = np.float32
 
 
-def _project_twice(q, t):
-    for _ in range(2):
+def _project(q, t, passes=2):
+    for _ in range(passes):
         if q.shape[1]:
             r = q.T @ t
             t = t - q @ r
     return t
 
 
+def _project_twice(q, t):
+    return _project(q, t, 2)
+
+
+def _chol_drop(g, drop_rel=1e-10):
+    """Upper factor R (g = R^T R on the kept columns); a column whose pivot is
+    at most drop_rel times its diagonal is dropped (its row of R stays zero)."""
+    b = g.shape[0]
+    w = g.copy()
+    r = np.zeros_like(g)
+    keep = np.zeros(b, bool)
+    for k in range(b):
+        piv = w[k, k]
+        if g[k, k] == 0.0 or piv <= drop_rel * g[k, k]:
+            continue
+        keep[k] = True
+        rk = w[k, k:] / np.sqrt(piv)
+        r[k, k:] = rk
+        w[k + 1:, k + 1:] -= np.outer(rk[1:], rk[1:])
+    return r, keep
+
+
+def _cholqr_pass(x, repeat):
+    x64 = x.astype(np.float64)
+    g = x64.T @ x64
+    if repeat:
+        kept = np.diag(g) != 0.0
+        dev = np.abs(g - np.eye(len(g)))[np.ix_(kept, kept)]
+        if dev.size == 0 or dev.max() <= 1e-8:
+            return x
+    r, keep = _chol_drop(g)
+    rinv = np.zeros_like(r)
+    idx = np.where(keep)[0]
+    if len(idx):
+        rinv[np.ix_(idx, idx)] = np.linalg.inv(r[np.ix_(idx, idx)])
+    return (x64 @ rinv).astype(F32)
+
+
 def _cholqr2(x):
-    for _ in range(2):
-        x64 = x.astype(np.float64)
-        g = x64.T @ x64
-        r = np.linalg.cholesky(g).T                  # upper factor, g = r^T r
-        x = (x64 @ np.linalg.inv(r)).astype(F32)
-    return x
+    return _cholqr_pass(_cholqr_pass(x, False), True)
+
+
+def _orth_block(q, y):
+    y = _project(q, y, 2)
+    y = _cholqr_pass(y, False)
+    y = _project(q, y, 1)
+    return _cholqr_pass(y, True)
 
 
 def farpca_fp32(a32, tol=0.0, rank=0, block=0, power=1, sketch="sparse_sign", p=0.0, zeta=0,
@@ -78,8 +122,7 @@ def farpca_fp32(a32, tol=0.0, rank=0, block=0, power=1, sketch="sparse_sign", p=
                 if k < power:
                     t = a32 @ g
             y = a32 @ g
-        y = _project_twice(q, y)
-        qj = _cholqr2(y)
+        qj = _orth_block(q, y)
         cj = a32.T @ qj
         q = np.hstack([q, qj])
         ct = np.hstack([ct, cj])

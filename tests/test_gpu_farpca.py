@@ -642,3 +642,53 @@ def test_stability_blockdiag_v(fp, d, sketch):
               f"err/thr={err / thr:.3f}", flush=True)
         # met up to the FP32 accuracy of the indicator the stop test used
         assert err < thr + 5e-7 * ref.norm_a2
+
+
+@pytest.mark.parametrize("d", [1, 100, 1000])
+@pytest.mark.parametrize("sketch", ["std_bernoulli", "sparse_sign", "sparse_gaussian", "bernoulli"])
+def test_small_tol_indicator(fp, d, sketch):
+    # Section 5.5 inputs at its threshold eps = 1e-4 (tol^2 = 1e-8 of ||A||^2,
+    # below what FP32 sums of ||C_j||^2 resolve): the library forms C_j^T =
+    # A^T Q_j with FP64 products and sums for the indicator.  What is left is
+    # the FP32 storage of the basis: a deviation of Q^T Q from I of ~1e-7
+    # moves ||Q^T A||^2 against ||Q Q^T A||^2 by up to that much of the
+    # dominant sigma_1^2, measured at up to 7e-9 ||A||^2 here (Matrix 1:
+    # ||A||^2 is 92 % sigma_1^2).  Checked on the GPU result: the indicator is
+    # the true residual of the basis to 1e-8 ||A||^2, the basis stays
+    # orthonormal (the block after a nearly dependent one is projected
+    # again), and a run that stops meets the tolerance to that accuracy
+    # (err^2 < tol^2 ||A||^2 + 1e-8 ||A||^2).  Well-conditioned inputs (d = 1)
+    # are compared with the oracle run to the GPU's rank (with E this close to
+    # its resolution the two runs may stop blocks apart).
+    import torch
+    n, tol, b = 1000, 1e-4, 20
+    a32 = synth.spectral_blockdiag_v(n, synth.matrix1_sigma(n), d, seed=7).astype(np.float32)
+    a = a32.astype(np.float64)
+    nA2 = float(np.sum(a * a))
+    thr = tol * tol * nA2
+    for seed in (1, 2):
+        kw = dict(tol=tol, block=b, power=1, sketch=sketch, p=math.log(n) / n, seed=seed)
+        print(f"farpca_run m={n} n={n} d={d} {kw}", flush=True)
+        res = fp.solve(torch.from_numpy(a32).cuda(), **kw)
+        torch.cuda.synchronize()
+        if d == 1:
+            okw = {k: v for k, v in kw.items() if k != "tol"}
+            okw["rank"] = int(res.info.rank_l)
+            ref = farpca(a, FarpcaParams(**okw), keep_bases=True)
+            ref.okw = okw
+            compare(res, ref, a32)
+        U = res.U.cpu().double().numpy()
+        S = res.S.cpu().numpy()
+        V = res.V.cpu().double().numpy()
+        kg = int(np.sum(S > 0))
+        U, S, V = U[:, :kg], S[:kg], V[:, :kg]
+        orth = np.abs(U.T @ U - np.eye(kg)).max()
+        true_e = np.linalg.norm(a - U @ (U.T @ a)) ** 2
+        err = np.linalg.norm(a - (U * S) @ V.T) ** 2
+        print(f"  status={res.status} l={res.info.rank_l} kept={kg} |UtU-I|={orth:.1e} "
+              f"E/|A|^2={res.info.err_indicator / nA2:.3e} true/|A|^2={true_e / nA2:.3e} "
+              f"err/thr={err / thr:.3f}", flush=True)
+        assert orth < 1e-5
+        assert abs(res.info.err_indicator - true_e) <= 1e-8 * nA2 + 1e-3 * true_e
+        if res.status == 0:
+            assert err < thr + 1e-8 * nA2

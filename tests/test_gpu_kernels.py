@@ -212,6 +212,29 @@ def test_gemm_integer_exact(fp, M, K, N, kind):
     assert np.array_equal(host(C), ref.astype(np.float32))
 
 
+@pytest.mark.parametrize("M,K,N", [(4000, 20000, 50), (1000, 777, 50), (9001, 3001, 33), (8200, 40, 1)])
+@pytest.mark.parametrize("kind", ["nn", "tn"])
+def test_gemm_skinny_in_wide_buffer(fp, M, K, N, kind):
+    # the library's own skinny operands are N < 64 columns of K x 64 buffers:
+    # rows are read 64 wide and the columns >= N (here NaN) must not reach C
+    import torch
+    rng = np.random.default_rng(M + 3 * K + N)
+    a = rng.integers(-4, 5, size=(M, K) if kind == "nn" else (K, M)).astype(np.float32)
+    x = rng.integers(-4, 5, size=(K, N)).astype(np.float32)
+    xb = torch.full((K, 64), float("nan"), dtype=torch.float32, device="cuda")
+    xb[:, :N] = dev(x)
+    C = torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")
+    part = torch.empty(fp.farpca_gemm_scratch_bytes(M) // 4 + 1, dtype=torch.float32, device="cuda")
+    print(f"gemm {kind} M={M} K={K} N={N} ldx=64", flush=True)
+    if kind == "nn":
+        fp.farpca_gemm_nn(dev(a), xb, C, M, N, K, part, ldx=64)
+        ref = a.astype(np.float64) @ x.astype(np.float64)
+    else:
+        fp.farpca_gemm_tn(dev(a), xb, C, M, N, K, part, ldy=64)
+        ref = a.astype(np.float64).T @ x.astype(np.float64)
+    assert np.array_equal(host(C), ref.astype(np.float32))
+
+
 @pytest.mark.parametrize("M,K,N", [(2000, 15000, 64), (15000, 2000, 64), (333, 4000, 50), (4000, 100000, 50)])
 @pytest.mark.parametrize("kind", ["nn", "tn"])
 def test_gemm_float_error_bound(fp, M, K, N, kind):

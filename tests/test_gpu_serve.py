@@ -201,6 +201,52 @@ def test_served_result_matches_oracle(fp):
     assert np.abs(U.T @ U - np.eye(U.shape[1])).max() < 1e-5
 
 
+def test_served_mix_against_oracle(fp):
+    # every request of the mix, each in its storage (BF16 ones in BF16),
+    # served together and compared with the FP64 oracle on the values it
+    # holds; a stop on the other side of a tie (oracle E within 1 % of the
+    # threshold) is compared with the oracle run to the served rank
+    import torch
+    from oracle import FarpcaParams, farpca, projection_svd
+    reqs = requests_mix()
+    mats = [device_matrix(a, st) for _, a, _, st in reqs]
+    prms = [fp.make_params(a.shape[0], a.shape[1], a_dtype=st, **kw) for _, a, kw, st in reqs]
+    srv = fp.Server(2 * sum(fp.farpca_request_footprint(p) for p in prms), slots=4)
+    try:
+        for i in range(len(reqs)):
+            srv.submit(prms[i], mats[i], i)
+        got = drain(fp, srv, len(reqs))
+    finally:
+        srv.close()
+    for i, (name, a32, kw, st) in enumerate(reqs):
+        r, (U, S, V) = got[i]
+        a = mats[i].float().cpu().double().numpy()          # the stored values
+        print(f"serve vs oracle: {name} {st} {kw}", flush=True)
+        ref = farpca(a, FarpcaParams(**kw), keep_bases=True)
+        assert r.status == ref.status == 0
+        if r.info.rank_l != ref.rank:
+            thr = kw["tol"] ** 2 * ref.norm_a2
+            e = ref.e_history[min(r.info.blocks, ref.blocks) - 1]
+            assert abs(e - thr) <= 0.01 * thr, (name, r.info.rank_l, ref.rank)
+            okw = {k: v for k, v in kw.items() if k != "tol"}
+            okw["rank"] = int(r.info.rank_l)
+            ref = farpca(a, FarpcaParams(**okw), keep_bases=True)
+        U, S, V = U.cpu().double().numpy(), S.cpu().numpy(), V.cpu().double().numpy()
+        kg = int(np.sum(S > 0))
+        U, S, V = U[:, :kg], S[:kg], V[:, :kg]
+        na = np.linalg.norm(a)
+        eps_g = np.linalg.norm(a - (U * S) @ V.T) / na
+        eps_o = np.linalg.norm(a - (ref.U * ref.S) @ ref.V.T) / na
+        s_def = projection_svd(a, ref.Y)
+        true_e = np.linalg.norm(a - U @ (U.T @ a)) ** 2
+        ds = np.max(np.abs(S - s_def[:kg])) / s_def[0]
+        print(f"  l={r.info.rank_l} eps served={eps_g:.6e} oracle={eps_o:.6e} sigma diff={ds:.2e}", flush=True)
+        assert abs(eps_g - eps_o) <= 1e-6
+        assert ds <= 1e-6
+        assert abs(r.info.err_indicator - true_e) <= 1e-7 * ref.norm_a2 + 1e-3 * true_e
+        assert np.abs(U.T @ U - np.eye(kg)).max() < 1e-5
+
+
 def test_submit_errors(fp):
     import torch
     a = torch.zeros((300, 200), dtype=torch.float32, device="cuda")
