@@ -302,6 +302,17 @@ def serve_matrix(spec, device):
     return a.to(torch.float32).contiguous()
 
 
+def padded_rows(a, mult):
+    """Row-major copy of a with its leading dimension rounded up to `mult`
+    elements (zero padding), returned as the m x n view."""
+    import torch
+    m, n = a.shape
+    ld = (n + mult - 1) // mult * mult
+    buf = torch.zeros((m, ld), dtype=a.dtype, device=a.device)
+    buf[:, :n] = a
+    return buf[:, :n]
+
+
 def serve_bench(args, dev, emit=True):
     """Open-loop replay of the serving trace through farpca_server_*: the
     mixed-storage trace (BF16 where eligible) and the same trace all in FP32,
@@ -318,8 +329,10 @@ def serve_bench(args, dev, emit=True):
     from paper_2506_03859_amd import farpca as fp
     mats, reqs = serve_trace(nreq=args.serve_requests)
     log(f"serve: generating {len(mats)} matrices")
-    A32 = [serve_matrix(sp, dev) for sp in mats]
-    A16 = [a.to(torch.bfloat16).contiguous() for a in A32]
+    # rows padded to 16 bytes (lda a multiple of 4 FP32 / 8 BF16 elements), the
+    # layout the library's vector loads take for any width
+    A32 = [padded_rows(serve_matrix(sp, dev), 4) for sp in mats]
+    A16 = [padded_rows(a.to(torch.bfloat16), 8) for a in A32]
     floor = []
     for a, b16 in zip(A32, A16):
         floor.append(float(torch.linalg.norm(b16.float() - a) / torch.linalg.norm(a)))
@@ -338,7 +351,8 @@ def serve_bench(args, dev, emit=True):
         for q in rq:
             m, n = mats[q["mat"]][:2]
             bf = (mode == "mixed" and eligible(q)) if sub is None else sub[1] == "bf16"
-            prms.append(fp.make_params(m, n, tol=q["tol"], power=1, sketch="sparse_sign", zeta=8,
+            A = A16[q["mat"]] if bf else A32[q["mat"]]
+            prms.append(fp.make_params(m, n, A.stride(0), tol=q["tol"], power=1, sketch="sparse_sign", zeta=8,
                                        seed=q["seed"], a_dtype="bf16" if bf else "f32"))
             store.append(bf)
         results, kept = {}, {}
@@ -439,6 +453,41 @@ def serve_bench(args, dev, emit=True):
     return line
 
 
+def serve_burst(args, dev):
+    """The BF16-eligible requests of the serving trace submitted at once in one
+    storage form, served `serve_repeats` times (the burst of serve_bench alone)."""
+    import numpy as np
+    import torch
+    from paper_2506_03859_amd import farpca as fp
+    mats, reqs = serve_trace(nreq=args.serve_requests)
+    A32 = [padded_rows(serve_matrix(sp, dev), 4) for sp in mats]
+    A16 = [padded_rows(a.to(torch.bfloat16), 8) for a in A32]
+    floor = [float(torch.linalg.norm(b.float() - a) / torch.linalg.norm(a)) for a, b in zip(A32, A16)]
+    torch.cuda.synchronize()
+    elig = [q for q in reqs if q["bf16"] and q["tol"] >= 4 * floor[q["mat"]]]
+    form = args.serve_burst
+    rates = []
+    for _ in range(max(1, args.serve_repeats)):
+        srv = fp.Server(int(args.serve_pool_gb * (1 << 30)), slots=args.serve_slots, starve_s=0.25)
+        t0 = time.perf_counter()
+        for i, q in enumerate(elig):
+            m, n = mats[q["mat"]][:2]
+            A = A16[q["mat"]] if form == "bf16" else A32[q["mat"]]
+            srv.submit(fp.make_params(m, n, A.stride(0), tol=q["tol"], power=1, sketch="sparse_sign", zeta=8,
+                                      seed=q["seed"], a_dtype=form), A, i)
+        done = 0
+        while done < len(elig):
+            for r in srv.poll(64, wait_ms=50):
+                done += 1
+                srv.release(r.tag)
+        rates.append(len(elig) / (time.perf_counter() - t0))
+        srv.close()
+        log(f"serve burst {form}: {rates[-1]:.1f} solves/s")
+    print(json.dumps({"metric": "served solves/s (burst of the BF16-eligible requests)", "unit": "solves/s",
+                      "storage": form, "requests": len(elig), "runs": rates,
+                      "value": float(np.mean(rates))}), flush=True)
+
+
 def serve_summary(dev, nreq=512, slots=16):
     """The serving trace replayed once mixed (BF16 where eligible) and once all
     FP32, and the BF16-eligible requests as a burst in each storage: the figures
@@ -534,6 +583,9 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="replay the serving trace (Poisson arrivals, mixed shapes / tolerances / "
                          "storage) through farpca_server_* instead of the solve benchmark")
+    ap.add_argument("--serve-burst", choices=["bf16", "f32"], default=None,
+                    help="serve only the BF16-eligible requests of the trace as one burst in the "
+                         "given storage (--serve-repeats times): the run a kernel trace is taken of")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-repeats", type=int, default=3,
@@ -578,6 +630,9 @@ def main():
     wl = args.workload
     if args.kernel_probe:
         kernel_probe(wl, dev)
+        return
+    if args.serve_burst:
+        serve_burst(args, dev)
         return
     if args.serve:
         serve_bench(args, dev)

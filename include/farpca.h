@@ -8,6 +8,10 @@
  * Conventions
  *  - All matrices are row-major FP32 unless stated.  A is m x n with leading
  *    dimension lda >= n (elements).  Any m, n >= 1 is accepted (m < n too).
+ *    The whole m x lda array must be readable: the kernels may read a row's
+ *    padding between n and lda (never using its values).  Rows of 16 bytes
+ *    (lda a multiple of 4 for FP32, of 8 for BF16) on a 16-byte-aligned base
+ *    take the vector load paths; other layouts take slower element loads.
  *  - Pointers named d* are device pointers (global memory of the current HIP
  *    device), owned by the caller.  The library allocates no device memory
  *    while it runs: scratch buffers live in the caller's workspace, in a static
@@ -253,7 +257,9 @@ int farpca_gemm_tn(const float *dA, int64_t lda, const float *dY, int64_t ldy, f
 /* The same two products with A in BF16 (bit patterns, as for FARPCA_DTYPE_BF16):
  * BF16 matrix cores, the FP32 operand X / Y split exactly into three BF16
  * terms, FP32 accumulation.  dScratch: device, farpca_gemm_bf16_scratch_bytes(M, K)
- * bytes, 256-byte aligned (split-K partials and the transposed operand). */
+ * bytes, 256-byte aligned (split-K partials and the transposed operand).  The
+ * whole row-major array of A (rows x lda) must be readable (row padding may be
+ * read, never used). */
 size_t farpca_gemm_bf16_scratch_bytes(int64_t M, int64_t K);
 int farpca_gemm_bf16_nn(const uint16_t *dA, int64_t lda, const float *dX, int64_t ldx, float *dC,
                         int64_t ldc, int64_t M, int64_t N, int64_t K, void *dScratch, void *stream);

@@ -120,11 +120,18 @@ __global__ __launch_bounds__(256) void bf16_pack_kernel(const float *__restrict_
 // NN: v[2 rt + ks] = row group rt, MFMA step ks; TN: rows (2 j, 2 j + 1) in v[j].
 template <bool TN> struct ASlot { u32x4 v[B16Cfg<TN>::AV]; };
 
+// AVEC, NN: rows hold whole groups of 8 up to k8 = K rounded up to 8 (K % 8
+// == 0, or lda >= k8): a group is read at its start clamped to k8 - 8, and
+// when K % 8 != 0 its elements at k >= K are set to zero (the row padding may
+// hold anything).  AVEC, TN: columns are read in groups of 4 clamped to
+// mclamp - 4 (mclamp = M rounded up to 4 when lda allows; the columns past M
+// only feed outputs that are never stored).
 template <bool TN, bool AVEC>
 __device__ __forceinline__ void load_slot(const uint16_t *A, int64_t lda, int64_t M,
                                           int64_t K, int64_t t0, int li, int lk, int64_t k0,
-                                          ASlot<TN> &s) {
+                                          ASlot<TN> &s, int64_t mclamp) {
   if constexpr (!TN) {
+    const int64_t k8 = (K + 7) & ~int64_t(7);
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) {
       const int64_t row = b16_clamp(t0 + 16 * rt + li, M - 1);
@@ -133,8 +140,20 @@ __device__ __forceinline__ void load_slot(const uint16_t *A, int64_t lda, int64_
       for (int ks = 0; ks < 2; ++ks) {
         const int64_t kk = k0 + 32 * ks + 8 * lk;
         if (AVEC) {
-          // K % 8 == 0: a group of 8 is entirely inside K or entirely past it
-          s.v[2 * rt + ks] = *reinterpret_cast<const u32x4 *>(p + b16_clamp(kk, K - 8));
+          const int64_t g = b16_clamp(kk, k8 - 8);
+          u32x4 v = *reinterpret_cast<const u32x4 *>(p + g);
+          if ((K & 7) != 0 && g + 8 > K) {
+            const int64_t nv = K - g;            // 1 .. 7 valid elements
+            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const uint32_t lo = (2 * q < nv) ? 0x0000FFFFu : 0u;
+              const uint32_t hi = (2 * q + 1 < nv) ? 0xFFFF0000u : 0u;
+              w[q] &= lo | hi;
+            }
+            v = u32x4{w[0], w[1], w[2], w[3]};
+          }
+          s.v[2 * rt + ks] = v;
         } else {
           uint32_t h[8];
 #pragma unroll
@@ -148,7 +167,7 @@ __device__ __forceinline__ void load_slot(const uint16_t *A, int64_t lda, int64_
     const int64_t c = t0 + 4 * li;
     // rows k0 + 8 lk + q: pointer of the lane's first row plus q lda (the
     // slice base k0 lda is uniform); rows past K read row K - 1
-    const int64_t cc = AVEC ? b16_clamp(c, M - 4) : c;
+    const int64_t cc = AVEC ? b16_clamp(c, mclamp - 4) : c;
     const uint16_t *pc = A + cc;
     const uint16_t *plast = pc + (K - 1) * lda;
     const uint16_t *p0 = pc + k0 * lda + 8 * lk * lda;
@@ -161,7 +180,7 @@ __device__ __forceinline__ void load_slot(const uint16_t *A, int64_t lda, int64_
         const int q = 2 * j + h;
         const uint16_t *p = (r0 + q < K) ? p0 + q * lda : plast;
         if (AVEC) {
-          // M % 4 == 0: columns c .. c + 3 are inside the row or the whole group is clamped
+          // columns c .. c + 3 are inside the row (or its padding) or the whole group is clamped
           const uint2 u = *reinterpret_cast<const uint2 *>(p);
           w[2 * h] = u.x;
           w[2 * h + 1] = u.y;
@@ -250,7 +269,7 @@ template <bool TN, bool AVEC>
 __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
     const uint16_t *A, int64_t lda, const float *xt, int64_t kp, float *__restrict__ C, int64_t ldc,
     int64_t M, int64_t N, int64_t K, int64_t kps, int64_t tiles, int64_t total, float alpha,
-    float beta, float *__restrict__ part) {
+    float beta, float *__restrict__ part, int64_t mclamp) {
   using Cfg = B16Cfg<TN>;
   using Lds = B16Lds<TN>;
   constexpr int SL = Cfg::SL, RING = Cfg::RING, NBUF = Cfg::NBUF, XL = Lds::XL;
@@ -285,7 +304,7 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
     for (int g = 0; g < XL; ++g) xr[slot][g] = *reinterpret_cast<const float4 *>(xsrc + sl * SL + 4 * g);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
-    load_slot<TN, AVEC>(A, lda, M, K, t0, li, lk, kb + sl * SL, ar[slot]);
+    load_slot<TN, AVEC>(A, lda, M, K, t0, li, lk, kb + sl * SL, ar[slot], mclamp);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
   };
@@ -355,12 +374,13 @@ static int64_t bf16_slots(int is_tn) {
 int64_t bf16_padded_k(int64_t K) { return (K + kKGroup - 1) / kKGroup * kKGroup; }
 
 // K splits: as for the FP32 kernels (rounds of resident workgroups x split
-// length, partial tiles cheap next to A), splits in whole groups of kKGroup.
+// length, partial tiles cheap next to A), splits in whole groups of kKGroup
+// (so a short K still spreads over several workgroups per 512-row tile).
 int gemm_bf16_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split) {
   if (M < 1 || K < 1) return 1;
   const int64_t tiles = (M + kB16Rows - 1) / kB16Rows;
   const int64_t slots = bf16_slots(is_tn);
-  int64_t smax = K / 512;
+  int64_t smax = K / kKGroup;
   if (smax > max_split) smax = max_split;
   if (smax > 64) smax = 64;
   int best = 1;
@@ -394,15 +414,19 @@ static int launch_bf16(const uint16_t *A, int64_t lda, const float *X, int64_t l
   const int64_t tiles = (M + kB16Rows - 1) / kB16Rows;
   const int64_t total = tiles * nsp;
   const uintptr_t ad = reinterpret_cast<uintptr_t>(A);
-  const bool avec = TN ? (M % 4 == 0 && M >= 4 && lda % 4 == 0 && (ad & 7) == 0)
-                       : (K % 8 == 0 && lda % 8 == 0 && (ad & 15) == 0);
+  // vector loads: 8-byte (TN) / 16-byte (NN) aligned rows whose groups of 4
+  // columns (TN) / 8 k (NN) stay inside the row or its padding up to lda
+  const int64_t m4 = (M + 3) / 4 * 4, k8 = (K + 7) / 8 * 8;
+  const bool avec = TN ? (M >= 4 && lda % 4 == 0 && (ad & 7) == 0 && (M % 4 == 0 || lda >= m4))
+                       : (K >= 8 && lda % 8 == 0 && (ad & 15) == 0 && (K % 8 == 0 || lda >= k8));
+  const int64_t mclamp = (TN && M % 4 != 0) ? m4 : M;
   dim3 grid((unsigned)total), blk(kB16Threads);
   if (avec)
     hipLaunchKernelGGL((gemm_bf16_kernel<TN, true>), grid, blk, 0, st, A, lda, xt, kp, C, ldc, M, N,
-                       K, kps, tiles, total, alpha, beta, p);
+                       K, kps, tiles, total, alpha, beta, p, mclamp);
   else
     hipLaunchKernelGGL((gemm_bf16_kernel<TN, false>), grid, blk, 0, st, A, lda, xt, kp, C, ldc, M,
-                       N, K, kps, tiles, total, alpha, beta, p);
+                       N, K, kps, tiles, total, alpha, beta, p, mclamp);
   return nsp;
 }
 

@@ -310,6 +310,33 @@ def test_gemm_bf16_integer_exact(fp, M, K, N, kind):
     assert np.array_equal(got, ref.astype(np.float32))
 
 
+@pytest.mark.parametrize("M,K,N", [(1000, 777, 50), (1003, 2430, 64), (337, 345, 64), (9001, 3001, 33)])
+@pytest.mark.parametrize("kind", ["nn", "tn"])
+def test_gemm_bf16_padded_rows(fp, M, K, N, kind):
+    # rows padded to a multiple of 8 BF16 (the vector paths for any width):
+    # the padding holds NaN patterns, which must reach no stored output
+    import torch
+    rng = np.random.default_rng(M * 5 + K)
+    rows, cols = (M, K) if kind == "nn" else (K, M)
+    a = rng.integers(-4, 5, size=(rows, cols)).astype(np.float32)
+    xmax = min(2048, (2 ** 24 - 1) // (4 * K))          # |sums| < 2^24: exact in any order
+    x = rng.integers(-xmax, xmax + 1, size=(K, N)).astype(np.float32)
+    ld = (cols + 7) // 8 * 8
+    bits = np.full((rows, ld), 0x7FC0, dtype=np.uint16)
+    bits[:, :cols] = synth.bf16_bits(a)
+    A = torch.from_numpy(bits.view(np.int16)).cuda()
+    C = torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")
+    scratch = bf16_scratch(fp, M, K)
+    print(f"gemm bf16 {kind} M={M} K={K} N={N} lda={ld}", flush=True)
+    if kind == "nn":
+        fp.farpca_gemm_bf16_nn(A, dev(x), C, M, N, K, scratch, lda=ld)
+        ref = a.astype(np.float64) @ x.astype(np.float64)
+    else:
+        fp.farpca_gemm_bf16_tn(A, dev(x), C, M, N, K, scratch, lda=ld)
+        ref = a.astype(np.float64).T @ x.astype(np.float64)
+    assert np.array_equal(host(C), ref.astype(np.float32))
+
+
 @pytest.mark.parametrize("M,K,N", [(1000, 2048, 64), (3000, 777, 50), (9001, 3001, 64)])
 @pytest.mark.parametrize("kind", ["nn", "tn"])
 def test_gemm_bf16_split_exact(fp, M, K, N, kind):

@@ -223,7 +223,8 @@ def test_served_mix_against_oracle(fp):
         a = mats[i].float().cpu().double().numpy()          # the stored values
         print(f"serve vs oracle: {name} {st} {kw}", flush=True)
         ref = farpca(a, FarpcaParams(**kw), keep_bases=True)
-        assert r.status == ref.status == 0
+        # a BF16 request whose tol sits at its storage floor runs to the cap in both
+        assert r.status == ref.status
         if r.info.rank_l != ref.rank:
             thr = kw["tol"] ** 2 * ref.norm_a2
             e = ref.e_history[min(r.info.blocks, ref.blocks) - 1]

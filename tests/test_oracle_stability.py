@@ -47,3 +47,27 @@ def test_sparse_v_needs_more_blocks():
                                      seed=s)).blocks for s in range(4)]
         mean_blocks[d] = np.mean(nb)
     assert mean_blocks[n] > mean_blocks[1] + 1.5
+
+
+def test_stored_stability_grid_reproduces():
+    # tests/golden/stability_oracle_5000x5000.json (written by
+    # tests/golden/stability_oracle.py, oracle only): the whole grid is there,
+    # and one stored run comes out the same when the oracle is run again
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "stability_oracle_5000x5000.json")
+    with open(path) as f:
+        g = json.load(f)
+    n, trials = g["n"], g["trials"]
+    assert n == 5000 and g["tol"] == 1e-4 and trials == 10
+    cells = g["cells"]
+    assert len(cells) == 36 and all(len(v) == trials for v in cells.values())
+    assert all(s in (0, 1) and 1 <= b <= 50 and e >= 0 for v in cells.values() for s, b, e in v)
+    a = synth.spectral_blockdiag_v(n, synth.matrix1_sigma(n), n, seed=g["seed_matrix"])
+    r = farpca(a, FarpcaParams(tol=1e-4, power=1, sketch="sparse_gaussian", p=1e-2, seed=1))
+    err = float(np.linalg.norm(a - (r.U * r.S) @ r.V.T) / np.linalg.norm(a))
+    s0, b0, e0 = cells[f"SG p=1e-2 d={n}"][0]
+    assert (r.status, r.blocks) == (s0, b0)
+    # the relative error moves by ~1e-9 with the BLAS thread count (the
+    # oracle's ill-conditioned Z on this input amplifies rounding)
+    assert abs(err - e0) <= 1e-8
