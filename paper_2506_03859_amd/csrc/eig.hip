@@ -64,6 +64,14 @@ __device__ __forceinline__ int rr_player(int pos, int step, int n) {
   return pos == 0 ? 0 : ((pos - 1 + step) % (n - 1)) + 1;
 }
 
+// The player after x in the next step of the tournament (x in 0 .. S - 1):
+// 0 stays, S - 1 wraps to 1, the others add one.
+template <int S>
+__device__ __forceinline__ int rr_next(int x) {
+  const int y = x + 1;
+  return (y - (y / S) * (S - 1)) * min(x, 1);
+}
+
 // Rotation that (nearly) zeroes a_pq: t = tan(angle) from the hardware
 // reciprocal and square root (a few ulps off the exact angle, which only
 // leaves a tiny a_pq for the next sweep), then c = 1 / sqrt(1 + t^2) to full
@@ -97,7 +105,10 @@ __device__ __forceinline__ void jacobi_rotation(double app, double aqq, double a
 // rotation are bitwise equal), which leaves one barrier per step.  Thread t
 // owns the 2 x 2 blocks (pairs ia, ib) with ib = t mod S/2 and the rows of v
 // congruent to t div S/2; an identity rotation is applied like any other
-// (c = 1, s = 0 copy exactly).  Returns the buffer holding the result.
+// (c = 1, s = 0 copy exactly).  A step issues all of its LDS reads first and
+// computes its rotations without branches, so that it costs one LDS round
+// trip and one rotation's latency (the pairs' players advance by one
+// tournament step in registers).  Returns the buffer holding the result.
 // *converged (if given, thread 0's copy is enough) tells whether a sweep ended
 // without a rotation before max_sweeps ran out.
 template <int S, int LD, int NT>
@@ -113,35 +124,64 @@ __device__ double *jacobi_lds(double *a, double *a2, double *v, double floor_abs
   const int ib = tid % H, i0 = tid / H;
   if (tid == 0) { rot_flag[0] = 0; rot_flag[1] = 0; }
   __syncthreads();
+  // players of the thread's pairs (slot 0: pair ib; slots 1..: the pairs ia
+  // of its blocks), advanced by one tournament step at a time
+  int pr[BPT + 1], qr[BPT + 1];
+#pragma unroll
+  for (int k = 0; k <= BPT; ++k) {
+    const int idx = k == 0 ? ib : i0 + (k - 1) * TR;
+    pr[k] = rr_player(idx, 0, S);
+    qr[k] = rr_player(S - 1 - idx, 0, S);
+  }
   double *cur = a, *nxt = a2;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int step = 0; step < S - 1; ++step) {
       // the flag of the next sweep was last read before this sweep's first barrier
       if (step == 1 && tid == 0) rot_flag[(sweep + 1) & 1] = 0;
-      // rotations: slot 0 is pair ib, slots 1.. the pairs ia of this thread's blocks
+      const int pb = pr[0], qb = qr[0];
+      // every LDS read of the step first (one round trip): the three entries
+      // of each rotation, the thread's 2 x 2 blocks and its rows of v
+      double app[BPT + 1], aqq[BPT + 1], apq[BPT + 1];
+#pragma unroll
+      for (int k = 0; k <= BPT; ++k) {
+        app[k] = cur[pr[k] * LD + pr[k]];
+        aqq[k] = cur[qr[k] * LD + qr[k]];
+        apq[k] = cur[pr[k] * LD + qr[k]];
+      }
+      double x[BPT][4];
+#pragma unroll
+      for (int k = 1; k <= BPT; ++k) {
+        x[k - 1][0] = cur[pr[k] * LD + pb];
+        x[k - 1][1] = cur[pr[k] * LD + qb];
+        x[k - 1][2] = cur[qr[k] * LD + pb];
+        x[k - 1][3] = cur[qr[k] * LD + qb];
+      }
+      double vp[RPT], vq[RPT];
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int r = i0 + k * TR;
+        vp[k] = v[r * LD + pb];
+        vq[k] = v[r * LD + qb];
+      }
+      // the rotations, without branches (a negligible pair takes c = 1,
+      // s = 0; the values computed for it are discarded)
       double cr[BPT + 1], sr[BPT + 1];
-      int pr[BPT + 1], qr[BPT + 1];
       bool rotated = false;
 #pragma unroll
       for (int k = 0; k <= BPT; ++k) {
-        const int idx = k == 0 ? ib : i0 + (k - 1) * TR;
-        const int p = rr_player(idx, step, S), q = rr_player(S - 1 - idx, step, S);
-        const double app = cur[p * LD + p], aqq = cur[q * LD + q], apq = cur[p * LD + q];
-        double c = 1.0, s = 0.0;
-        if (!negligible(apq, app, aqq, floor_abs, rel)) {
-          jacobi_rotation(app, aqq, apq, c, s);
-          rotated = true;
-        }
-        cr[k] = c; sr[k] = s; pr[k] = p; qr[k] = q;
+        double c, s;
+        jacobi_rotation(app[k], aqq[k], apq[k], c, s);
+        const bool neg = negligible(apq[k], app[k], aqq[k], floor_abs, rel);
+        cr[k] = neg ? 1.0 : c;
+        sr[k] = neg ? 0.0 : s;
+        rotated |= !neg;
       }
       const double cb = cr[0], sb = sr[0];
-      const int pb = pr[0], qb = qr[0];
 #pragma unroll
       for (int k = 1; k <= BPT; ++k) {
         const double ca = cr[k], sa = sr[k];
         const int pa = pr[k], qa = qr[k];
-        const double x11 = cur[pa * LD + pb], x12 = cur[pa * LD + qb];
-        const double x21 = cur[qa * LD + pb], x22 = cur[qa * LD + qb];
+        const double x11 = x[k - 1][0], x12 = x[k - 1][1], x21 = x[k - 1][2], x22 = x[k - 1][3];
         const double y11 = ca * x11 - sa * x21, y12 = ca * x12 - sa * x22;
         const double y21 = sa * x11 + ca * x21, y22 = sa * x12 + ca * x22;
         nxt[pa * LD + pb] = cb * y11 - sb * y12;
@@ -152,11 +192,17 @@ __device__ double *jacobi_lds(double *a, double *a2, double *v, double floor_abs
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
         const int r = i0 + k * TR;
-        const double vp = v[r * LD + pb], vq = v[r * LD + qb];
-        v[r * LD + pb] = cb * vp - sb * vq;
-        v[r * LD + qb] = sb * vp + cb * vq;
+        v[r * LD + pb] = cb * vp[k] - sb * vq[k];
+        v[r * LD + qb] = sb * vp[k] + cb * vq[k];
       }
       if (rotated) rot_flag[sweep & 1] = 1;
+      // next step's players: player 0 stays, the others advance cyclically
+      // through 1 .. S - 1 (in arithmetic: no divergent branches)
+#pragma unroll
+      for (int k = 0; k <= BPT; ++k) {
+        pr[k] = rr_next<S>(pr[k]);
+        qr[k] = rr_next<S>(qr[k]);
+      }
       __syncthreads();
       double *t = cur; cur = nxt; nxt = t;
     }
@@ -230,11 +276,13 @@ __device__ __forceinline__ int sub_index(int u, int bi, int bj) {
 }
 
 // One workgroup per pair: one Jacobi sweep of M[S, S], S = block(bi) U block(bj).
+// rflag[pair] = 0 when no off-diagonal entry of the subproblem needed a
+// rotation (R = I exactly), 1 otherwise.
 constexpr int kPairThreads = 256;
 __global__ __launch_bounds__(kPairThreads) void bj_pair_kernel(const double *__restrict__ M, int64_t lp, int nb,
                                                      int step, double *__restrict__ R,
                                                      const double *__restrict__ floor_abs,
-                                                     double rel) {
+                                                     double rel, int *__restrict__ rflag) {
   __shared__ double a[kSub * kSubLd];
   __shared__ double a2[kSub * kSubLd];
   __shared__ double v[kSub * kSubLd];
@@ -258,6 +306,7 @@ __global__ __launch_bounds__(kPairThreads) void bj_pair_kernel(const double *__r
   __syncthreads();
   double *Rp = R + (int64_t)pair * kSub * kSub;
   for (int e = tid; e < kSub * kSub; e += kPairThreads) Rp[e] = v[(e / kSub) * kSubLd + (e % kSub)];
+  if (tid == 0) rflag[pair] = any_big ? 1 : 0;
 }
 
 // 32 x 32 products on the FP64 matrix cores (v_mfma_f64_16x16x4f64): wave w
@@ -282,10 +331,12 @@ __device__ __forceinline__ doublex4 mm32_quadrant(const double *L, const double 
 
 // Rotate M (pair blocks) and V (row tiles x pair columns) in place:
 // M[S_p, S_q] <- R_p^T M[S_p, S_q] R_q, V[:, S_q] <- V[:, S_q] R_q.  Each
-// workgroup reads its whole block before writing it back.
+// workgroup reads its whole block before writing it back.  A block whose
+// rotations are all the identity (rflag 0) is left as it is.
 __global__ __launch_bounds__(256) void bj_update_kernel(double *__restrict__ M, double *__restrict__ V,
                                                         int64_t lp, int nb, int step,
-                                                        const double *__restrict__ R) {
+                                                        const double *__restrict__ R,
+                                                        const int *__restrict__ rflag) {
   __shared__ double blk[kSub * kSubLd];
   __shared__ double tmp[kSub * kSubLd];
   __shared__ double rq[kSub * kSubLd];
@@ -301,6 +352,7 @@ __global__ __launch_bounds__(256) void bj_update_kernel(double *__restrict__ M, 
   int64_t rowtile = 0;
   if (is_m) { p = (int)(id / npairs); q = (int)(id % npairs); }
   else { const int64_t k = id - nm; rowtile = k / npairs; q = (int)(k % npairs); p = -1; }
+  if (rflag[q] == 0 && (!is_m || rflag[p] == 0)) return;      // uniform: the whole workgroup
   const int qi = rr_player(q, step, nb), qj = rr_player(nb - 1 - q, step, nb);
   for (int e = tid; e < kSub * kSub; e += 256) {
     rq[(e / kSub) * kSubLd + e % kSub] = R[(int64_t)q * kSub * kSub + e];
@@ -514,6 +566,7 @@ size_t eig_workspace_bytes(int64_t l) {
   bytes += (size_t)lp * lp * 8 * 2;                 // M, V
   bytes += (size_t)(nb / 2) * kSub * kSub * 8;      // rotations
   bytes += (size_t)lp * 4 + 64;                     // perm, counters
+  bytes += (size_t)(nb / 2) * 4 + 64;               // per-pair rotation flags
   bytes += 256;
   return bytes;
 }
@@ -538,6 +591,7 @@ int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, dou
   double *V = reinterpret_cast<double *>(p); p += (size_t)lp * lp * 8;
   double *R = reinterpret_cast<double *>(p); p += (size_t)npairs * kSub * kSub * 8;
   int *perm = reinterpret_cast<int *>(p); p += (size_t)lp * 4;
+  int *rflag = reinterpret_cast<int *>(p); p += (size_t)npairs * 4;
   p = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(p) + 63) & ~uintptr_t(63));
   int *count = reinterpret_cast<int *>(p);
   double *floor_abs = reinterpret_cast<double *>(p + 8);
@@ -575,9 +629,9 @@ int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, dou
     ++sweeps;
     for (int step = 0; step < nb - 1; ++step) {
       hipLaunchKernelGGL(bj_pair_kernel, dim3(npairs), dim3(kPairThreads), 0, st, M, lp, nb, step, R, floor_abs,
-                         rel);
+                         rel, rflag);
       const int64_t nwg = (int64_t)npairs * npairs + (lp / kSub) * npairs;
-      hipLaunchKernelGGL(bj_update_kernel, dim3((unsigned)nwg), dim3(256), 0, st, M, V, lp, nb, step, R);
+      hipLaunchKernelGGL(bj_update_kernel, dim3((unsigned)nwg), dim3(256), 0, st, M, V, lp, nb, step, R, rflag);
     }
   }
   hipLaunchKernelGGL(bj_rank_kernel, dim3((unsigned)((l + 255) / 256)), dim3(256), 0, st, M, l, lp, perm);

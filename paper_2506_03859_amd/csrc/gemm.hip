@@ -549,9 +549,11 @@ static int gemm_best_split(int64_t M, int64_t K, int wm, int64_t smax, int64_t s
 // WM = 1).  The choice does not depend on the caller's split limit, so that
 // launch and split choice agree.
 static int gemm_wm(int64_t M, int64_t K, int is_tn) {
-  // short NN products over many rows (Q r: K = l, M = m): each wave walks the
-  // whole K range of its own 64 rows, with no cross-wave reduction at the end
-  if (K < 1024) return (!is_tn && M >= 8192) ? 4 : 1;
+  // short NN products (Q r: K = l): with enough rows for two 256-row tiles
+  // per CU, each wave walks the whole K range of its own 64 rows (no
+  // cross-wave reduction at the end); with fewer, 64-row tiles spread the
+  // product over more CUs (20000 rows: 313 workgroups against 79)
+  if (K < 1024) return (!is_tn && M >= 131072) ? 4 : 1;
   double c1 = 0.0, c4 = 0.0;
   gemm_best_split(M, K, 1, 64, gemm_slots(is_tn, 1), &c1);
   gemm_best_split(M, K, 4, 64, gemm_slots(is_tn, 4), &c4);
