@@ -102,6 +102,7 @@ KERNEL_SOURCES = {
     "gemm_nn": ["paper_2506_03859_amd/csrc/gemm.hip"],
     "sketch": ["paper_2506_03859_amd/csrc/sketch.hip"],
     "gemm_tn_bf16": ["paper_2506_03859_amd/csrc/gemm_bf16.hip"],
+    "gemm_tn_split": ["paper_2506_03859_amd/csrc/gemm_bf16.hip"],
     "gemm_nn_bf16": ["paper_2506_03859_amd/csrc/gemm_bf16.hip"],
     "sketch_bf16": ["paper_2506_03859_amd/csrc/sketch.hip"],
 }
@@ -196,7 +197,7 @@ def time_solves(wl, A, steps, warmup, dev):
            "ms_per_solve": ms, "solves_per_s": 1e3 / ms,
            "l": sorted({i[1] for i in infos}), "blocks": sorted({i[2] for i in infos}),
            "status": sorted({i[0] for i in infos})}
-    for c in ("gemm_tn", "gemm_nn", "sketch", "eig"):
+    for c in ("gemm_tn", "gemm_nn", "gemm_c", "sketch", "eig"):
         tot, cnt = prof[c]
         if not cnt:
             continue
@@ -239,12 +240,24 @@ def kernel_probe(wl, dev, reps=3):
         off = (-buf.data_ptr()) % 256
         scratch = buf[off:off + nb]
         gemm_tn, gemm_nn = fp.farpca_gemm_bf16_tn, fp.farpca_gemm_bf16_nn
+    elif layout == "row":
+        # the solve's power-step A^T T passes on row-major FP32 A run split on
+        # the BF16 matrix cores, A G on the FP32 ones
+        nb = max(fp.farpca_gemm_bf16_scratch_bytes(max(m, n), max(m, n)),
+                 fp.farpca_gemm_scratch_bytes(max(m, n)))
+        buf = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        off = (-buf.data_ptr()) % 256
+        scratch = buf[off:off + nb]
+        gemm_tn, gemm_nn = fp.farpca_gemm_f32s_tn, fp.farpca_gemm_nn
     else:
         scratch = torch.empty(fp.farpca_gemm_scratch_bytes(max(m, n)) // 4, device=dev)
         gemm_tn, gemm_nn = fp.farpca_gemm_tn, fp.farpca_gemm_nn
     for r in range(reps):
         gemm_tn(A, skinny_m, Cn, n, b, m, scratch)
         gemm_nn(A, skinny_n, Cm, m, b, n, scratch)
+        if storage == "f32" and layout == "row":
+            # C_j^T = A^T Q_j stays on the FP32 matrix cores
+            fp.farpca_gemm_tn(A, skinny_m, Cn, n, b, m, scratch)
         # column-major workloads: the sketch reads A^T row-major (same buffer, n x m)
         fp.farpca_sketch(plan, A if layout == "row" else A.reshape(n, m), r, work, Cm)
     torch.cuda.synchronize()
@@ -696,12 +709,17 @@ def main():
     elem = 2.0 if storage == "bf16" else 4.0
     a_bytes = elem * m * n
     cand = {}
-    for c in ("gemm_tn", "gemm_nn", "sketch"):
+    for c in ("gemm_tn", "gemm_nn", "gemm_c", "sketch"):
         a_ms, cnt = avg(c)
         if a_ms:
             cand[c] = (prof[c][0], a_ms, cnt)
     dom = max(cand, key=lambda c: cand[c][0])
     tot_ms, a_ms, cnt = cand[dom]
+    layout = LAYOUTS.get(wl, "row")
+    # row-major FP32 A: the power-step A^T T products run split on the BF16
+    # matrix cores, A G and C_j^T = A^T Q_j on the FP32 ones
+    split = storage == "f32" and layout == "row" and dom == "gemm_tn"
+    pass_name = {"gemm_tn": "A^T Y", "gemm_nn": "A G", "gemm_c": "C_j^T = A^T Q_j"}.get(dom)
     if dom == "sketch":
         alg = a_bytes + 4.0 * m * b
         achieved = alg / (a_ms * 1e-3) / 1e9
@@ -711,23 +729,35 @@ def main():
         # BF16 A-passes: 2 m n bytes of A per launch against HBM (the exact
         # three-term products need 3 x 2 m n b flop of BF16 MFMA, under its peak)
         achieved = a_bytes / (a_ms * 1e-3) / 1e9
-        roof = {"kernel": f"{dom}_bf16_kernel", "bound": "hbm", "achieved": achieved,
+        kname = f"gemm_bf16_kernel<{'false' if dom == 'gemm_nn' else 'true'}, *, false> ({pass_name})"
+        roof = {"kernel": kname, "bound": "hbm", "achieved": achieved,
                 "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS}
+    elif split:
+        # FP32 A-passes on the BF16 matrix cores (both operands split in three,
+        # 6 x 2 m n b flop of BF16 MFMA, far under its peak): 4 m n bytes of A
+        # per launch against HBM
+        achieved = a_bytes / (a_ms * 1e-3) / 1e9
+        kname = "gemm_bf16_kernel<true, true, true> (A^T Y, FP32 A split)"
+        roof = {"kernel": kname, "bound": "hbm",
+                "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBPS,
+                "fp32_equivalent_tflops": gemm_flops / (a_ms * 1e-3) / 1e12}
     else:
         achieved = gemm_flops / (a_ms * 1e-3) / 1e12
-        roof = {"kernel": f"{dom}_kernel", "bound": "mfma", "achieved": achieved,
+        kname = f"gemm_kernel<{'false' if dom == 'gemm_nn' else 'true'}, *> ({pass_name}, FP32 matrix cores)"
+        roof = {"kernel": kname, "bound": "mfma", "achieved": achieved,
                 "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS}
     if dom == "sketch":
         alg_per_launch = a_bytes + 4.0 * m * b
     else:
-        alg_per_launch = a_bytes if storage == "bf16" else gemm_flops
-    layout = LAYOUTS.get(wl, "row")
-    traffic_key = dom if storage == "f32" else f"{dom}_bf16"
+        alg_per_launch = a_bytes if (storage == "bf16" or split) else gemm_flops
+    base_key = "gemm_tn" if dom == "gemm_c" else dom
+    traffic_key = f"{dom}_split" if split else (base_key if storage == "f32" else f"{base_key}_bf16")
     roof.update({"avg_launch_ms": a_ms, "launches": cnt, "algorithmic_per_launch": alg_per_launch,
                  "traffic": measured_traffic(traffic_key) if layout == "row" else None})
     if layout == "col" and dom != "sketch":
         # A^T row-major: the logical A^T Y runs on the NN kernel, A G on the TN one
-        roof["kernel"] = f"{dom} as the {'NN' if dom == 'gemm_tn' else 'TN'} kernel on A^T"
+        roof["kernel"] = f"{pass_name} as the {'TN' if dom == 'gemm_nn' else 'NN'} kernel on A^T"
     if layout == "col" and dom == "sketch":
         roof["kernel"] = "sketch_cols_kernel"
         alg_per_launch = 4.0 * m * (p * n * b) + 4.0 * m * b
@@ -746,7 +776,7 @@ def main():
     else:
         sk_bytes = a_bytes + 4.0 * m * b
     sketch_gbps = sk_bytes / (sk_ms * 1e-3) / 1e9 if sk_ms else None
-    for c in ("gemm_tn", "gemm_nn"):
+    for c in ("gemm_tn", "gemm_nn", "gemm_c"):
         if classes[c]["avg_launch_ms"]:
             classes[c]["tflops"] = gemm_flops / (classes[c]["avg_launch_ms"] * 1e-3) / 1e12
             classes[c]["a_GBps"] = a_bytes / (classes[c]["avg_launch_ms"] * 1e-3) / 1e9

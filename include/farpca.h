@@ -266,6 +266,20 @@ int farpca_gemm_bf16_nn(const uint16_t *dA, int64_t lda, const float *dX, int64_
 int farpca_gemm_bf16_tn(const uint16_t *dA, int64_t lda, const float *dY, int64_t ldy, float *dC,
                         int64_t ldc, int64_t M, int64_t N, int64_t K, void *dScratch, void *stream);
 
+/* The FP32 products on the BF16 matrix cores (the dense A-passes of Algorithms
+ * 1 and 2 with A in FP32): both operands are split exactly into three BF16
+ * terms (rounding to nearest; each difference is exact in FP32) and six of
+ * the nine term products are accumulated in FP32 (hi hi, hi mid, mid hi, mid
+ * mid, hi lo, lo hi).  The three left out are below 2^-23 |a x| per product
+ * together and of either sign (about one FP32 rounding of the product), so
+ * the result carries FP32-level rounding, not BF16's.  Same arguments, scratch
+ * (farpca_gemm_bf16_scratch_bytes) and readability rule as the BF16 products,
+ * with A FP32. */
+int farpca_gemm_f32s_nn(const float *dA, int64_t lda, const float *dX, int64_t ldx, float *dC,
+                        int64_t ldc, int64_t M, int64_t N, int64_t K, void *dScratch, void *stream);
+int farpca_gemm_f32s_tn(const float *dA, int64_t lda, const float *dY, int64_t ldy, float *dC,
+                        int64_t ldc, int64_t M, int64_t N, int64_t K, void *dScratch, void *stream);
+
 /* FP64 symmetric eigendecomposition (block Jacobi) of K (l x l, row-major):
  * dW (l) descending, dV (l x l) eigenvectors in columns.  dWork holds
  * farpca_eig_scratch_bytes(l) bytes.  The sweeps stop once every off-diagonal
@@ -345,10 +359,11 @@ int farpca_server_destroy(farpca_server_t *srv);
  * and, on return, adds their elapsed times per class.  Enabling resets the
  * totals.  Events cost a few microseconds per launch; leave off in production. */
 #define FARPCA_PROF_SKETCH 0   /* sparse sketch kernel (partials not included)   */
-#define FARPCA_PROF_GEMM_TN 1  /* A^T T products (power steps, C_j^T = A^T Q_j)  */
+#define FARPCA_PROF_GEMM_TN 1  /* A^T T products of the power steps              */
 #define FARPCA_PROF_GEMM_NN 2  /* A G products (and the Gaussian sketch)        */
 #define FARPCA_PROF_EIG 3      /* final FP64 eigendecomposition                 */
-#define FARPCA_PROF_NCLASS 4
+#define FARPCA_PROF_GEMM_C 4   /* C_j^T = A^T Q_j (values kept in C and E)      */
+#define FARPCA_PROF_NCLASS 5
 void farpca_profile_enable(int on);
 int farpca_profile_get(int cls, double *total_ms, int64_t *count);
 

@@ -63,6 +63,7 @@ struct farpca_plan_s {
   bool bf16;            // A holds BF16 bit patterns (precision form)
   bool colmajor;        // A stored column-major (FARPCA_LAYOUT_COL)
   bool c64;             // C_j^T = A^T Q_j with FP64 accumulation (tol below kC64Tol)
+  bool split;           // A^T T passes on the BF16 matrix cores with both operands split (FP32 row-major A)
   int b;
   int P;
   int kind;
@@ -192,7 +193,7 @@ static size_t carve_loop(farpca_plan_s *pl, int64_t cap) {
   pl->off_sq = c.take((size_t)256 * 8);                               // <= 256 partials for any K
   pl->off_scal = c.take(64);                        // nA2, E, alpha, flags, truncation rank
   pl->off_ehist = c.take((size_t)pl->maxblk * 8);
-  pl->off_xt = pl->bf16 ? c.take(bf16_pack_bytes(imax(m, n))) : 0;
+  pl->off_xt = (pl->bf16 || pl->split) ? c.take(bf16_pack_bytes(imax(m, n))) : 0;
   // column-major: one list per column of Omega_j over all n rows
   pl->off_flat = pl->colmajor ? c.take((size_t)b * n * sizeof(ChunkEntry)) : 0;
   pl->off_colcnt = pl->colmajor ? c.take((size_t)kMaxBlock * 4) : 0;
@@ -247,6 +248,7 @@ extern "C" int farpca_plan(const farpca_params *prm, farpca_plan_t **out, int64_
   pl->bf16 = q.a_dtype == FARPCA_DTYPE_BF16;
   pl->colmajor = colmajor;
   pl->c64 = q.tol > 0.0 && q.tol < kC64Tol;
+  pl->split = !pl->bf16 && !colmajor;
   pl->b = b;
   pl->P = q.power;
   pl->kind = q.sketch;
@@ -408,9 +410,13 @@ int setup_partials(const farpca_plan_s *pl) {
 //   NN (tn false): C (m x ncols) = A X, X n x ncols (ld kBld)
 //   TN (tn true):  C (n x ncols) = A^T T, T m x ncols (ld kBld)
 // Returns the number of partial products left in the partial buffer (1: C
-// was written directly); launch_gemm_finish completes the product.
+// was written directly); launch_gemm_finish completes the product.  With FP32
+// row-major A a TN pass runs split on the BF16 matrix cores unless allow_split
+// is false (the FP32 matrix cores).  NN passes stay on the FP32 matrix cores:
+// split, their row pieces (a few hundred bytes of each of many rows per
+// workgroup) hold them near the same HBM rate, so they would gain nothing.
 int a_pass(const farpca_plan_s *pl, const Ws &w, bool tn, const void *A, const float *X, int ncols,
-           float *C, int64_t ldc, hipStream_t st) {
+           float *C, int64_t ldc, hipStream_t st, bool allow_split = true) {
   const farpca_params &q = pl->prm;
   float *part = w.at<float>(pl->off_part);
   const int64_t M = tn ? q.n : q.m, K = tn ? q.m : q.n;
@@ -424,6 +430,17 @@ int a_pass(const farpca_plan_s *pl, const Ws &w, bool tn, const void *A, const f
                                          part, xt, st);
   }
   const float *Af = static_cast<const float *>(A);
+  if (pl->split && allow_split && tn) {
+    // FP32 A on the BF16 matrix cores (exact three-term splits of both
+    // operands, six term products): the pass is then bound by streaming A,
+    // not by the FP32 matrix-core rate
+    float *xt = w.at<float>(pl->off_xt);
+    const int ks = gemm_f32s_choose_ksplit(M, K, tn, pl->part_splits(M));
+    return tn ? launch_gemm_f32s_tn_main(Af, q.lda, X, kBld, C, ldc, M, ncols, K, 1.f, 0.f, ks,
+                                         part, xt, st)
+              : launch_gemm_f32s_nn_main(Af, q.lda, X, kBld, C, ldc, M, ncols, K, 1.f, 0.f, ks,
+                                         part, xt, st);
+  }
   // column-major A is A^T row-major: A X is its TN product, A^T T its NN one
   const bool ktn = pl->colmajor ? !tn : tn;
   const int ks = gemm_choose_ksplit(M, K, ktn, pl->part_splits(M));
@@ -717,8 +734,10 @@ static int enqueue_block(farpca_plan_s *pl, hipStream_t st) {
   } else {
     int nsp4;
     {
-      ProfScope ps(FARPCA_PROF_GEMM_TN, st);
-      nsp4 = a_pass(pl, w, true, A, Ysrc, b, Ct + l, pl->ldq, st);
+      // C_j stays on the FP32 matrix cores: its values are what the indicator
+      // subtracts from ||A||^2 and what the final decomposition reads
+      ProfScope ps(FARPCA_PROF_GEMM_C, st);
+      nsp4 = a_pass(pl, w, true, A, Ysrc, b, Ct + l, pl->ldq, st, false);
     }
     launch_gemm_finish(part, nsp4, n, b, Ct + l, pl->ldq, 1.f, 0.f, st);
     launch_sqnorm(Ct + l, pl->ldq, n, b, w.at<double>(pl->off_sq), st);
@@ -1041,6 +1060,44 @@ extern "C" int farpca_gemm_bf16_tn(const uint16_t *dA, int64_t lda, const float 
                                         align_up((size_t)16 * M * kBld * 4));
   const int ks = gemm_bf16_choose_ksplit(M, K, 1, 16);
   const int nsp = launch_gemm_bf16_tn_main(dA, lda, dY, ldy, dC, ldc, M, N, K, 1.f, 0.f, ks, part,
+                                           xt, st);
+  launch_gemm_finish(part, nsp, M, N, dC, ldc, 1.f, 0.f, st);
+  HIP_OK(hipGetLastError());
+  return FARPCA_OK;
+}
+
+extern "C" int farpca_gemm_f32s_nn(const float *dA, int64_t lda, const float *dX, int64_t ldx,
+                                   float *dC, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                                   void *dScratch, void *stream) {
+  if (!dA || !dX || !dC || !dScratch || M < 1 || K < 1 || N < 1 || N > kBld || lda < K ||
+      ldx < N || ldc < N)
+    return FARPCA_E_INVALID;
+  if ((reinterpret_cast<uintptr_t>(dScratch) & 255) != 0) return FARPCA_E_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float *part = static_cast<float *>(dScratch);
+  float *xt = reinterpret_cast<float *>(static_cast<char *>(dScratch) +
+                                        align_up((size_t)16 * M * kBld * 4));
+  const int ks = gemm_f32s_choose_ksplit(M, K, 0, 16);
+  const int nsp = launch_gemm_f32s_nn_main(dA, lda, dX, ldx, dC, ldc, M, N, K, 1.f, 0.f, ks, part,
+                                           xt, st);
+  launch_gemm_finish(part, nsp, M, N, dC, ldc, 1.f, 0.f, st);
+  HIP_OK(hipGetLastError());
+  return FARPCA_OK;
+}
+
+extern "C" int farpca_gemm_f32s_tn(const float *dA, int64_t lda, const float *dY, int64_t ldy,
+                                   float *dC, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                                   void *dScratch, void *stream) {
+  if (!dA || !dY || !dC || !dScratch || M < 1 || K < 1 || N < 1 || N > kBld || lda < M ||
+      ldy < N || ldc < N)
+    return FARPCA_E_INVALID;
+  if ((reinterpret_cast<uintptr_t>(dScratch) & 255) != 0) return FARPCA_E_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float *part = static_cast<float *>(dScratch);
+  float *xt = reinterpret_cast<float *>(static_cast<char *>(dScratch) +
+                                        align_up((size_t)16 * M * kBld * 4));
+  const int ks = gemm_f32s_choose_ksplit(M, K, 1, 16);
+  const int nsp = launch_gemm_f32s_tn_main(dA, lda, dY, ldy, dC, ldc, M, N, K, 1.f, 0.f, ks, part,
                                            xt, st);
   launch_gemm_finish(part, nsp, M, N, dC, ldc, 1.f, 0.f, st);
   HIP_OK(hipGetLastError());

@@ -7,10 +7,10 @@
 //   TN: C[M x N] = A^T Y, A is K x M        (A row-major BF16, reduce over rows)
 //
 // Exact skinny operand.  The FP32 skinny operand x is split into three BF16
-// terms by truncation: hi = x with the low 16 bits cleared, mid = (x - hi)
-// truncated the same way, lo = x - hi - mid.  Each difference is exact in FP32
-// and x = hi + mid + lo exactly (24 significand bits = 3 x 8; while lo is a
-// normal number, |x| >= 2^-110, below which bits under 2^-126 are dropped), so three MFMAs
+// terms by rounding to nearest: hi = rn(x), mid = rn(x - hi), lo = x - hi -
+// mid.  Each difference is exact in FP32 and x = hi + mid + lo exactly (lo has
+// at most 8 significant bits while it is a normal number, |x| >= 2^-110, below
+// which bits under 2^-126 are dropped), so three MFMAs
 // per product reproduce the products A_ij x_j exactly (BF16 x BF16 products are
 // exact in FP32) and only the FP32 accumulation rounds: the precision form
 // computes what the FP32 path would compute on the BF16-rounded matrix.  At
@@ -40,6 +40,17 @@
 // Output D lane l element v = (row 4 (l/16) + v, column l % 16).
 // Rows / columns outside the matrix are read at clamped addresses (finite
 // values that meet zero skinny entries or feed outputs that are never stored).
+//
+// FP32 A (the same kernel, F32 = true).  The FP32 A-passes are bound by the
+// FP32 matrix-core rate (157 TFLOP/s: 2 m n b flop per 4 m n bytes needs 20
+// TB/s of A at b = 64), the BF16 matrix cores are 16 times faster: A is split
+// in registers into three BF16 terms as well and six term products are formed,
+// 6 x 2 m n b BF16 flop, well under the time it takes to stream A.  Each lane
+// holds FP32 values (16 bytes per load) in the same operand positions as the
+// BF16 layout: TN reads 16 bytes (4 columns) of each of its 8 rows, 256
+// contiguous bytes per row and instruction; NN holds 2 row groups per wave
+// (32 rows, 256 per workgroup) with 64-deep slices, 256 contiguous bytes per
+// row and slice.
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -62,23 +73,40 @@ constexpr int kKGroup = 192;                  // K granularity of splits and pad
 // that a lane's two 16-byte loads of a row are back-to-back halves of one
 // 128-byte line (64-byte row pieces one slice apart stream at a much lower HBM
 // rate); TN rows are read as 128-byte runs already.
-template <bool TN> struct B16Cfg;
-template <> struct B16Cfg<true> {
-  static constexpr int SL = 32, RING = 6, NBUF = 2, AV = 4;
+template <bool TN, bool F32> struct B16Cfg;
+// RG: 16-row groups of output rows per wave.
+template <> struct B16Cfg<true, false> {
+  static constexpr int SL = 32, RING = 6, NBUF = 2, AV = 4, RG = 4;
 };
-template <> struct B16Cfg<false> {
-  static constexpr int SL = 64, RING = 3, NBUF = 3, AV = 8;
+template <> struct B16Cfg<false, false> {
+  static constexpr int SL = 64, RING = 3, NBUF = 3, AV = 8, RG = 4;
 };
-template <bool TN> struct B16Lds {
-  static constexpr int CS = B16Cfg<TN>::SL + 8;   // BF16 per staged column (16-byte aligned)
-  static constexpr int PLANE = kBld * CS;          // BF16 per split plane
-  static constexpr int STAGE = 3 * PLANE;          // BF16 per staged slice
-  static constexpr int XL = B16Cfg<TN>::SL / 32;   // float4 skinny pieces per thread per slice
+// FP32 A: a slot holds 8 float4 per lane, so the ring is shallower.  TN: 4
+// columns of 8 rows, 32-deep slices.  NN: 2 row groups per wave (32 output
+// rows) and 64-deep slices, so that a slice reads 256 contiguous bytes of each
+// row (16 k of 2 rows per lane).
+template <> struct B16Cfg<true, true> {
+  static constexpr int SL = 32, RING = 3, NBUF = 3, AV = 8, RG = 4;
 };
-static_assert(B16Cfg<true>::SL * B16Cfg<true>::RING == kKGroup, "TN group");
-static_assert(B16Cfg<false>::SL * B16Cfg<false>::RING == kKGroup, "NN group");
+template <> struct B16Cfg<false, true> {
+  static constexpr int SL = 64, RING = 3, NBUF = 3, AV = 8, RG = 2;
+};
+template <bool TN, bool F32> constexpr int kWgRows = 16 * B16Cfg<TN, F32>::RG * kB16Waves;
+template <bool TN, bool F32> struct B16Lds {
+  static constexpr int CS = B16Cfg<TN, F32>::SL + 8;   // BF16 per staged column (16-byte aligned)
+  static constexpr int PLANE = kBld * CS;               // BF16 per split plane
+  static constexpr int STAGE = 3 * PLANE;               // BF16 per staged slice
+  static constexpr int XL = B16Cfg<TN, F32>::SL / 32;   // float4 skinny pieces per thread per slice
+};
+template <bool TN, bool F32> constexpr int kGroup = B16Cfg<TN, F32>::SL * B16Cfg<TN, F32>::RING;
+static_assert(kGroup<true, false> == kKGroup && kGroup<false, false> == kKGroup, "BF16 groups");
+static_assert(kKGroup % kGroup<true, true> == 0 && kKGroup % kGroup<false, true> == 0,
+              "FP32 groups divide the split granularity");
 static_assert(kB16Threads == kBld * 8, "eight column pieces per skinny column");
-static_assert(B16Cfg<true>::RING % B16Cfg<true>::NBUF == 0 && B16Cfg<false>::RING % B16Cfg<false>::NBUF == 0,
+static_assert(B16Cfg<true, false>::RING % B16Cfg<true, false>::NBUF == 0 &&
+                  B16Cfg<false, false>::RING % B16Cfg<false, false>::NBUF == 0 &&
+                  B16Cfg<true, true>::RING % B16Cfg<true, true>::NBUF == 0 &&
+                  B16Cfg<false, true>::RING % B16Cfg<false, true>::NBUF == 0,
               "static LDS buffer of every unrolled step");
 
 __device__ __forceinline__ floatx4 mfma_bf16(u32x4 a, u32x4 b, floatx4 c) {
@@ -118,7 +146,8 @@ __global__ __launch_bounds__(256) void bf16_pack_kernel(const float *__restrict_
 
 // ---------------------------------------------------------- A slot loads
 // NN: v[2 rt + ks] = row group rt, MFMA step ks; TN: rows (2 j, 2 j + 1) in v[j].
-template <bool TN> struct ASlot { u32x4 v[B16Cfg<TN>::AV]; };
+template <bool TN, bool F32> struct ASlot { u32x4 v[B16Cfg<TN, F32>::AV]; };
+template <bool TN> struct ASlot<TN, true> { float4 v[B16Cfg<TN, true>::AV]; };
 
 // AVEC, NN: rows hold whole groups of 8 up to k8 = K rounded up to 8 (K % 8
 // == 0, or lda >= k8): a group is read at its start clamped to k8 - 8, and
@@ -129,7 +158,7 @@ template <bool TN> struct ASlot { u32x4 v[B16Cfg<TN>::AV]; };
 template <bool TN, bool AVEC>
 __device__ __forceinline__ void load_slot(const uint16_t *A, int64_t lda, int64_t M,
                                           int64_t K, int64_t t0, int li, int lk, int64_t k0,
-                                          ASlot<TN> &s, int64_t mclamp) {
+                                          ASlot<TN, false> &s, int64_t mclamp) {
   if constexpr (!TN) {
     const int64_t k8 = (K + 7) & ~int64_t(7);
 #pragma unroll
@@ -200,7 +229,7 @@ __device__ __forceinline__ void load_slot(const uint16_t *A, int64_t lda, int64_
 // TN: the MFMA operand of column t (0..3) of the lane's 4 columns: element e =
 // row 8 lk + e.  v[j] holds row 2 j in (x, y) and row 2 j + 1 in (z, w), each
 // row as (columns 0,1), (columns 2,3).
-__device__ __forceinline__ u32x4 tn_operand(const ASlot<true> &s, int t) {
+__device__ __forceinline__ u32x4 tn_operand(const ASlot<true, false> &s, int t) {
   uint32_t d[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -211,39 +240,58 @@ __device__ __forceinline__ u32x4 tn_operand(const ASlot<true> &s, int t) {
   return u32x4{d[0], d[1], d[2], d[3]};
 }
 
-// Split the thread's 4 XL FP32 skinny values (k = 4 XL kq .. + 4 XL - 1 of
-// column sc) into the three BF16 planes of the staged slice.
-__device__ __forceinline__ void split3(float v, uint32_t &hi, uint32_t &mid, uint32_t &lo) {
-  hi = __float_as_uint(v) & 0xFFFF0000u;
-  const float r = v - __uint_as_float(hi);                         // exact
-  mid = __float_as_uint(r) & 0xFFFF0000u;
-  lo = __float_as_uint(r - __uint_as_float(mid)) & 0xFFFF0000u;    // exact, <= 8 bits
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values rounded to nearest BF16 (v_cvt_pk_bf16_f32), the first in the
+// low half.
+__device__ __forceinline__ uint32_t rn_pair(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){a, b}, bf16x2));
 }
 
-template <bool TN>
+// Exact split of two FP32 values into three BF16 terms each, packed in pairs:
+// hi = rn(v), mid = rn(v - hi), lo = v - hi - mid.  Both differences are exact
+// in FP32 (|v - hi| <= 2^-8 |v| on the FP32 grid of v), and lo has at most 8
+// significant bits, so v = hi + mid + lo exactly while lo is a normal number
+// (|v| >= 2^-110; below that, bits under 2^-126 are dropped); |mid| <= 2^-8
+// |v|, |lo| <= 2^-16 |v|, and the residuals take either sign.
+__device__ __forceinline__ void split_pair(float a0, float a1, uint32_t &h, uint32_t &m, uint32_t &l) {
+  h = rn_pair(a0, a1);
+  const float r0 = a0 - __uint_as_float(h << 16);             // exact
+  const float r1 = a1 - __uint_as_float(h & 0xFFFF0000u);
+  m = rn_pair(r0, r1);
+  const float s0 = r0 - __uint_as_float(m << 16);             // exact, <= 8 bits
+  const float s1 = r1 - __uint_as_float(m & 0xFFFF0000u);
+  l = rn_pair(s0, s1);                                        // exact
+}
+
+// FP32 A, NN: the group of 4 k at j = 4 .. 4 j + 3 of a 32-k step goes to the
+// MFMA positions of the permuted order (see load_slot_f32): 8 (j % 4) + 4 (j / 4).
+template <bool TN, bool F32>
 __device__ __forceinline__ void stage_skinny(uint16_t *xs, int sc, int kq,
-                                             const float4 (&x)[B16Lds<TN>::XL]) {
-  using Lds = B16Lds<TN>;
-  uint16_t *base = xs + sc * Lds::CS + 4 * Lds::XL * kq;
+                                             const float4 (&x)[B16Lds<TN, F32>::XL]) {
+  using Lds = B16Lds<TN, F32>;
+  constexpr bool kPerm = F32 && !TN;
+  uint16_t *col = xs + sc * Lds::CS;
 #pragma unroll
   for (int g = 0; g < Lds::XL; ++g) {
-    const float v[4] = {x[g].x, x[g].y, x[g].z, x[g].w};
-    uint32_t hi[4], mid[4], lo[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) split3(v[i], hi[i], mid[i], lo[i]);
-    *reinterpret_cast<uint2 *>(base + 4 * g) = make_uint2((hi[0] >> 16) | hi[1], (hi[2] >> 16) | hi[3]);
-    *reinterpret_cast<uint2 *>(base + 4 * g + Lds::PLANE) =
-        make_uint2((mid[0] >> 16) | mid[1], (mid[2] >> 16) | mid[3]);
-    *reinterpret_cast<uint2 *>(base + 4 * g + 2 * Lds::PLANE) =
-        make_uint2((lo[0] >> 16) | lo[1], (lo[2] >> 16) | lo[3]);
+    const int j = Lds::XL * kq + g;                   // 4-group of k in the slice
+    const int pos = kPerm ? 32 * (j >> 3) + 8 * (j & 3) + 4 * ((j >> 2) & 1) : 4 * j;
+    uint32_t h0, m0, l0, h1, m1, l1;
+    split_pair(x[g].x, x[g].y, h0, m0, l0);
+    split_pair(x[g].z, x[g].w, h1, m1, l1);
+    *reinterpret_cast<uint2 *>(col + pos) = make_uint2(h0, h1);
+    *reinterpret_cast<uint2 *>(col + pos + Lds::PLANE) = make_uint2(m0, m1);
+    *reinterpret_cast<uint2 *>(col + pos + 2 * Lds::PLANE) = make_uint2(l0, l1);
   }
 }
 
 template <bool TN>
-__device__ __forceinline__ void mma_slice_bf16(floatx4 (&acc)[16], const ASlot<TN> &s,
+__device__ __forceinline__ void mma_slice_bf16(floatx4 (&acc)[16], const ASlot<TN, false> &s,
                                                const uint16_t *xs, int li, int lk) {
-  using Lds = B16Lds<TN>;
-  constexpr int KS = B16Cfg<TN>::SL / 32;
+  using Lds = B16Lds<TN, false>;
+  constexpr int KS = B16Cfg<TN, false>::SL / 32;
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
     u32x4 a[4];
@@ -265,13 +313,146 @@ __device__ __forceinline__ void mma_slice_bf16(floatx4 (&acc)[16], const ASlot<T
   }
 }
 
+// ------------------------------------------------------- FP32 A operand
+// FP32 A, same operand layout as the BF16 slots but 4 bytes per element.
+//   NN: v[(rt KS + ks) 2 + h] = row t0 + 16 rt + li (rt < RG), k = k0 + 32 ks +
+//       16 h + 4 lk .. + 3 (KS = SL / 32 MFMA steps): MFMA element e of lane
+//       group lk is k = 4 lk + e (e < 4), 16 + 4 lk + e - 4 (e >= 4) of the
+//       step, a permutation of its 32 k that the staged skinny slice follows
+//       (so that four lanes read 64 contiguous bytes of a row per
+//       instruction, not four 16-byte pieces 32 bytes apart).  AVEC: groups of 4 k
+//       clamped to k4 - 4 (k4 = K rounded up to 4; K % 4 == 0 or lda >= k4),
+//       elements at k >= K of the group that crosses K set to zero.
+//   TN: v[q] = row k0 + 8 lk + q, columns t0 + 4 li .. + 3 (AVEC: the group
+//       clamped to mclamp - 4 as for BF16); rows past K read row K - 1.
+// Values at k >= K meet zero skinny rows, clamped columns feed outputs that
+// are never stored.
 template <bool TN, bool AVEC>
+__device__ __forceinline__ void load_slot_f32(const float *A, int64_t lda, int64_t M, int64_t K,
+                                              int64_t t0, int li, int lk, int64_t k0,
+                                              ASlot<TN, true> &s, int64_t mclamp) {
+  if constexpr (!TN) {
+    constexpr int RG = B16Cfg<false, true>::RG, KS = B16Cfg<false, true>::SL / 32;
+    const int64_t k4 = (K + 3) & ~int64_t(3);
+#pragma unroll
+    for (int rt = 0; rt < RG; ++rt) {
+      const int64_t row = b16_clamp(t0 + 16 * rt + li, M - 1);
+      const float *p = A + row * lda;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          // lanes lk = 0..3 of a row read 64 contiguous bytes per instruction
+          const int64_t kk = k0 + 32 * ks + 16 * h + 4 * lk;
+          float4 v;
+          if (AVEC) {
+            const int64_t g = b16_clamp(kk, k4 - 4);
+            v = *reinterpret_cast<const float4 *>(p + g);
+            if ((K & 3) != 0 && g + 4 > K) {
+              const int64_t nv = K - g;            // 1 .. 3 valid elements
+              v.y = nv > 1 ? v.y : 0.0f;
+              v.z = nv > 2 ? v.z : 0.0f;
+              v.w = 0.0f;
+            }
+          } else {
+            v = make_float4(p[b16_clamp(kk, K - 1)], p[b16_clamp(kk + 1, K - 1)],
+                            p[b16_clamp(kk + 2, K - 1)], p[b16_clamp(kk + 3, K - 1)]);
+          }
+          s.v[(rt * KS + ks) * 2 + h] = v;
+        }
+    }
+  } else {
+    const int64_t c = t0 + 4 * li;
+    const int64_t cc = AVEC ? b16_clamp(c, mclamp - 4) : c;
+    const float *pc = A + cc;
+    const float *plast = pc + (K - 1) * lda;
+    const float *p0 = pc + k0 * lda + 8 * lk * lda;
+    const int64_t r0 = k0 + 8 * lk;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float *p = (r0 + q < K) ? p0 + q * lda : plast;
+      if (AVEC) {
+        s.v[q] = *reinterpret_cast<const float4 *>(p);
+      } else {
+        s.v[q] = make_float4(p[b16_clamp(c, M - 1) - c], p[b16_clamp(c + 1, M - 1) - c],
+                             p[b16_clamp(c + 2, M - 1) - c], p[b16_clamp(c + 3, M - 1) - c]);
+      }
+    }
+  }
+}
+
+// The MFMA operand of 8 FP32 values of A as three BF16 planes (split_pair).
+__device__ __forceinline__ void split8(const float (&e)[8], u32x4 &hi, u32x4 &mid, u32x4 &lo) {
+  uint32_t h[4], m[4], l[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) split_pair(e[2 * j], e[2 * j + 1], h[j], m[j], l[j]);
+  hi = u32x4{h[0], h[1], h[2], h[3]};
+  mid = u32x4{m[0], m[1], m[2], m[3]};
+  lo = u32x4{l[0], l[1], l[2], l[3]};
+}
+
+// One 32-deep slice with FP32 A: both operands split in three, six of the nine
+// products (hi hi, hi mid, mid hi, mid mid, hi lo, lo hi).  The three left out
+// (mid lo, lo mid, lo lo) are below 2^-23 of |a x| together (|mid| <= 2^-8,
+// |lo| <= 2^-16 of either operand) and of either sign: about one FP32
+// rounding of the product.
+template <bool TN> constexpr int kAccF32 = 4 * B16Cfg<TN, true>::RG;
+
+template <bool TN>
+__device__ __forceinline__ void mma_slice_f32(floatx4 (&acc)[kAccF32<TN>], const ASlot<TN, true> &s,
+                                              const uint16_t *xs, int li, int lk) {
+  using Lds = B16Lds<TN, true>;
+  constexpr int RG = B16Cfg<TN, true>::RG, KS = B16Cfg<TN, true>::SL / 32;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const uint16_t *xb = xs + li * Lds::CS + 32 * ks + 8 * lk;
+    u32x4 b[3][4];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+        b[p][ct] = *reinterpret_cast<const u32x4 *>(xb + p * Lds::PLANE + 16 * ct * Lds::CS);
+#pragma unroll
+    for (int x = 0; x < RG; ++x) {
+      float e[8];
+      if constexpr (TN) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float4 &r = s.v[q];
+          e[q] = x == 0 ? r.x : (x == 1 ? r.y : (x == 2 ? r.z : r.w));
+        }
+      } else {
+        const float4 &u = s.v[(x * KS + ks) * 2], &w = s.v[(x * KS + ks) * 2 + 1];
+        e[0] = u.x; e[1] = u.y; e[2] = u.z; e[3] = u.w;
+        e[4] = w.x; e[5] = w.y; e[6] = w.z; e[7] = w.w;
+      }
+      u32x4 ah, am, al;
+      split8(e, ah, am, al);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(ah, b[0][ct], acc[x * 4 + ct]);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(ah, b[1][ct], acc[x * 4 + ct]);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(am, b[0][ct], acc[x * 4 + ct]);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(am, b[1][ct], acc[x * 4 + ct]);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(ah, b[2][ct], acc[x * 4 + ct]);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(al, b[0][ct], acc[x * 4 + ct]);
+    }
+  }
+}
+
+// F32: A holds FP32 values (split in registers), else BF16 bit patterns.
+template <bool TN, bool AVEC, bool F32>
 __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
-    const uint16_t *A, int64_t lda, const float *xt, int64_t kp, float *__restrict__ C, int64_t ldc,
+    const void *Av, int64_t lda, const float *xt, int64_t kp, float *__restrict__ C, int64_t ldc,
     int64_t M, int64_t N, int64_t K, int64_t kps, int64_t tiles, int64_t total, float alpha,
     float beta, float *__restrict__ part, int64_t mclamp) {
-  using Cfg = B16Cfg<TN>;
-  using Lds = B16Lds<TN>;
+  using Cfg = B16Cfg<TN, F32>;
+  using Lds = B16Lds<TN, F32>;
+  constexpr int G = kGroup<TN, F32>;
   constexpr int SL = Cfg::SL, RING = Cfg::RING, NBUF = Cfg::NBUF, XL = Lds::XL;
   __shared__ __attribute__((aligned(16))) uint16_t xs[NBUF][Lds::STAGE];
   const int tid = threadIdx.x;
@@ -279,20 +460,21 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
   const int li = lane & 15, lk = lane >> 4;
   const int64_t L = b16_xcd_remap(blockIdx.x, total);
   const int64_t tile = L % tiles, split = L / tiles;
-  const int64_t t0 = tile * kB16Rows + 64 * wave;
+  constexpr int RG = Cfg::RG;
+  const int64_t t0 = tile * kWgRows<TN, F32> + 16 * RG * wave;
   const int64_t kb = split * kps;
   const int64_t ke = (kb + kps < K) ? kb + kps : K;
-  // slices of this split, a multiple of RING (kps is a multiple of kKGroup;
-  // slices past K meet zero skinny rows)
-  const int64_t nsl = ((ke - kb + kKGroup - 1) / kKGroup) * RING;
+  // slices of this split, a multiple of RING (kps is a multiple of kKGroup, a
+  // multiple of G = SL RING; slices past K meet zero skinny rows)
+  const int64_t nsl = ((ke - kb + G - 1) / G) * RING;
   const int sc = tid >> 3, kq = tid & 7;
   const float *xsrc = xt + sc * kp + kb + 4 * XL * kq;
 
-  floatx4 acc[16];
+  floatx4 acc[4 * RG];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < 4 * RG; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  ASlot<TN> ar[RING];
+  ASlot<TN, F32> ar[RING];
   float4 xr[RING][XL];
   // Every slice's loads are issued in one fixed order (skinny pieces, then A),
   // in the prologue as in the loop: the wait counts the compiler derives from
@@ -304,13 +486,18 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
     for (int g = 0; g < XL; ++g) xr[slot][g] = *reinterpret_cast<const float4 *>(xsrc + sl * SL + 4 * g);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
-    load_slot<TN, AVEC>(A, lda, M, K, t0, li, lk, kb + sl * SL, ar[slot], mclamp);
+    if constexpr (F32)
+      load_slot_f32<TN, AVEC>(static_cast<const float *>(Av), lda, M, K, t0, li, lk, kb + sl * SL,
+                              ar[slot], mclamp);
+    else
+      load_slot<TN, AVEC>(static_cast<const uint16_t *>(Av), lda, M, K, t0, li, lk, kb + sl * SL,
+                          ar[slot], mclamp);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
   };
 #pragma unroll
   for (int d = 0; d < RING; ++d) issue(d, d);
-  stage_skinny<TN>(xs[0], sc, kq, xr[0]);
+  stage_skinny<TN, F32>(xs[0], sc, kq, xr[0]);
 
   for (int64_t s0 = 0; s0 < nsl; s0 += RING) {
 #pragma unroll
@@ -319,9 +506,10 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
       const int buf = d % NBUF;
       __syncthreads();                 // slice s0 + d staged; slice s0 + d - 1 consumed
       __builtin_amdgcn_sched_barrier(0);
-      mma_slice_bf16<TN>(acc, ar[d], xs[buf], li, lk);
+      if constexpr (F32) mma_slice_f32<TN>(acc, ar[d], xs[buf], li, lk);
+      else mma_slice_bf16<TN>(acc, ar[d], xs[buf], li, lk);
       __builtin_amdgcn_sched_barrier(0);
-      stage_skinny<TN>(xs[(d + 1) % NBUF], sc, kq, xr[(d + 1) % RING]);
+      stage_skinny<TN, F32>(xs[(d + 1) % NBUF], sc, kq, xr[(d + 1) % RING]);
       issue(s0 + d + RING, d);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -330,7 +518,7 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
   float *dst = part ? part + split * M * kBld : C;
   const int64_t ld = part ? kBld : ldc;
 #pragma unroll
-  for (int g = 0; g < 4; ++g)
+  for (int g = 0; g < RG; ++g)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
@@ -349,20 +537,23 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
 }
 
 // ------------------------------------------------------------------ host
-static int64_t bf16_slots(int is_tn) {
+static int64_t bf16_slots(int is_tn, bool f32) {
   static std::mutex mu;
-  static std::map<std::pair<int, int>, int64_t> cache;
+  static std::map<std::tuple<int, int, int>, int64_t> cache;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
   std::lock_guard<std::mutex> lock(mu);
-  const auto key = std::make_pair(dev, is_tn);
+  const auto key = std::make_tuple(dev, is_tn, f32 ? 1 : 0);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
   int cus = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
     cus = 256;
-  const void *fn = is_tn ? reinterpret_cast<const void *>(&gemm_bf16_kernel<true, true>)
-                         : reinterpret_cast<const void *>(&gemm_bf16_kernel<false, true>);
+  const void *fn =
+      f32 ? (is_tn ? reinterpret_cast<const void *>(&gemm_bf16_kernel<true, true, true>)
+                   : reinterpret_cast<const void *>(&gemm_bf16_kernel<false, true, true>))
+          : (is_tn ? reinterpret_cast<const void *>(&gemm_bf16_kernel<true, true, false>)
+                   : reinterpret_cast<const void *>(&gemm_bf16_kernel<false, true, false>));
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kB16Threads, 0) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
@@ -376,10 +567,11 @@ int64_t bf16_padded_k(int64_t K) { return (K + kKGroup - 1) / kKGroup * kKGroup;
 // K splits: as for the FP32 kernels (rounds of resident workgroups x split
 // length, partial tiles cheap next to A), splits in whole groups of kKGroup
 // (so a short K still spreads over several workgroups per 512-row tile).
-int gemm_bf16_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split) {
+static int choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split, bool f32) {
   if (M < 1 || K < 1) return 1;
-  const int64_t tiles = (M + kB16Rows - 1) / kB16Rows;
-  const int64_t slots = bf16_slots(is_tn);
+  const int64_t rows = f32 ? (is_tn ? kWgRows<true, true> : kWgRows<false, true>) : kB16Rows;
+  const int64_t tiles = (M + rows - 1) / rows;
+  const int64_t slots = bf16_slots(is_tn, f32);
   int64_t smax = K / kKGroup;
   if (smax > max_split) smax = max_split;
   if (smax > 64) smax = 64;
@@ -396,10 +588,18 @@ int gemm_bf16_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split) 
   return best;
 }
 
+int gemm_bf16_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split) {
+  return choose_ksplit(M, K, is_tn, max_split, false);
+}
+
+int gemm_f32s_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split) {
+  return choose_ksplit(M, K, is_tn, max_split, true);
+}
+
 size_t bf16_pack_bytes(int64_t K) { return (size_t)bf16_padded_k(K) * kBld * sizeof(float); }
 
-template <bool TN>
-static int launch_bf16(const uint16_t *A, int64_t lda, const float *X, int64_t ldx, float *C,
+template <bool TN, bool F32>
+static int launch_bf16(const void *A, int64_t lda, const float *X, int64_t ldx, float *C,
                        int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
                        int ksplit, float *part, float *xt, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0) return 1;
@@ -411,35 +611,53 @@ static int launch_bf16(const uint16_t *A, int64_t lda, const float *X, int64_t l
   kps = (kps + kKGroup - 1) / kKGroup * kKGroup;
   const int nsp = (int)((K + kps - 1) / kps);
   float *p = (nsp > 1) ? part : nullptr;
-  const int64_t tiles = (M + kB16Rows - 1) / kB16Rows;
+  const int64_t tiles = (M + kWgRows<TN, F32> - 1) / kWgRows<TN, F32>;
   const int64_t total = tiles * nsp;
   const uintptr_t ad = reinterpret_cast<uintptr_t>(A);
-  // vector loads: 8-byte (TN) / 16-byte (NN) aligned rows whose groups of 4
-  // columns (TN) / 8 k (NN) stay inside the row or its padding up to lda
-  const int64_t m4 = (M + 3) / 4 * 4, k8 = (K + 7) / 8 * 8;
-  const bool avec = TN ? (M >= 4 && lda % 4 == 0 && (ad & 7) == 0 && (M % 4 == 0 || lda >= m4))
-                       : (K >= 8 && lda % 8 == 0 && (ad & 15) == 0 && (K % 8 == 0 || lda >= k8));
+  // vector loads: aligned rows whose groups of 4 columns (TN: 8 bytes BF16,
+  // 16 bytes FP32) / of 8 (BF16) or 4 (FP32) k (NN) stay inside the row or its
+  // padding up to lda
+  const int64_t m4 = (M + 3) / 4 * 4, k8 = (K + 7) / 8 * 8, k4 = (K + 3) / 4 * 4;
+  bool avec;
+  if (F32)
+    avec = TN ? (M >= 4 && lda % 4 == 0 && (ad & 15) == 0 && (M % 4 == 0 || lda >= m4))
+              : (K >= 4 && lda % 4 == 0 && (ad & 15) == 0 && (K % 4 == 0 || lda >= k4));
+  else
+    avec = TN ? (M >= 4 && lda % 4 == 0 && (ad & 7) == 0 && (M % 4 == 0 || lda >= m4))
+              : (K >= 8 && lda % 8 == 0 && (ad & 15) == 0 && (K % 8 == 0 || lda >= k8));
   const int64_t mclamp = (TN && M % 4 != 0) ? m4 : M;
   dim3 grid((unsigned)total), blk(kB16Threads);
   if (avec)
-    hipLaunchKernelGGL((gemm_bf16_kernel<TN, true>), grid, blk, 0, st, A, lda, xt, kp, C, ldc, M, N,
-                       K, kps, tiles, total, alpha, beta, p, mclamp);
+    hipLaunchKernelGGL((gemm_bf16_kernel<TN, true, F32>), grid, blk, 0, st, A, lda, xt, kp, C, ldc,
+                       M, N, K, kps, tiles, total, alpha, beta, p, mclamp);
   else
-    hipLaunchKernelGGL((gemm_bf16_kernel<TN, false>), grid, blk, 0, st, A, lda, xt, kp, C, ldc, M,
-                       N, K, kps, tiles, total, alpha, beta, p, mclamp);
+    hipLaunchKernelGGL((gemm_bf16_kernel<TN, false, F32>), grid, blk, 0, st, A, lda, xt, kp, C, ldc,
+                       M, N, K, kps, tiles, total, alpha, beta, p, mclamp);
   return nsp;
 }
 
 int launch_gemm_bf16_nn_main(const uint16_t *A, int64_t lda, const float *X, int64_t ldx, float *C,
                              int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
                              int ksplit, float *part, float *xt, hipStream_t st) {
-  return launch_bf16<false>(A, lda, X, ldx, C, ldc, M, N, K, alpha, beta, ksplit, part, xt, st);
+  return launch_bf16<false, false>(A, lda, X, ldx, C, ldc, M, N, K, alpha, beta, ksplit, part, xt, st);
 }
 
 int launch_gemm_bf16_tn_main(const uint16_t *A, int64_t lda, const float *Y, int64_t ldy, float *C,
                              int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
                              int ksplit, float *part, float *xt, hipStream_t st) {
-  return launch_bf16<true>(A, lda, Y, ldy, C, ldc, M, N, K, alpha, beta, ksplit, part, xt, st);
+  return launch_bf16<true, false>(A, lda, Y, ldy, C, ldc, M, N, K, alpha, beta, ksplit, part, xt, st);
+}
+
+int launch_gemm_f32s_nn_main(const float *A, int64_t lda, const float *X, int64_t ldx, float *C,
+                             int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
+                             int ksplit, float *part, float *xt, hipStream_t st) {
+  return launch_bf16<false, true>(A, lda, X, ldx, C, ldc, M, N, K, alpha, beta, ksplit, part, xt, st);
+}
+
+int launch_gemm_f32s_tn_main(const float *A, int64_t lda, const float *Y, int64_t ldy, float *C,
+                             int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
+                             int ksplit, float *part, float *xt, hipStream_t st) {
+  return launch_bf16<true, true>(A, lda, Y, ldy, C, ldc, M, N, K, alpha, beta, ksplit, part, xt, st);
 }
 
 }  // namespace farpca_int

@@ -119,6 +119,17 @@ int launch_gemm_bf16_nn_main(const uint16_t *A, int64_t lda, const float *X, int
 int launch_gemm_bf16_tn_main(const uint16_t *A, int64_t lda, const float *Y, int64_t ldy, float *C,
                              int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
                              int ksplit, float *part, float *xt, hipStream_t st);
+// The same products with FP32 A on the BF16 matrix cores: A is split exactly
+// into three BF16 terms in registers as well, and six of the nine term
+// products are formed (the three left out are below 2^-23 of |a x| and of
+// either sign).
+int gemm_f32s_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split);
+int launch_gemm_f32s_nn_main(const float *A, int64_t lda, const float *X, int64_t ldx, float *C,
+                             int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
+                             int ksplit, float *part, float *xt, hipStream_t st);
+int launch_gemm_f32s_tn_main(const float *A, int64_t lda, const float *Y, int64_t ldy, float *C,
+                             int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
+                             int ksplit, float *part, float *xt, hipStream_t st);
 
 // ---- dense64.hip (FP64 small-matrix work)
 // Gram G[b x b] (FP64) = X^T X for X (K x b, FP32, ldx; columns >= b ignored);

@@ -2,7 +2,7 @@
 
 The names follow the C-ABI in include/farpca.h: farpca_plan, farpca_run,
 farpca_free, farpca_omega, farpca_sketch, farpca_gemm_nn, farpca_gemm_tn,
-farpca_gemm_bf16_nn, farpca_gemm_bf16_tn, farpca_eig.  Device buffers are torch tensors on the current HIP device;
+farpca_gemm_bf16_nn, farpca_gemm_bf16_tn, farpca_gemm_f32s_nn, farpca_gemm_f32s_tn, farpca_eig.  Device buffers are torch tensors on the current HIP device;
 every step of the method runs in the library's kernels.  ``solve`` is a
 convenience wrapper that allocates the caller-owned buffers the C-ABI asks for.
 
@@ -29,11 +29,12 @@ EXPORTED = ["farpca_plan", "farpca_run", "farpca_run_static", "farpca_begin", "f
             "farpca_grow", "farpca_final_bytes", "farpca_finish_final", "farpca_finish", "farpca_free", "farpca_status_str", "farpca_omega",
             "farpca_sketch", "farpca_gemm_scratch_bytes", "farpca_gemm_nn", "farpca_gemm_tn",
             "farpca_gemm_bf16_scratch_bytes", "farpca_gemm_bf16_nn", "farpca_gemm_bf16_tn",
+            "farpca_gemm_f32s_nn", "farpca_gemm_f32s_tn",
             "farpca_eig_scratch_bytes", "farpca_eig", "farpca_profile_enable", "farpca_profile_get",
             "farpca_request_footprint", "farpca_server_create", "farpca_server_submit",
             "farpca_server_poll", "farpca_server_release", "farpca_server_fetch",
             "farpca_server_stats", "farpca_server_memory", "farpca_server_destroy"]
-PROF_CLASSES = {"sketch": 0, "gemm_tn": 1, "gemm_nn": 2, "eig": 3}
+PROF_CLASSES = {"sketch": 0, "gemm_tn": 1, "gemm_nn": 2, "eig": 3, "gemm_c": 4}
 
 
 class FarpcaParams(ctypes.Structure):
@@ -77,6 +78,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise FarpcaError(f"{path} not found: build it with `python -c 'import __graft_entry__ as g; "
                           "g.build()'` (hipcc, gfx950)")
+    # torch brings its own HIP runtime (same soname, found by name only once it is
+    # loaded): load it first so that this library binds to it instead of loading
+    # a second runtime, whose streams and pointers torch's would not know.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
     lib.farpca_plan.argtypes = [ctypes.POINTER(FarpcaParams), ctypes.POINTER(vp),
@@ -118,7 +123,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.farpca_gemm_scratch_bytes.restype = sz
     lib.farpca_gemm_bf16_scratch_bytes.argtypes = [i64, i64]
     lib.farpca_gemm_bf16_scratch_bytes.restype = sz
-    for name in ("farpca_gemm_nn", "farpca_gemm_tn", "farpca_gemm_bf16_nn", "farpca_gemm_bf16_tn"):
+    for name in ("farpca_gemm_nn", "farpca_gemm_tn", "farpca_gemm_bf16_nn", "farpca_gemm_bf16_tn",
+                 "farpca_gemm_f32s_nn", "farpca_gemm_f32s_tn"):
         f = getattr(lib, name)
         f.argtypes = [vp, i64, vp, i64, vp, i64, i64, i64, i64, vp, vp]
         f.restype = ctypes.c_int
@@ -353,6 +359,23 @@ def farpca_gemm_bf16_tn(A, Y, C, M, N, K, scratch, lda=None, ldy=None, ldc=None,
     return _check(lib.farpca_gemm_bf16_tn(_ptr(A), lda or A.stride(0), _ptr(Y), ldy or Y.stride(0),
                                           _ptr(C), ldc or C.stride(0), M, N, K, _ptr(scratch),
                                           _stream(stream)), "farpca_gemm_bf16_tn")
+
+
+def farpca_gemm_f32s_nn(A, X, C, M, N, K, scratch, lda=None, ldx=None, ldc=None,
+                        stream=None) -> int:
+    """A, X, C: FP32; scratch: farpca_gemm_bf16_scratch_bytes(M, K) bytes."""
+    lib = load_library()
+    return _check(lib.farpca_gemm_f32s_nn(_ptr(A), lda or A.stride(0), _ptr(X), ldx or X.stride(0),
+                                          _ptr(C), ldc or C.stride(0), M, N, K, _ptr(scratch),
+                                          _stream(stream)), "farpca_gemm_f32s_nn")
+
+
+def farpca_gemm_f32s_tn(A, Y, C, M, N, K, scratch, lda=None, ldy=None, ldc=None,
+                        stream=None) -> int:
+    lib = load_library()
+    return _check(lib.farpca_gemm_f32s_tn(_ptr(A), lda or A.stride(0), _ptr(Y), ldy or Y.stride(0),
+                                          _ptr(C), ldc or C.stride(0), M, N, K, _ptr(scratch),
+                                          _stream(stream)), "farpca_gemm_f32s_tn")
 
 
 def farpca_eig_scratch_bytes(l: int) -> int:

@@ -381,6 +381,99 @@ def test_gemm_bf16_float_error_bound(fp, M, K, N, kind):
     assert np.all(np.abs(got - ref) <= 6 * U32 * math.sqrt(K) * absref)
 
 
+# ------------------------------------------- FP32 A on the BF16 matrix cores
+def f32s_gemm(fp, kind, a, x, M, N, K, lda=None):
+    import torch
+    C = torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")
+    scratch = bf16_scratch(fp, M, K)
+    A = a if isinstance(a, torch.Tensor) else dev(a)
+    if kind == "nn":
+        fp.farpca_gemm_f32s_nn(A, dev(x), C, M, N, K, scratch, lda=lda)
+    else:
+        fp.farpca_gemm_f32s_tn(A, dev(x), C, M, N, K, scratch, lda=lda)
+    return host(C)
+
+
+# NN vector loads need K % 4 == 0, TN vector loads M % 4 == 0: both paths occur
+@pytest.mark.parametrize("M,K,N", BF16_GEMM_SHAPES)
+@pytest.mark.parametrize("kind", ["nn", "tn"])
+def test_gemm_f32s_integer_exact(fp, M, K, N, kind):
+    # |a| <= 255 (one BF16 term), X up to 2^11 (two terms): every term product
+    # that is formed is exact and the left-out ones are zero; |sums| < 2^24
+    rng = np.random.default_rng(M * 13 + K)
+    xmax = max(1, min(2048, (2 ** 24 - 1) // (255 * max(K, 1))))
+    shape = (M, K) if kind == "nn" else (K, M)
+    a = rng.integers(-255, 256, size=shape).astype(np.float32)
+    x = rng.integers(-xmax, xmax + 1, size=(K, N)).astype(np.float32)
+    print(f"gemm f32s {kind} M={M} K={K} N={N}", flush=True)
+    got = f32s_gemm(fp, kind, a, x, M, N, K)
+    a64, x64 = a.astype(np.float64), x.astype(np.float64)
+    ref = (a64 @ x64) if kind == "nn" else (a64.T @ x64)
+    assert np.array_equal(got, ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("M,K,N", [(1000, 777, 50), (1003, 2430, 64), (337, 345, 64), (9001, 3001, 33)])
+@pytest.mark.parametrize("kind", ["nn", "tn"])
+def test_gemm_f32s_padded_rows(fp, M, K, N, kind):
+    # rows padded to a multiple of 4 floats (the vector paths for any width),
+    # NaN in the padding: it must reach no stored output
+    import torch
+    rng = np.random.default_rng(M * 7 + K)
+    rows, cols = (M, K) if kind == "nn" else (K, M)
+    a = rng.integers(-255, 256, size=(rows, cols)).astype(np.float32)
+    xmax = max(1, min(2048, (2 ** 24 - 1) // (255 * K)))
+    x = rng.integers(-xmax, xmax + 1, size=(K, N)).astype(np.float32)
+    ld = (cols + 3) // 4 * 4
+    buf = np.full((rows, ld), np.nan, dtype=np.float32)
+    buf[:, :cols] = a
+    A = torch.from_numpy(buf).cuda()
+    print(f"gemm f32s {kind} M={M} K={K} N={N} lda={ld}", flush=True)
+    got = f32s_gemm(fp, kind, A, x, M, N, K, lda=ld)
+    a64, x64 = a.astype(np.float64), x.astype(np.float64)
+    ref = (a64 @ x64) if kind == "nn" else (a64.T @ x64)
+    assert np.array_equal(got, ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("M,K,N", [(2000, 15000, 64), (15000, 2000, 64), (333, 4000, 50),
+                                   (4000, 100000, 50), (20000, 15000, 64)])
+@pytest.mark.parametrize("kind", ["nn", "tn"])
+def test_gemm_f32s_float_error_bound(fp, M, K, N, kind):
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal((M, K) if kind == "nn" else (K, M)).astype(np.float32)
+    x = rng.standard_normal((K, N)).astype(np.float32)
+    print(f"gemm f32s float {kind} M={M} K={K} N={N}", flush=True)
+    got = f32s_gemm(fp, kind, a, x, M, N, K)
+    a64, x64 = a.astype(np.float64), x.astype(np.float64)
+    if kind == "nn":
+        ref, absref = a64 @ x64, np.abs(a64) @ np.abs(x64)
+    else:
+        ref, absref = a64.T @ x64, np.abs(a64).T @ np.abs(x64)
+    # the three term products left out are below 2^-23 |a x| per product
+    # together; six FP32 accumulations per product
+    err = np.abs(got - ref)
+    assert np.all(err <= (6 * U32 * math.sqrt(6 * K) + 2.0 ** -23) * absref)
+    # and the typical error is FP32's, not BF16's
+    assert np.median(err / absref) < 4 * U32 * math.sqrt(K)
+
+
+@pytest.mark.parametrize("kind", ["nn", "tn"])
+def test_gemm_f32s_sum_of_squares_unbiased(fp, kind):
+    # the indicator subtracts sum ||C_j||^2 from ||A||^2: a one-signed error of
+    # the left-out term products (truncated splits: about 1e-7 of every
+    # product) would shift the sum of squares by about 2e-7 relative; splits
+    # rounded to nearest keep it at the level of random FP32 rounding
+    M, K, N = 3000, 20000, 64
+    rng = np.random.default_rng(11)
+    a = rng.standard_normal((M, K) if kind == "nn" else (K, M)).astype(np.float32)
+    x = rng.standard_normal((K, N)).astype(np.float32)
+    print(f"gemm f32s sum of squares {kind}", flush=True)
+    got = f32s_gemm(fp, kind, a, x, M, N, K).astype(np.float64)
+    a64, x64 = a.astype(np.float64), x.astype(np.float64)
+    ref = (a64 @ x64) if kind == "nn" else (a64.T @ x64)
+    rel = abs(np.sum(got * got) - np.sum(ref * ref)) / np.sum(ref * ref)
+    assert rel < 3e-8, rel
+
+
 @pytest.mark.parametrize("sketch,p,zeta,b,m,n", SKETCH_CASES[:6] + SKETCH_CASES[-3:])
 def test_sketch_bf16_bit_exact_integer_A(fp, sketch, p, zeta, b, m, n):
     import torch
