@@ -103,6 +103,7 @@ KERNEL_SOURCES = {
     "sketch": ["paper_2506_03859_amd/csrc/sketch.hip"],
     "gemm_tn_bf16": ["paper_2506_03859_amd/csrc/gemm_bf16.hip"],
     "gemm_tn_split": ["paper_2506_03859_amd/csrc/gemm_bf16.hip"],
+    "gemm_nn_split": ["paper_2506_03859_amd/csrc/gemm_bf16.hip"],
     "gemm_nn_bf16": ["paper_2506_03859_amd/csrc/gemm_bf16.hip"],
     "sketch_bf16": ["paper_2506_03859_amd/csrc/sketch.hip"],
 }
@@ -241,14 +242,14 @@ def kernel_probe(wl, dev, reps=3):
         scratch = buf[off:off + nb]
         gemm_tn, gemm_nn = fp.farpca_gemm_bf16_tn, fp.farpca_gemm_bf16_nn
     elif layout == "row":
-        # the solve's power-step A^T T passes on row-major FP32 A run split on
-        # the BF16 matrix cores, A G on the FP32 ones
+        # the solve's power-step A^T T and its A G passes on row-major FP32 A
+        # run split on the BF16 matrix cores
         nb = max(fp.farpca_gemm_bf16_scratch_bytes(max(m, n), max(m, n)),
                  fp.farpca_gemm_scratch_bytes(max(m, n)))
         buf = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
         off = (-buf.data_ptr()) % 256
         scratch = buf[off:off + nb]
-        gemm_tn, gemm_nn = fp.farpca_gemm_f32s_tn, fp.farpca_gemm_nn
+        gemm_tn, gemm_nn = fp.farpca_gemm_f32s_tn, fp.farpca_gemm_f32s_nn
     else:
         scratch = torch.empty(fp.farpca_gemm_scratch_bytes(max(m, n)) // 4, device=dev)
         gemm_tn, gemm_nn = fp.farpca_gemm_tn, fp.farpca_gemm_nn
@@ -716,9 +717,9 @@ def main():
     dom = max(cand, key=lambda c: cand[c][0])
     tot_ms, a_ms, cnt = cand[dom]
     layout = LAYOUTS.get(wl, "row")
-    # row-major FP32 A: the power-step A^T T products run split on the BF16
-    # matrix cores, A G and C_j^T = A^T Q_j on the FP32 ones
-    split = storage == "f32" and layout == "row" and dom == "gemm_tn"
+    # row-major FP32 A: the power-step A^T T and the A G products run split on
+    # the BF16 matrix cores, C_j^T = A^T Q_j on the FP32 ones
+    split = storage == "f32" and layout == "row" and dom in ("gemm_tn", "gemm_nn")
     pass_name = {"gemm_tn": "A^T Y", "gemm_nn": "A G", "gemm_c": "C_j^T = A^T Q_j"}.get(dom)
     if dom == "sketch":
         alg = a_bytes + 4.0 * m * b
@@ -737,7 +738,8 @@ def main():
         # 6 x 2 m n b flop of BF16 MFMA, far under its peak): 4 m n bytes of A
         # per launch against HBM
         achieved = a_bytes / (a_ms * 1e-3) / 1e9
-        kname = "gemm_bf16_kernel<true, true, true> (A^T Y, FP32 A split)"
+        kname = ("gemm_bf16_kernel<true, true, true> (A^T Y, FP32 A split)" if dom == "gemm_tn"
+                 else "gemm_f32s_nn_lds_kernel<true> (A G, FP32 A split)")
         roof = {"kernel": kname, "bound": "hbm",
                 "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBPS,

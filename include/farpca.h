@@ -111,7 +111,7 @@ typedef struct farpca_info {
                             truncation error, since A - Q Q^T A is orthogonal to range(Q)).
                             rank_out when the run did not converge or in fixed-rank use.  */
   int32_t eig_converged; /* 1 if the final eigensolver met its off-diagonal test
-                            (|k_pq| <= 1e-8 sqrt(k_pp k_qq) after the sweeps, so V is
+                            (|k_pq| <= 1e-7 sqrt(k_pp k_qq) after the sweeps, so V is
                             orthonormal to that level, or stalled below 1e-11 of it);
                             0 if it stopped at its cap of FARPCA_EIG_MAX_SWEEPS sweeps
                             (U S V^T = Q Q^T A still holds)                          */
@@ -284,7 +284,7 @@ int farpca_gemm_f32s_tn(const float *dA, int64_t lda, const float *dY, int64_t l
  * dW (l) descending, dV (l x l) eigenvectors in columns.  dWork holds
  * farpca_eig_scratch_bytes(l) bytes.  The sweeps stop once every off-diagonal
  * entry of V^T K V meets |k_pq| <= rel sqrt(|k_pp k_qq|) (rel <= 0: 1e-14; the
- * final step of farpca_run uses 1e-8) or |k_pq| <= 4e-15 max|k_ii| (the FP64
+ * final step of farpca_run uses 1e-7) or |k_pq| <= 4e-15 max|k_ii| (the FP64
  * rounding of the largest entry), or once two sweeps in a row halve neither the
  * largest ratio |k_pq| / sqrt(|k_pp k_qq|) nor the largest |k_pq| of the failing
  * entries while the ratio is below 1e-11 or the entry below 1e-12 max|k_ii|

@@ -51,19 +51,19 @@ static constexpr int kCholqrPasses = 2;
 // FP32 data and the method need)
 static constexpr double kRepeatSkip = 1e-8;
 // Final eigensolve of K = C C^T: Jacobi stops once every off-diagonal entry is
-// below 1e-8 of the geometric mean of its two diagonal entries.  The
+// below 1e-7 of the geometric mean of its two diagonal entries.  The
 // eigenvalues are then exact to FP64 rounding (their error is quadratic in the
-// off-diagonal entries); V = C^T U~ Sigma^{-1} is orthonormal to the same 1e-8,
-// and U S V^T = Q Q^T A holds for any orthogonal U~, so FP32 outputs lose
-// nothing.
-static constexpr double kFinalEigRel = 1e-8;
+// off-diagonal entries); V = C^T U~ Sigma^{-1} is orthonormal to the same 1e-7,
+// about the rounding of its FP32 entries, and U S V^T = Q Q^T A holds for any
+// orthogonal U~, so FP32 outputs lose nothing.
+static constexpr double kFinalEigRel = 1e-7;
 
 struct farpca_plan_s {
   farpca_params prm;
   bool bf16;            // A holds BF16 bit patterns (precision form)
   bool colmajor;        // A stored column-major (FARPCA_LAYOUT_COL)
   bool c64;             // C_j^T = A^T Q_j with FP64 accumulation (tol below kC64Tol)
-  bool split;           // A^T T passes on the BF16 matrix cores with both operands split (FP32 row-major A)
+  bool split;           // A-passes on the BF16 matrix cores with both operands split (FP32 row-major A)
   int b;
   int P;
   int kind;
@@ -411,10 +411,8 @@ int setup_partials(const farpca_plan_s *pl) {
 //   TN (tn true):  C (n x ncols) = A^T T, T m x ncols (ld kBld)
 // Returns the number of partial products left in the partial buffer (1: C
 // was written directly); launch_gemm_finish completes the product.  With FP32
-// row-major A a TN pass runs split on the BF16 matrix cores unless allow_split
-// is false (the FP32 matrix cores).  NN passes stay on the FP32 matrix cores:
-// split, their row pieces (a few hundred bytes of each of many rows per
-// workgroup) hold them near the same HBM rate, so they would gain nothing.
+// row-major A the pass runs split on the BF16 matrix cores unless allow_split
+// is false (the FP32 matrix cores).
 int a_pass(const farpca_plan_s *pl, const Ws &w, bool tn, const void *A, const float *X, int ncols,
            float *C, int64_t ldc, hipStream_t st, bool allow_split = true) {
   const farpca_params &q = pl->prm;
@@ -430,7 +428,7 @@ int a_pass(const farpca_plan_s *pl, const Ws &w, bool tn, const void *A, const f
                                          part, xt, st);
   }
   const float *Af = static_cast<const float *>(A);
-  if (pl->split && allow_split && tn) {
+  if (pl->split && allow_split) {
     // FP32 A on the BF16 matrix cores (exact three-term splits of both
     // operands, six term products): the pass is then bound by streaming A,
     // not by the FP32 matrix-core rate

@@ -536,6 +536,153 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
       }
 }
 
+// ------------------------------------------- FP32 A, NN, A staged in LDS
+// A G with FP32 A.  Read straight into the MFMA operand layout, a load
+// instruction covers 16 rows x 64 bytes and the pass streams A at about 3 TB/s
+// whatever the arithmetic; here each 64-deep slice of the workgroup's 256 rows
+// is read as 32 rows x 256 contiguous bytes per instruction (16 lanes per
+// row), kNlRing slices ahead in registers, stored into an LDS tile (row stride 68
+// floats: the 16-byte stores of a row and the 16-byte operand reads of 8
+// consecutive rows are bank-conflict free), and each wave takes its operands
+// (32 rows: 2 row groups of 16) from there.  The skinny slice is staged as for
+// the BF16 NN kernel (natural k order).  Two barriers per slice: the tile is
+// single-buffered (256 x 68 floats = 68 KB, plus 27 KB of skinny planes).
+constexpr int kNlRows = 256;                 // output rows per workgroup
+constexpr int kNlSl = 64;                    // k per slice
+constexpr int kNlLd = kNlSl + 4;             // floats per LDS row of the tile
+constexpr int kNlRing = 2;                   // slices in flight in registers
+static_assert(kKGroup % kNlSl == 0, "slices divide the split granularity");
+
+template <bool AVEC>
+__device__ __forceinline__ void nl_load(const float *A, int64_t lda, int64_t M, int64_t K,
+                                        int64_t r0, int64_t k0, int tid, float4 (&v)[8]) {
+  const int kq = (tid & 15) * 4;
+  const int64_t k4 = (K + 3) & ~int64_t(3);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t row = b16_clamp(r0 + 32 * q + (tid >> 4), M - 1);
+    const float *p = A + row * lda;
+    const int64_t kk = k0 + kq;
+    if (AVEC) {
+      const int64_t g = b16_clamp(kk, k4 - 4);
+      float4 x = *reinterpret_cast<const float4 *>(p + g);
+      if ((K & 3) != 0 && g + 4 > K) {
+        const int64_t nv = K - g;                // 1 .. 3 valid elements
+        x.y = nv > 1 ? x.y : 0.0f;
+        x.z = nv > 2 ? x.z : 0.0f;
+        x.w = 0.0f;
+      }
+      v[q] = x;
+    } else {
+      v[q] = make_float4(p[b16_clamp(kk, K - 1)], p[b16_clamp(kk + 1, K - 1)],
+                         p[b16_clamp(kk + 2, K - 1)], p[b16_clamp(kk + 3, K - 1)]);
+    }
+  }
+}
+
+template <bool AVEC>
+__global__ __launch_bounds__(kB16Threads) void gemm_f32s_nn_lds_kernel(
+    const float *__restrict__ A, int64_t lda, const float *xt, int64_t kp, float *__restrict__ C,
+    int64_t ldc, int64_t M, int64_t N, int64_t K, int64_t kps, int64_t tiles, int64_t total,
+    float alpha, float beta, float *__restrict__ part) {
+  using Lds = B16Lds<false, false>;                 // 64-deep skinny slices, natural k order
+  static_assert(Lds::XL == 2 && B16Cfg<false, false>::SL == kNlSl, "skinny slice layout");
+  __shared__ __attribute__((aligned(16))) float al[kNlRows * kNlLd];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[Lds::STAGE];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t L = b16_xcd_remap(blockIdx.x, total);
+  const int64_t tile = L % tiles, split = L / tiles;
+  const int64_t r0 = tile * kNlRows;
+  const int64_t kb = split * kps;
+  const int64_t ke = (kb + kps < K) ? kb + kps : K;
+  const int64_t nsl = (ke - kb + kNlSl - 1) / kNlSl;
+  const int sc = tid >> 3, kq = tid & 7;
+  const float *xsrc = xt + sc * kp + kb + 8 * kq;
+
+  floatx4 acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  constexpr int R = kNlRing;
+  float4 ar[R][8];
+  float4 xr[R][2];
+  auto issue = [&](int64_t s, int slot) {
+    const int64_t sl = s < nsl ? s : nsl - 1;      // clamped: in bounds, never used
+#pragma unroll
+    for (int g = 0; g < 2; ++g) xr[slot][g] = *reinterpret_cast<const float4 *>(xsrc + sl * kNlSl + 4 * g);
+    nl_load<AVEC>(A, lda, M, K, r0, kb + sl * kNlSl, tid, ar[slot]);
+  };
+#pragma unroll
+  for (int d = 0; d < R; ++d) issue(d, d);
+  const int wrow = 32 * wave;
+  for (int64_t s0 = 0; s0 < nsl; s0 += R) {
+#pragma unroll
+    for (int d = 0; d < R; ++d) {
+      if (s0 + d >= nsl) break;                    // uniform
+      __syncthreads();                             // slice s0 + d - 1 consumed
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        *reinterpret_cast<float4 *>(al + (32 * q + (tid >> 4)) * kNlLd + (tid & 15) * 4) = ar[d][q];
+      stage_skinny<false, false>(xs, sc, kq, xr[d]);
+      issue(s0 + d + R, d);
+      __syncthreads();                             // slice s0 + d staged
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const uint16_t *xb = xs + li * Lds::CS + 32 * ks + 8 * lk;
+        u32x4 b[3][4];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct)
+            b[p][ct] = *reinterpret_cast<const u32x4 *>(xb + p * Lds::PLANE + 16 * ct * Lds::CS);
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const float *ap = al + (wrow + 16 * x + li) * kNlLd + 32 * ks + 8 * lk;
+          const float4 u = *reinterpret_cast<const float4 *>(ap);
+          const float4 w = *reinterpret_cast<const float4 *>(ap + 4);
+          const float e[8] = {u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
+          u32x4 ah, am, alo;
+          split8(e, ah, am, alo);
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(ah, b[0][ct], acc[x * 4 + ct]);
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(ah, b[1][ct], acc[x * 4 + ct]);
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(am, b[0][ct], acc[x * 4 + ct]);
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(am, b[1][ct], acc[x * 4 + ct]);
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(ah, b[2][ct], acc[x * 4 + ct]);
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(alo, b[0][ct], acc[x * 4 + ct]);
+        }
+      }
+    }
+  }
+
+  float *dst = part ? part + split * M * kBld : C;
+  const int64_t ld = part ? kBld : ldc;
+#pragma unroll
+  for (int g = 0; g < 2; ++g)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + wrow + 16 * g + 4 * lk + v;
+        const int64_t col = 16 * ct + li;
+        if (row < M && col < N) {
+          float r = acc[g * 4 + ct][v];
+          if (!part) {
+            r *= alpha;
+            if (beta != 0.0f) r += beta * dst[row * ld + col];
+          }
+          dst[row * ld + col] = r;
+        }
+      }
+}
+
 // ------------------------------------------------------------------ host
 static int64_t bf16_slots(int is_tn, bool f32) {
   static std::mutex mu;
@@ -551,7 +698,7 @@ static int64_t bf16_slots(int is_tn, bool f32) {
     cus = 256;
   const void *fn =
       f32 ? (is_tn ? reinterpret_cast<const void *>(&gemm_bf16_kernel<true, true, true>)
-                   : reinterpret_cast<const void *>(&gemm_bf16_kernel<false, true, true>))
+                   : reinterpret_cast<const void *>(&gemm_f32s_nn_lds_kernel<true>))
           : (is_tn ? reinterpret_cast<const void *>(&gemm_bf16_kernel<true, true, false>)
                    : reinterpret_cast<const void *>(&gemm_bf16_kernel<false, true, false>));
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kB16Threads, 0) != hipSuccess ||
@@ -627,12 +774,22 @@ static int launch_bf16(const void *A, int64_t lda, const float *X, int64_t ldx, 
               : (K >= 8 && lda % 8 == 0 && (ad & 15) == 0 && (K % 8 == 0 || lda >= k8));
   const int64_t mclamp = (TN && M % 4 != 0) ? m4 : M;
   dim3 grid((unsigned)total), blk(kB16Threads);
-  if (avec)
-    hipLaunchKernelGGL((gemm_bf16_kernel<TN, true, F32>), grid, blk, 0, st, A, lda, xt, kp, C, ldc,
-                       M, N, K, kps, tiles, total, alpha, beta, p, mclamp);
-  else
-    hipLaunchKernelGGL((gemm_bf16_kernel<TN, false, F32>), grid, blk, 0, st, A, lda, xt, kp, C, ldc,
-                       M, N, K, kps, tiles, total, alpha, beta, p, mclamp);
+  if constexpr (F32 && !TN) {
+    const float *Af = static_cast<const float *>(A);
+    if (avec)
+      hipLaunchKernelGGL((gemm_f32s_nn_lds_kernel<true>), grid, blk, 0, st, Af, lda, xt, kp, C, ldc,
+                         M, N, K, kps, tiles, total, alpha, beta, p);
+    else
+      hipLaunchKernelGGL((gemm_f32s_nn_lds_kernel<false>), grid, blk, 0, st, Af, lda, xt, kp, C, ldc,
+                         M, N, K, kps, tiles, total, alpha, beta, p);
+  } else {
+    if (avec)
+      hipLaunchKernelGGL((gemm_bf16_kernel<TN, true, F32>), grid, blk, 0, st, A, lda, xt, kp, C, ldc,
+                         M, N, K, kps, tiles, total, alpha, beta, p, mclamp);
+    else
+      hipLaunchKernelGGL((gemm_bf16_kernel<TN, false, F32>), grid, blk, 0, st, A, lda, xt, kp, C, ldc,
+                         M, N, K, kps, tiles, total, alpha, beta, p, mclamp);
+  }
   return nsp;
 }
 
