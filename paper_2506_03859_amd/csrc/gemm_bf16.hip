@@ -41,16 +41,15 @@
 // Rows / columns outside the matrix are read at clamped addresses (finite
 // values that meet zero skinny entries or feed outputs that are never stored).
 //
-// FP32 A (the same kernel, F32 = true).  The FP32 A-passes are bound by the
-// FP32 matrix-core rate (157 TFLOP/s: 2 m n b flop per 4 m n bytes needs 20
-// TB/s of A at b = 64), the BF16 matrix cores are 16 times faster: A is split
-// in registers into three BF16 terms as well and six term products are formed,
-// 6 x 2 m n b BF16 flop, well under the time it takes to stream A.  Each lane
-// holds FP32 values (16 bytes per load) in the same operand positions as the
-// BF16 layout: TN reads 16 bytes (4 columns) of each of its 8 rows, 256
-// contiguous bytes per row and instruction; NN holds 2 row groups per wave
-// (32 rows, 256 per workgroup) with 64-deep slices, 256 contiguous bytes per
-// row and slice.
+// FP32 A.  The FP32 A-passes are bound by the FP32 matrix-core rate (157
+// TFLOP/s: 2 m n b flop per 4 m n bytes needs 20 TB/s of A at b = 64), the
+// BF16 matrix cores are 16 times faster: A is split in registers into three
+// BF16 terms as well and six term products are formed, 6 x 2 m n b BF16 flop,
+// well under the time it takes to stream A.  TN runs in the same kernel
+// (F32 = true): each lane holds FP32 values (16 bytes per load) in the
+// operand positions of the BF16 layout, 16 bytes (4 columns) of each of its 8
+// rows, 256 contiguous bytes per row and instruction.  NN has a kernel of its
+// own that stages A through LDS (gemm_f32s_nn_lds_kernel).
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -74,24 +73,17 @@ constexpr int kKGroup = 192;                  // K granularity of splits and pad
 // 128-byte line (64-byte row pieces one slice apart stream at a much lower HBM
 // rate); TN rows are read as 128-byte runs already.
 template <bool TN, bool F32> struct B16Cfg;
-// RG: 16-row groups of output rows per wave.
 template <> struct B16Cfg<true, false> {
-  static constexpr int SL = 32, RING = 6, NBUF = 2, AV = 4, RG = 4;
+  static constexpr int SL = 32, RING = 6, NBUF = 2, AV = 4;
 };
 template <> struct B16Cfg<false, false> {
-  static constexpr int SL = 64, RING = 3, NBUF = 3, AV = 8, RG = 4;
+  static constexpr int SL = 64, RING = 3, NBUF = 3, AV = 8;
 };
-// FP32 A: a slot holds 8 float4 per lane, so the ring is shallower.  TN: 4
-// columns of 8 rows, 32-deep slices.  NN: 2 row groups per wave (32 output
-// rows) and 64-deep slices, so that a slice reads 256 contiguous bytes of each
-// row (16 k of 2 rows per lane).
+// FP32 A (TN): a slot holds 8 float4 per lane (4 columns of 8 rows), so the
+// ring is shallower; 32-deep slices.
 template <> struct B16Cfg<true, true> {
-  static constexpr int SL = 32, RING = 3, NBUF = 3, AV = 8, RG = 4;
+  static constexpr int SL = 32, RING = 3, NBUF = 3, AV = 8;
 };
-template <> struct B16Cfg<false, true> {
-  static constexpr int SL = 64, RING = 3, NBUF = 3, AV = 8, RG = 2;
-};
-template <bool TN, bool F32> constexpr int kWgRows = 16 * B16Cfg<TN, F32>::RG * kB16Waves;
 template <bool TN, bool F32> struct B16Lds {
   static constexpr int CS = B16Cfg<TN, F32>::SL + 8;   // BF16 per staged column (16-byte aligned)
   static constexpr int PLANE = kBld * CS;               // BF16 per split plane
@@ -100,13 +92,11 @@ template <bool TN, bool F32> struct B16Lds {
 };
 template <bool TN, bool F32> constexpr int kGroup = B16Cfg<TN, F32>::SL * B16Cfg<TN, F32>::RING;
 static_assert(kGroup<true, false> == kKGroup && kGroup<false, false> == kKGroup, "BF16 groups");
-static_assert(kKGroup % kGroup<true, true> == 0 && kKGroup % kGroup<false, true> == 0,
-              "FP32 groups divide the split granularity");
+static_assert(kKGroup % kGroup<true, true> == 0, "FP32 groups divide the split granularity");
 static_assert(kB16Threads == kBld * 8, "eight column pieces per skinny column");
 static_assert(B16Cfg<true, false>::RING % B16Cfg<true, false>::NBUF == 0 &&
                   B16Cfg<false, false>::RING % B16Cfg<false, false>::NBUF == 0 &&
-                  B16Cfg<true, true>::RING % B16Cfg<true, true>::NBUF == 0 &&
-                  B16Cfg<false, true>::RING % B16Cfg<false, true>::NBUF == 0,
+                  B16Cfg<true, true>::RING % B16Cfg<true, true>::NBUF == 0,
               "static LDS buffer of every unrolled step");
 
 __device__ __forceinline__ floatx4 mfma_bf16(u32x4 a, u32x4 b, floatx4 c) {
@@ -266,18 +256,16 @@ __device__ __forceinline__ void split_pair(float a0, float a1, uint32_t &h, uint
   l = rn_pair(s0, s1);                                        // exact
 }
 
-// FP32 A, NN: the group of 4 k at j = 4 .. 4 j + 3 of a 32-k step goes to the
-// MFMA positions of the permuted order (see load_slot_f32): 8 (j % 4) + 4 (j / 4).
+// The thread's 4 XL skinny values (k = 4 XL kq .. + 4 XL - 1 of column sc)
+// into the three BF16 planes of the staged slice.
 template <bool TN, bool F32>
 __device__ __forceinline__ void stage_skinny(uint16_t *xs, int sc, int kq,
                                              const float4 (&x)[B16Lds<TN, F32>::XL]) {
   using Lds = B16Lds<TN, F32>;
-  constexpr bool kPerm = F32 && !TN;
   uint16_t *col = xs + sc * Lds::CS;
 #pragma unroll
   for (int g = 0; g < Lds::XL; ++g) {
-    const int j = Lds::XL * kq + g;                   // 4-group of k in the slice
-    const int pos = kPerm ? 32 * (j >> 3) + 8 * (j & 3) + 4 * ((j >> 2) & 1) : 4 * j;
+    const int pos = 4 * (Lds::XL * kq + g);
     uint32_t h0, m0, l0, h1, m1, l1;
     split_pair(x[g].x, x[g].y, h0, m0, l0);
     split_pair(x[g].z, x[g].w, h1, m1, l1);
@@ -314,69 +302,27 @@ __device__ __forceinline__ void mma_slice_bf16(floatx4 (&acc)[16], const ASlot<T
 }
 
 // ------------------------------------------------------- FP32 A operand
-// FP32 A, same operand layout as the BF16 slots but 4 bytes per element.
-//   NN: v[(rt KS + ks) 2 + h] = row t0 + 16 rt + li (rt < RG), k = k0 + 32 ks +
-//       16 h + 4 lk .. + 3 (KS = SL / 32 MFMA steps): MFMA element e of lane
-//       group lk is k = 4 lk + e (e < 4), 16 + 4 lk + e - 4 (e >= 4) of the
-//       step, a permutation of its 32 k that the staged skinny slice follows
-//       (so that four lanes read 64 contiguous bytes of a row per
-//       instruction, not four 16-byte pieces 32 bytes apart).  AVEC: groups of 4 k
-//       clamped to k4 - 4 (k4 = K rounded up to 4; K % 4 == 0 or lda >= k4),
-//       elements at k >= K of the group that crosses K set to zero.
-//   TN: v[q] = row k0 + 8 lk + q, columns t0 + 4 li .. + 3 (AVEC: the group
-//       clamped to mclamp - 4 as for BF16); rows past K read row K - 1.
-// Values at k >= K meet zero skinny rows, clamped columns feed outputs that
-// are never stored.
-template <bool TN, bool AVEC>
+// FP32 A, TN: v[q] = row k0 + 8 lk + q, columns t0 + 4 li .. + 3 (AVEC: the
+// group clamped to mclamp - 4 as for BF16); rows past K read row K - 1 (they
+// meet zero skinny rows), clamped columns feed outputs that are never stored.
+template <bool AVEC>
 __device__ __forceinline__ void load_slot_f32(const float *A, int64_t lda, int64_t M, int64_t K,
                                               int64_t t0, int li, int lk, int64_t k0,
-                                              ASlot<TN, true> &s, int64_t mclamp) {
-  if constexpr (!TN) {
-    constexpr int RG = B16Cfg<false, true>::RG, KS = B16Cfg<false, true>::SL / 32;
-    const int64_t k4 = (K + 3) & ~int64_t(3);
+                                              ASlot<true, true> &s, int64_t mclamp) {
+  const int64_t c = t0 + 4 * li;
+  const int64_t cc = AVEC ? b16_clamp(c, mclamp - 4) : c;
+  const float *pc = A + cc;
+  const float *plast = pc + (K - 1) * lda;
+  const float *p0 = pc + k0 * lda + 8 * lk * lda;
+  const int64_t r0 = k0 + 8 * lk;
 #pragma unroll
-    for (int rt = 0; rt < RG; ++rt) {
-      const int64_t row = b16_clamp(t0 + 16 * rt + li, M - 1);
-      const float *p = A + row * lda;
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          // lanes lk = 0..3 of a row read 64 contiguous bytes per instruction
-          const int64_t kk = k0 + 32 * ks + 16 * h + 4 * lk;
-          float4 v;
-          if (AVEC) {
-            const int64_t g = b16_clamp(kk, k4 - 4);
-            v = *reinterpret_cast<const float4 *>(p + g);
-            if ((K & 3) != 0 && g + 4 > K) {
-              const int64_t nv = K - g;            // 1 .. 3 valid elements
-              v.y = nv > 1 ? v.y : 0.0f;
-              v.z = nv > 2 ? v.z : 0.0f;
-              v.w = 0.0f;
-            }
-          } else {
-            v = make_float4(p[b16_clamp(kk, K - 1)], p[b16_clamp(kk + 1, K - 1)],
-                            p[b16_clamp(kk + 2, K - 1)], p[b16_clamp(kk + 3, K - 1)]);
-          }
-          s.v[(rt * KS + ks) * 2 + h] = v;
-        }
-    }
-  } else {
-    const int64_t c = t0 + 4 * li;
-    const int64_t cc = AVEC ? b16_clamp(c, mclamp - 4) : c;
-    const float *pc = A + cc;
-    const float *plast = pc + (K - 1) * lda;
-    const float *p0 = pc + k0 * lda + 8 * lk * lda;
-    const int64_t r0 = k0 + 8 * lk;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const float *p = (r0 + q < K) ? p0 + q * lda : plast;
-      if (AVEC) {
-        s.v[q] = *reinterpret_cast<const float4 *>(p);
-      } else {
-        s.v[q] = make_float4(p[b16_clamp(c, M - 1) - c], p[b16_clamp(c + 1, M - 1) - c],
-                             p[b16_clamp(c + 2, M - 1) - c], p[b16_clamp(c + 3, M - 1) - c]);
-      }
+  for (int q = 0; q < 8; ++q) {
+    const float *p = (r0 + q < K) ? p0 + q * lda : plast;
+    if (AVEC) {
+      s.v[q] = *reinterpret_cast<const float4 *>(p);
+    } else {
+      s.v[q] = make_float4(p[b16_clamp(c, M - 1) - c], p[b16_clamp(c + 1, M - 1) - c],
+                           p[b16_clamp(c + 2, M - 1) - c], p[b16_clamp(c + 3, M - 1) - c]);
     }
   }
 }
@@ -396,51 +342,55 @@ __device__ __forceinline__ void split8(const float (&e)[8], u32x4 &hi, u32x4 &mi
 // (mid lo, lo mid, lo lo) are below 2^-23 of |a x| together (|mid| <= 2^-8,
 // |lo| <= 2^-16 of either operand) and of either sign: about one FP32
 // rounding of the product.
-template <bool TN> constexpr int kAccF32 = 4 * B16Cfg<TN, true>::RG;
+// The six term products of one 16-row group of A (planes ah, am, al) with the
+// four 16-column tiles of the staged skinny planes b, accumulated in acc4[ct]
+// (all column tiles of a product before the next product).
+__device__ __forceinline__ void mma_split6(floatx4 *acc4, const u32x4 &ah, const u32x4 &am,
+                                           const u32x4 &al, const u32x4 (&b)[3][4]) {
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc4[ct] = mfma_bf16(ah, b[0][ct], acc4[ct]);
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc4[ct] = mfma_bf16(ah, b[1][ct], acc4[ct]);
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc4[ct] = mfma_bf16(am, b[0][ct], acc4[ct]);
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc4[ct] = mfma_bf16(am, b[1][ct], acc4[ct]);
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc4[ct] = mfma_bf16(ah, b[2][ct], acc4[ct]);
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc4[ct] = mfma_bf16(al, b[0][ct], acc4[ct]);
+}
 
-template <bool TN>
-__device__ __forceinline__ void mma_slice_f32(floatx4 (&acc)[kAccF32<TN>], const ASlot<TN, true> &s,
+// The three skinny planes of MFMA step ks for lane (li, lk): b[p][ct].
+template <typename Lds>
+__device__ __forceinline__ void load_b_planes(const uint16_t *xs, int li, int lk, int ks,
+                                              u32x4 (&b)[3][4]) {
+  const uint16_t *xb = xs + li * Lds::CS + 32 * ks + 8 * lk;
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+      b[p][ct] = *reinterpret_cast<const u32x4 *>(xb + p * Lds::PLANE + 16 * ct * Lds::CS);
+}
+
+// One 32-deep TN slice with FP32 A: column t of the lane's 4 (output rows
+// t0 + 4 li + t) is MFMA row group t.
+__device__ __forceinline__ void mma_slice_f32(floatx4 (&acc)[16], const ASlot<true, true> &s,
                                               const uint16_t *xs, int li, int lk) {
-  using Lds = B16Lds<TN, true>;
-  constexpr int RG = B16Cfg<TN, true>::RG, KS = B16Cfg<TN, true>::SL / 32;
+  static_assert(B16Cfg<true, true>::SL == 32, "one MFMA step per slice");
+  u32x4 b[3][4];
+  load_b_planes<B16Lds<true, true>>(xs, li, lk, 0, b);
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const uint16_t *xb = xs + li * Lds::CS + 32 * ks + 8 * lk;
-    u32x4 b[3][4];
+  for (int x = 0; x < 4; ++x) {
+    float e[8];
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-        b[p][ct] = *reinterpret_cast<const u32x4 *>(xb + p * Lds::PLANE + 16 * ct * Lds::CS);
-#pragma unroll
-    for (int x = 0; x < RG; ++x) {
-      float e[8];
-      if constexpr (TN) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const float4 &r = s.v[q];
-          e[q] = x == 0 ? r.x : (x == 1 ? r.y : (x == 2 ? r.z : r.w));
-        }
-      } else {
-        const float4 &u = s.v[(x * KS + ks) * 2], &w = s.v[(x * KS + ks) * 2 + 1];
-        e[0] = u.x; e[1] = u.y; e[2] = u.z; e[3] = u.w;
-        e[4] = w.x; e[5] = w.y; e[6] = w.z; e[7] = w.w;
-      }
-      u32x4 ah, am, al;
-      split8(e, ah, am, al);
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(ah, b[0][ct], acc[x * 4 + ct]);
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(ah, b[1][ct], acc[x * 4 + ct]);
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(am, b[0][ct], acc[x * 4 + ct]);
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(am, b[1][ct], acc[x * 4 + ct]);
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(ah, b[2][ct], acc[x * 4 + ct]);
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(al, b[0][ct], acc[x * 4 + ct]);
+    for (int q = 0; q < 8; ++q) {
+      const float4 &r = s.v[q];
+      e[q] = x == 0 ? r.x : (x == 1 ? r.y : (x == 2 ? r.z : r.w));
     }
+    u32x4 ah, am, al;
+    split8(e, ah, am, al);
+    mma_split6(acc + 4 * x, ah, am, al, b);
   }
 }
 
@@ -460,8 +410,8 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
   const int li = lane & 15, lk = lane >> 4;
   const int64_t L = b16_xcd_remap(blockIdx.x, total);
   const int64_t tile = L % tiles, split = L / tiles;
-  constexpr int RG = Cfg::RG;
-  const int64_t t0 = tile * kWgRows<TN, F32> + 16 * RG * wave;
+  static_assert(TN || !F32, "FP32 A, NN: gemm_f32s_nn_lds_kernel");
+  const int64_t t0 = tile * kB16Rows + 64 * wave;
   const int64_t kb = split * kps;
   const int64_t ke = (kb + kps < K) ? kb + kps : K;
   // slices of this split, a multiple of RING (kps is a multiple of kKGroup, a
@@ -470,9 +420,9 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
   const int sc = tid >> 3, kq = tid & 7;
   const float *xsrc = xt + sc * kp + kb + 4 * XL * kq;
 
-  floatx4 acc[4 * RG];
+  floatx4 acc[16];
 #pragma unroll
-  for (int q = 0; q < 4 * RG; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < 16; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   ASlot<TN, F32> ar[RING];
   float4 xr[RING][XL];
@@ -487,7 +437,7 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (F32)
-      load_slot_f32<TN, AVEC>(static_cast<const float *>(Av), lda, M, K, t0, li, lk, kb + sl * SL,
+      load_slot_f32<AVEC>(static_cast<const float *>(Av), lda, M, K, t0, li, lk, kb + sl * SL,
                               ar[slot], mclamp);
     else
       load_slot<TN, AVEC>(static_cast<const uint16_t *>(Av), lda, M, K, t0, li, lk, kb + sl * SL,
@@ -506,7 +456,7 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
       const int buf = d % NBUF;
       __syncthreads();                 // slice s0 + d staged; slice s0 + d - 1 consumed
       __builtin_amdgcn_sched_barrier(0);
-      if constexpr (F32) mma_slice_f32<TN>(acc, ar[d], xs[buf], li, lk);
+      if constexpr (F32) mma_slice_f32(acc, ar[d], xs[buf], li, lk);
       else mma_slice_bf16<TN>(acc, ar[d], xs[buf], li, lk);
       __builtin_amdgcn_sched_barrier(0);
       stage_skinny<TN, F32>(xs[(d + 1) % NBUF], sc, kq, xr[(d + 1) % RING]);
@@ -518,7 +468,7 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
   float *dst = part ? part + split * M * kBld : C;
   const int64_t ld = part ? kBld : ldc;
 #pragma unroll
-  for (int g = 0; g < RG; ++g)
+  for (int g = 0; g < 4; ++g)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
@@ -630,13 +580,8 @@ __global__ __launch_bounds__(kB16Threads) void gemm_f32s_nn_lds_kernel(
       __syncthreads();                             // slice s0 + d staged
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        const uint16_t *xb = xs + li * Lds::CS + 32 * ks + 8 * lk;
         u32x4 b[3][4];
-#pragma unroll
-        for (int p = 0; p < 3; ++p)
-#pragma unroll
-          for (int ct = 0; ct < 4; ++ct)
-            b[p][ct] = *reinterpret_cast<const u32x4 *>(xb + p * Lds::PLANE + 16 * ct * Lds::CS);
+        load_b_planes<Lds>(xs, li, lk, ks, b);
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
           const float *ap = al + (wrow + 16 * x + li) * kNlLd + 32 * ks + 8 * lk;
@@ -645,18 +590,7 @@ __global__ __launch_bounds__(kB16Threads) void gemm_f32s_nn_lds_kernel(
           const float e[8] = {u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
           u32x4 ah, am, alo;
           split8(e, ah, am, alo);
-#pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(ah, b[0][ct], acc[x * 4 + ct]);
-#pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(ah, b[1][ct], acc[x * 4 + ct]);
-#pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(am, b[0][ct], acc[x * 4 + ct]);
-#pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(am, b[1][ct], acc[x * 4 + ct]);
-#pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(ah, b[2][ct], acc[x * 4 + ct]);
-#pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[x * 4 + ct] = mfma_bf16(alo, b[0][ct], acc[x * 4 + ct]);
+          mma_split6(acc + 4 * x, ah, am, alo, b);
         }
       }
     }
@@ -716,7 +650,7 @@ int64_t bf16_padded_k(int64_t K) { return (K + kKGroup - 1) / kKGroup * kKGroup;
 // (so a short K still spreads over several workgroups per 512-row tile).
 static int choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split, bool f32) {
   if (M < 1 || K < 1) return 1;
-  const int64_t rows = f32 ? (is_tn ? kWgRows<true, true> : kWgRows<false, true>) : kB16Rows;
+  const int64_t rows = (f32 && !is_tn) ? kNlRows : kB16Rows;
   const int64_t tiles = (M + rows - 1) / rows;
   const int64_t slots = bf16_slots(is_tn, f32);
   int64_t smax = K / kKGroup;
@@ -758,7 +692,8 @@ static int launch_bf16(const void *A, int64_t lda, const float *X, int64_t ldx, 
   kps = (kps + kKGroup - 1) / kKGroup * kKGroup;
   const int nsp = (int)((K + kps - 1) / kps);
   float *p = (nsp > 1) ? part : nullptr;
-  const int64_t tiles = (M + kWgRows<TN, F32> - 1) / kWgRows<TN, F32>;
+  constexpr int64_t rows = (F32 && !TN) ? kNlRows : kB16Rows;
+  const int64_t tiles = (M + rows - 1) / rows;
   const int64_t total = tiles * nsp;
   const uintptr_t ad = reinterpret_cast<uintptr_t>(A);
   // vector loads: aligned rows whose groups of 4 columns (TN: 8 bytes BF16,
