@@ -207,7 +207,10 @@ def time_solves(wl, A, steps, warmup, dev):
         if c.startswith("gemm"):
             rec["tflops"] = 2.0 * m * n * b / (a_ms * 1e-3) / 1e12
             rec["a_GBps"] = elem * m * n / (a_ms * 1e-3) / 1e9
-            rec["mfma_frac"] = rec["tflops"] / PEAK_FP32_MFMA_TFLOPS if storage == "f32" else None
+            # FP32 matrix-core fraction only where the pass runs on them (row-major
+            # FP32 A: C_j^T = A^T Q_j; the power-step passes run split on BF16)
+            on_fp32 = storage == "f32" and (LAYOUTS.get(wl, "row") == "col" or c == "gemm_c")
+            rec["mfma_frac"] = rec["tflops"] / PEAK_FP32_MFMA_TFLOPS if on_fp32 else None
             rec["hbm_frac"] = rec["a_GBps"] / PEAK_HBM_GBPS
         elif c == "sketch":
             rec["GBps"] = (elem * m * n + 4.0 * m * b) / (a_ms * 1e-3) / 1e9
