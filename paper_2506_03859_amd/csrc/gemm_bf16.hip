@@ -490,27 +490,32 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
 // A G with FP32 A.  Read straight into the MFMA operand layout, a load
 // instruction covers 16 rows x 64 bytes and the pass streams A at about 3 TB/s
 // whatever the arithmetic; here each 64-deep slice of the workgroup's 256 rows
-// is read as 32 rows x 256 contiguous bytes per instruction (16 lanes per
-// row), kNlRing slices ahead in registers, stored into an LDS tile (row stride 68
-// floats: the 16-byte stores of a row and the 16-byte operand reads of 8
-// consecutive rows are bank-conflict free), and each wave takes its operands
-// (32 rows: 2 row groups of 16) from there.  The skinny slice is staged as for
-// the BF16 NN kernel (natural k order).  Two barriers per slice: the tile is
-// single-buffered (256 x 68 floats = 68 KB, plus 27 KB of skinny planes).
+// is read as 64 rows x 256 contiguous bytes per instruction (16 lanes per
+// row), kNlRing slices ahead in registers, stored into an LDS tile (row stride
+// 68 floats: the 16-byte stores of a row and the 16-byte operand reads of 8
+// consecutive rows are bank-conflict free), and each of the 16 waves takes the
+// operands of its 16 rows from there; the skinny planes are read one at a time
+// (hi: three products, mid: two, lo: one), so that a wave fits in 128
+// registers and four waves share a SIMD.  The skinny slice is staged in its
+// natural k order.  Two barriers per slice: the tile is single-buffered
+// (256 x 68 floats = 68 KB, plus 27 KB of skinny planes).
 constexpr int kNlRows = 256;                 // output rows per workgroup
 constexpr int kNlSl = 64;                    // k per slice
 constexpr int kNlLd = kNlSl + 4;             // floats per LDS row of the tile
 constexpr int kNlRing = 2;                   // slices in flight in registers
 static_assert(kKGroup % kNlSl == 0, "slices divide the split granularity");
 
+constexpr int kNlWaves = 16;
+constexpr int kNlThreads = 64 * kNlWaves;
+
 template <bool AVEC>
 __device__ __forceinline__ void nl_load(const float *A, int64_t lda, int64_t M, int64_t K,
-                                        int64_t r0, int64_t k0, int tid, float4 (&v)[8]) {
+                                        int64_t r0, int64_t k0, int tid, float4 (&v)[4]) {
   const int kq = (tid & 15) * 4;
   const int64_t k4 = (K + 3) & ~int64_t(3);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int64_t row = b16_clamp(r0 + 32 * q + (tid >> 4), M - 1);
+  for (int q = 0; q < 4; ++q) {
+    const int64_t row = b16_clamp(r0 + 64 * q + (tid >> 4), M - 1);
     const float *p = A + row * lda;
     const int64_t kk = k0 + kq;
     if (AVEC) {
@@ -531,12 +536,12 @@ __device__ __forceinline__ void nl_load(const float *A, int64_t lda, int64_t M, 
 }
 
 template <bool AVEC>
-__global__ __launch_bounds__(kB16Threads) void gemm_f32s_nn_lds_kernel(
+__global__ __launch_bounds__(kNlThreads) void gemm_f32s_nn_lds_kernel(
     const float *__restrict__ A, int64_t lda, const float *xt, int64_t kp, float *__restrict__ C,
     int64_t ldc, int64_t M, int64_t N, int64_t K, int64_t kps, int64_t tiles, int64_t total,
     float alpha, float beta, float *__restrict__ part) {
   using Lds = B16Lds<false, false>;                 // 64-deep skinny slices, natural k order
-  static_assert(Lds::XL == 2 && B16Cfg<false, false>::SL == kNlSl, "skinny slice layout");
+  static_assert(B16Cfg<false, false>::SL == kNlSl, "skinny slice layout");
   __shared__ __attribute__((aligned(16))) float al[kNlRows * kNlLd];
   __shared__ __attribute__((aligned(16))) uint16_t xs[Lds::STAGE];
   const int tid = threadIdx.x;
@@ -548,50 +553,71 @@ __global__ __launch_bounds__(kB16Threads) void gemm_f32s_nn_lds_kernel(
   const int64_t kb = split * kps;
   const int64_t ke = (kb + kps < K) ? kb + kps : K;
   const int64_t nsl = (ke - kb + kNlSl - 1) / kNlSl;
-  const int sc = tid >> 3, kq = tid & 7;
-  const float *xsrc = xt + sc * kp + kb + 8 * kq;
+  const int sc = tid >> 4, kq = tid & 15;
+  const float *xsrc = xt + sc * kp + kb + 4 * kq;
 
-  floatx4 acc[8];
+  floatx4 acc[4];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < 4; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   constexpr int R = kNlRing;
-  float4 ar[R][8];
-  float4 xr[R][2];
+  float4 ar[R][4];
+  float4 xr[R];
   auto issue = [&](int64_t s, int slot) {
     const int64_t sl = s < nsl ? s : nsl - 1;      // clamped: in bounds, never used
-#pragma unroll
-    for (int g = 0; g < 2; ++g) xr[slot][g] = *reinterpret_cast<const float4 *>(xsrc + sl * kNlSl + 4 * g);
+    xr[slot] = *reinterpret_cast<const float4 *>(xsrc + sl * kNlSl);
     nl_load<AVEC>(A, lda, M, K, r0, kb + sl * kNlSl, tid, ar[slot]);
   };
 #pragma unroll
   for (int d = 0; d < R; ++d) issue(d, d);
-  const int wrow = 32 * wave;
+  const int wrow = 16 * wave;
   for (int64_t s0 = 0; s0 < nsl; s0 += R) {
 #pragma unroll
     for (int d = 0; d < R; ++d) {
       if (s0 + d >= nsl) break;                    // uniform
       __syncthreads();                             // slice s0 + d - 1 consumed
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        *reinterpret_cast<float4 *>(al + (32 * q + (tid >> 4)) * kNlLd + (tid & 15) * 4) = ar[d][q];
-      stage_skinny<false, false>(xs, sc, kq, xr[d]);
+      for (int q = 0; q < 4; ++q)
+        *reinterpret_cast<float4 *>(al + (64 * q + (tid >> 4)) * kNlLd + (tid & 15) * 4) = ar[d][q];
+      {
+        uint32_t h0, m0, l0, h1, m1, l1;
+        split_pair(xr[d].x, xr[d].y, h0, m0, l0);
+        split_pair(xr[d].z, xr[d].w, h1, m1, l1);
+        uint16_t *col = xs + sc * Lds::CS + 4 * kq;
+        *reinterpret_cast<uint2 *>(col) = make_uint2(h0, h1);
+        *reinterpret_cast<uint2 *>(col + Lds::PLANE) = make_uint2(m0, m1);
+        *reinterpret_cast<uint2 *>(col + 2 * Lds::PLANE) = make_uint2(l0, l1);
+      }
       issue(s0 + d + R, d);
       __syncthreads();                             // slice s0 + d staged
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        u32x4 b[3][4];
-        load_b_planes<Lds>(xs, li, lk, ks, b);
+        const float *ap = al + (wrow + li) * kNlLd + 32 * ks + 8 * lk;
+        const float4 u = *reinterpret_cast<const float4 *>(ap);
+        const float4 w = *reinterpret_cast<const float4 *>(ap + 4);
+        const float e[8] = {u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
+        u32x4 ah, am, alo;
+        split8(e, ah, am, alo);
+        const uint16_t *xb = xs + li * Lds::CS + 32 * ks + 8 * lk;
+        u32x4 b[4];
 #pragma unroll
-        for (int x = 0; x < 2; ++x) {
-          const float *ap = al + (wrow + 16 * x + li) * kNlLd + 32 * ks + 8 * lk;
-          const float4 u = *reinterpret_cast<const float4 *>(ap);
-          const float4 w = *reinterpret_cast<const float4 *>(ap + 4);
-          const float e[8] = {u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
-          u32x4 ah, am, alo;
-          split8(e, ah, am, alo);
-          mma_split6(acc + 4 * x, ah, am, alo, b);
-        }
+        for (int ct = 0; ct < 4; ++ct) b[ct] = *reinterpret_cast<const u32x4 *>(xb + 16 * ct * Lds::CS);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma_bf16(ah, b[ct], acc[ct]);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma_bf16(am, b[ct], acc[ct]);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma_bf16(alo, b[ct], acc[ct]);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) b[ct] = *reinterpret_cast<const u32x4 *>(xb + Lds::PLANE + 16 * ct * Lds::CS);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma_bf16(ah, b[ct], acc[ct]);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma_bf16(am, b[ct], acc[ct]);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) b[ct] = *reinterpret_cast<const u32x4 *>(xb + 2 * Lds::PLANE + 16 * ct * Lds::CS);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma_bf16(ah, b[ct], acc[ct]);
       }
     }
   }
@@ -599,22 +625,20 @@ __global__ __launch_bounds__(kB16Threads) void gemm_f32s_nn_lds_kernel(
   float *dst = part ? part + split * M * kBld : C;
   const int64_t ld = part ? kBld : ldc;
 #pragma unroll
-  for (int g = 0; g < 2; ++g)
+  for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = r0 + wrow + 16 * g + 4 * lk + v;
-        const int64_t col = 16 * ct + li;
-        if (row < M && col < N) {
-          float r = acc[g * 4 + ct][v];
-          if (!part) {
-            r *= alpha;
-            if (beta != 0.0f) r += beta * dst[row * ld + col];
-          }
-          dst[row * ld + col] = r;
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + wrow + 4 * lk + v;
+      const int64_t col = 16 * ct + li;
+      if (row < M && col < N) {
+        float r = acc[ct][v];
+        if (!part) {
+          r *= alpha;
+          if (beta != 0.0f) r += beta * dst[row * ld + col];
         }
+        dst[row * ld + col] = r;
       }
+    }
 }
 
 // ------------------------------------------------------------------ host
@@ -635,7 +659,8 @@ static int64_t bf16_slots(int is_tn, bool f32) {
                    : reinterpret_cast<const void *>(&gemm_f32s_nn_lds_kernel<true>))
           : (is_tn ? reinterpret_cast<const void *>(&gemm_bf16_kernel<true, true, false>)
                    : reinterpret_cast<const void *>(&gemm_bf16_kernel<false, true, false>));
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kB16Threads, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (f32 && !is_tn) ? kNlThreads : kB16Threads,
+                                                   0) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   const int64_t slots = (int64_t)cus * per_cu;
@@ -710,6 +735,7 @@ static int launch_bf16(const void *A, int64_t lda, const float *X, int64_t ldx, 
   const int64_t mclamp = (TN && M % 4 != 0) ? m4 : M;
   dim3 grid((unsigned)total), blk(kB16Threads);
   if constexpr (F32 && !TN) {
+    blk = dim3(kNlThreads);
     const float *Af = static_cast<const float *>(A);
     if (avec)
       hipLaunchKernelGGL((gemm_f32s_nn_lds_kernel<true>), grid, blk, 0, st, Af, lda, xt, kp, C, ldc,
