@@ -549,10 +549,9 @@ static int gemm_best_split(int64_t M, int64_t K, int wm, int64_t smax, int64_t s
 // WM = 1).  The choice does not depend on the caller's split limit, so that
 // launch and split choice agree.
 static int gemm_wm(int64_t M, int64_t K, int is_tn) {
-  // short NN products (Q r: K = l): with enough rows for two 256-row tiles
-  // per CU, each wave walks the whole K range of its own 64 rows (no
-  // cross-wave reduction at the end); with fewer, 64-row tiles spread the
-  // product over more CUs (20000 rows: 313 workgroups against 79)
+  // short NN products (Q r: K = l) past kShortMaxM rows (below it they take
+  // gemm_nn_short_kernel): each wave walks the whole K range of its own 64
+  // rows (no cross-wave reduction at the end)
   if (K < 1024) return (!is_tn && M >= 131072) ? 4 : 1;
   double c1 = 0.0, c4 = 0.0;
   gemm_best_split(M, K, 1, 64, gemm_slots(is_tn, 1), &c1);
@@ -571,12 +570,134 @@ int gemm_choose_ksplit(int64_t M, int64_t K, int is_tn, int64_t max_split) {
 
 static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// ------------------------------------------------------------- short K (NN)
+// The basis products Q r (K = l, a few hundred) are latency-bound in the
+// chunk pipeline above (one DRAM round trip per 64-deep chunk, 15-25 us per
+// launch against a few us of HBM time).  Here a workgroup of 8 waves owns 128
+// output rows; every wave issues the loads of its 16 rows over the whole K at
+// once (one 16-byte load per 16-deep slice and lane, at most kShortK / 16
+// slices in registers), the workgroup stages all of X (K x 64) in LDS, and
+// after one barrier each wave runs its K / 4 steps of 4 MFMAs.  Same MFMA
+// operand order as gemm_kernel (lane (li, lk), slice s: row li, k = 16 s +
+// 4 lk + u for MFMA u).
+constexpr int kShortK = 384;
+// The X stage takes 104 KB of LDS (one workgroup per CU): past about 130000
+// rows (over 4 rounds of workgroups) the 4-tile chunk pipeline is faster.
+constexpr int64_t kShortMaxM = 131072;
+constexpr int kShortWaves = 8;
+constexpr int kShortRows = 16 * kShortWaves;
+
+template <bool AVEC, bool XVEC>
+__global__ __launch_bounds__(64 * kShortWaves) void gemm_nn_short_kernel(
+    const float *__restrict__ A, int64_t lda, const float *__restrict__ X, int64_t ldx,
+    float *__restrict__ C, int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta) {
+  constexpr int kMaxSl = kShortK / 16;
+  __shared__ float xs[kShortK * kXs];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nsl = (int)((K + 15) / 16);
+  const int64_t r0 = (int64_t)blockIdx.x * kShortRows + 16 * wave;
+  const float *ar = A + clampi(r0 + li, M - 1) * lda;
+  float4 a[kMaxSl];
+#pragma unroll
+  for (int s = 0; s < kMaxSl; ++s) {
+    if (s < nsl) {
+      const int64_t g = 16 * s + 4 * lk;
+      if (AVEC && g + 4 <= K) {
+        a[s] = *reinterpret_cast<const float4 *>(ar + g);
+      } else {
+        float v[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const float u = ar[clampi(g + t, K - 1)];
+          v[t] = (g + t < K) ? u : 0.0f;
+        }
+        a[s] = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
+  }
+  // X rows 0 .. 16 nsl - 1 (zero past K and past column N)
+  const int nf = 16 * 16 * nsl;                  // float4 pieces
+  for (int f = tid; f < nf; f += 64 * kShortWaves) {
+    const int64_t k = f >> 4;
+    const int col = 4 * (f & 15);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (k < K) {
+      // the last row is read by vector only when N == 64: a caller's buffer
+      // may end at its N-th column
+      if (XVEC && (N == 64 || k + 1 < K)) {
+        v = *reinterpret_cast<const float4 *>(X + k * ldx + col);
+        if (N < 64) {
+          v.x = col < N ? v.x : 0.0f;
+          v.y = col + 1 < N ? v.y : 0.0f;
+          v.z = col + 2 < N ? v.z : 0.0f;
+          v.w = col + 3 < N ? v.w : 0.0f;
+        }
+      } else {
+        const float *p = X + k * ldx;
+        float w[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const float u = p[clampi(col + t, N - 1)];
+          w[t] = (col + t < N) ? u : 0.0f;
+        }
+        v = make_float4(w[0], w[1], w[2], w[3]);
+      }
+    }
+    *reinterpret_cast<float4 *>(xs + k * kXs + col) = v;
+  }
+  __syncthreads();
+  floatx4 acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < kMaxSl; ++s) {
+    if (s < nsl) {
+      const float *xb = xs + (16 * s + 4 * lk) * kXs + li;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float av = comp(a[s], u);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma4(av, xb[u * kXs + 16 * ct], acc[ct]);
+      }
+    }
+  }
+  // D lane l element v = (row 4 (l / 16) + v, column l % 16)
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + 4 * lk + v;
+      const int64_t col = 16 * ct + li;
+      if (row < M && col < N) {
+        float r = alpha * acc[ct][v];
+        if (beta != 0.0f) r += beta * C[row * ldc + col];
+        C[row * ldc + col] = r;
+      }
+    }
+}
+
 template <bool TN>
 static int launch_main(const float *A, int64_t lda, const float *X, int64_t ldx, float *C,
                        int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta,
                        int ksplit, float *part, hipStream_t st) {
   if (M <= 0 || N <= 0) return 1;
   if (ksplit < 1) ksplit = 1;
+  if (!TN && K > 0 && K <= kShortK && M < kShortMaxM) {
+    const bool avec = (lda % 4 == 0) && aligned16(A);
+    const bool xvec = (ldx % 4 == 0) && aligned16(X) && (N == 64 || ldx >= 64);
+    const dim3 grid((unsigned)((M + kShortRows - 1) / kShortRows)), blk(64 * kShortWaves);
+#define FARPCA_SHORT_LAUNCH(AV, XV)                                                               \
+  hipLaunchKernelGGL((gemm_nn_short_kernel<AV, XV>), grid, blk, 0, st, A, lda, X, ldx, C, ldc, M, N, \
+                     K, alpha, beta)
+    if (avec && xvec) FARPCA_SHORT_LAUNCH(true, true);
+    else if (avec) FARPCA_SHORT_LAUNCH(true, false);
+    else if (xvec) FARPCA_SHORT_LAUNCH(false, true);
+    else FARPCA_SHORT_LAUNCH(false, false);
+#undef FARPCA_SHORT_LAUNCH
+    return 1;
+  }
   const int wm = gemm_wm(M, K, TN ? 1 : 0);
   const int64_t kc = (wm == 4) ? 32 : 64;        // K rows per chunk (KC)
   int64_t kps = (K + ksplit - 1) / ksplit;

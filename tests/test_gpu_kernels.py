@@ -183,6 +183,8 @@ def test_sketch_real_A(fp, sketch, p, zeta, b, layout):
 GEMM_SHAPES = [(1000, 777, 50), (130, 3000, 64), (64, 64, 1), (5000, 20000, 64), (1, 300, 7),
                (257, 1500, 33), (3000, 64, 64), (9001, 3001, 64), (20000, 1000, 64),
                (8192, 4000, 50), (12000, 2048, 64), (8200, 40, 64),
+               # short K (the basis products Q r, K = l <= 384) and just past it
+               (20000, 320, 64), (7001, 130, 7), (5000, 384, 33), (300, 385, 64), (129, 3, 64),
                # tall A: short output (4000 or 2500 columns of A) over a long K
                (4000, 100000, 50), (2500, 30000, 64),
                # short K over many rows (the basis product Q r of a tall A)
