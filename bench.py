@@ -207,9 +207,9 @@ def time_solves(wl, A, steps, warmup, dev):
         if c.startswith("gemm"):
             rec["tflops"] = 2.0 * m * n * b / (a_ms * 1e-3) / 1e12
             rec["a_GBps"] = elem * m * n / (a_ms * 1e-3) / 1e9
-            # FP32 matrix-core fraction only where the pass runs on them (row-major
-            # FP32 A: C_j^T = A^T Q_j; the power-step passes run split on BF16)
-            on_fp32 = storage == "f32" and (LAYOUTS.get(wl, "row") == "col" or c == "gemm_c")
+            # FP32 matrix-core fraction only where the pass runs on them (column-
+            # major FP32 A; row-major FP32 A runs every A-pass split on BF16)
+            on_fp32 = storage == "f32" and LAYOUTS.get(wl, "row") == "col"
             rec["mfma_frac"] = rec["tflops"] / PEAK_FP32_MFMA_TFLOPS if on_fp32 else None
             rec["hbm_frac"] = rec["a_GBps"] / PEAK_HBM_GBPS
         elif c == "sketch":
@@ -245,8 +245,8 @@ def kernel_probe(wl, dev, reps=3):
         scratch = buf[off:off + nb]
         gemm_tn, gemm_nn = fp.farpca_gemm_bf16_tn, fp.farpca_gemm_bf16_nn
     elif layout == "row":
-        # the solve's power-step A^T T and its A G passes on row-major FP32 A
-        # run split on the BF16 matrix cores
+        # the solve's A-passes on row-major FP32 A run split on the BF16
+        # matrix cores
         nb = max(fp.farpca_gemm_bf16_scratch_bytes(max(m, n), max(m, n)),
                  fp.farpca_gemm_scratch_bytes(max(m, n)))
         buf = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
@@ -259,9 +259,6 @@ def kernel_probe(wl, dev, reps=3):
     for r in range(reps):
         gemm_tn(A, skinny_m, Cn, n, b, m, scratch)
         gemm_nn(A, skinny_n, Cm, m, b, n, scratch)
-        if storage == "f32" and layout == "row":
-            # C_j^T = A^T Q_j stays on the FP32 matrix cores
-            fp.farpca_gemm_tn(A, skinny_m, Cn, n, b, m, scratch)
         # column-major workloads: the sketch reads A^T row-major (same buffer, n x m)
         fp.farpca_sketch(plan, A if layout == "row" else A.reshape(n, m), r, work, Cm)
     torch.cuda.synchronize()
@@ -720,9 +717,8 @@ def main():
     dom = max(cand, key=lambda c: cand[c][0])
     tot_ms, a_ms, cnt = cand[dom]
     layout = LAYOUTS.get(wl, "row")
-    # row-major FP32 A: the power-step A^T T and the A G products run split on
-    # the BF16 matrix cores, C_j^T = A^T Q_j on the FP32 ones
-    split = storage == "f32" and layout == "row" and dom in ("gemm_tn", "gemm_nn")
+    # row-major FP32 A: every A-pass runs split on the BF16 matrix cores
+    split = storage == "f32" and layout == "row" and dom in ("gemm_tn", "gemm_nn", "gemm_c")
     pass_name = {"gemm_tn": "A^T Y", "gemm_nn": "A G", "gemm_c": "C_j^T = A^T Q_j"}.get(dom)
     if dom == "sketch":
         alg = a_bytes + 4.0 * m * b
@@ -741,8 +737,8 @@ def main():
         # 6 x 2 m n b flop of BF16 MFMA, far under its peak): 4 m n bytes of A
         # per launch against HBM
         achieved = a_bytes / (a_ms * 1e-3) / 1e9
-        kname = ("gemm_bf16_kernel<true, true, true> (A^T Y, FP32 A split)" if dom == "gemm_tn"
-                 else "gemm_f32s_nn_lds_kernel<true> (A G, FP32 A split)")
+        kname = ("gemm_f32s_nn_lds_kernel<true> (A G, FP32 A split)" if dom == "gemm_nn"
+                 else f"gemm_bf16_kernel<true, true, true> ({pass_name}, FP32 A split)")
         roof = {"kernel": kname, "bound": "hbm",
                 "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBPS,
@@ -757,7 +753,7 @@ def main():
     else:
         alg_per_launch = a_bytes if (storage == "bf16" or split) else gemm_flops
     base_key = "gemm_tn" if dom == "gemm_c" else dom
-    traffic_key = f"{dom}_split" if split else (base_key if storage == "f32" else f"{base_key}_bf16")
+    traffic_key = f"{base_key}_split" if split else (base_key if storage == "f32" else f"{base_key}_bf16")
     roof.update({"avg_launch_ms": a_ms, "launches": cnt, "algorithmic_per_launch": alg_per_launch,
                  "traffic": measured_traffic(traffic_key) if layout == "row" else None})
     if layout == "col" and dom != "sketch":

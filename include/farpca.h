@@ -272,7 +272,10 @@ int farpca_gemm_bf16_tn(const uint16_t *dA, int64_t lda, const float *dY, int64_
  * the nine term products are accumulated in FP32 (hi hi, hi mid, mid hi, mid
  * mid, hi lo, lo hi).  The three left out are below 2^-23 |a x| per product
  * together and of either sign (about one FP32 rounding of the product), so
- * the result carries FP32-level rounding, not BF16's.  Same arguments, scratch
+ * the result carries FP32-level rounding, not BF16's.  In the TN product each
+ * 32-deep slice's products are summed from zero and added to the running sum
+ * in FP32 by the vector unit (no bias in sums of squares of its columns: it
+ * forms C_j^T = A^T Q_j of the indicator).  Same arguments, scratch
  * (farpca_gemm_bf16_scratch_bytes) and readability rule as the BF16 products,
  * with A FP32. */
 int farpca_gemm_f32s_nn(const float *dA, int64_t lda, const float *dX, int64_t ldx, float *dC,
@@ -362,7 +365,7 @@ int farpca_server_destroy(farpca_server_t *srv);
 #define FARPCA_PROF_GEMM_TN 1  /* A^T T products of the power steps              */
 #define FARPCA_PROF_GEMM_NN 2  /* A G products (and the Gaussian sketch)        */
 #define FARPCA_PROF_EIG 3      /* final FP64 eigendecomposition                 */
-#define FARPCA_PROF_GEMM_C 4   /* C_j^T = A^T Q_j (values kept in C and E)      */
+#define FARPCA_PROF_GEMM_C 4   /* C_j^T = A^T Q_j (kept in C^T, summed in E)    */
 #define FARPCA_PROF_NCLASS 5
 void farpca_profile_enable(int on);
 int farpca_profile_get(int cls, double *total_ms, int64_t *count);

@@ -411,10 +411,9 @@ int setup_partials(const farpca_plan_s *pl) {
 //   TN (tn true):  C (n x ncols) = A^T T, T m x ncols (ld kBld)
 // Returns the number of partial products left in the partial buffer (1: C
 // was written directly); launch_gemm_finish completes the product.  With FP32
-// row-major A the pass runs split on the BF16 matrix cores unless allow_split
-// is false (the FP32 matrix cores).
+// row-major A the pass runs split on the BF16 matrix cores.
 int a_pass(const farpca_plan_s *pl, const Ws &w, bool tn, const void *A, const float *X, int ncols,
-           float *C, int64_t ldc, hipStream_t st, bool allow_split = true) {
+           float *C, int64_t ldc, hipStream_t st) {
   const farpca_params &q = pl->prm;
   float *part = w.at<float>(pl->off_part);
   const int64_t M = tn ? q.n : q.m, K = tn ? q.m : q.n;
@@ -428,7 +427,7 @@ int a_pass(const farpca_plan_s *pl, const Ws &w, bool tn, const void *A, const f
                                          part, xt, st);
   }
   const float *Af = static_cast<const float *>(A);
-  if (pl->split && allow_split) {
+  if (pl->split) {
     // FP32 A on the BF16 matrix cores (exact three-term splits of both
     // operands, six term products): the pass is then bound by streaming A,
     // not by the FP32 matrix-core rate
@@ -732,10 +731,8 @@ static int enqueue_block(farpca_plan_s *pl, hipStream_t st) {
   } else {
     int nsp4;
     {
-      // C_j stays on the FP32 matrix cores: its values are what the indicator
-      // subtracts from ||A||^2 and what the final decomposition reads
       ProfScope ps(FARPCA_PROF_GEMM_C, st);
-      nsp4 = a_pass(pl, w, true, A, Ysrc, b, Ct + l, pl->ldq, st, false);
+      nsp4 = a_pass(pl, w, true, A, Ysrc, b, Ct + l, pl->ldq, st);
     }
     launch_gemm_finish(part, nsp4, n, b, Ct + l, pl->ldq, 1.f, 0.f, st);
     launch_sqnorm(Ct + l, pl->ldq, n, b, w.at<double>(pl->off_sq), st);

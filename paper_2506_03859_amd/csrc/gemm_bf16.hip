@@ -80,9 +80,10 @@ template <> struct B16Cfg<false, false> {
   static constexpr int SL = 64, RING = 3, NBUF = 3, AV = 8;
 };
 // FP32 A (TN): a slot holds 8 float4 per lane (4 columns of 8 rows), so the
-// ring is shallower; 32-deep slices.
+// ring is shallower (two slots: the per-slice accumulators of mma_slice_f32
+// take the registers of a third, at the same measured speed); 32-deep slices.
 template <> struct B16Cfg<true, true> {
-  static constexpr int SL = 32, RING = 3, NBUF = 3, AV = 8;
+  static constexpr int SL = 32, RING = 2, NBUF = 2, AV = 8;
 };
 template <bool TN, bool F32> struct B16Lds {
   static constexpr int CS = B16Cfg<TN, F32>::SL + 8;   // BF16 per staged column (16-byte aligned)
@@ -374,7 +375,11 @@ __device__ __forceinline__ void load_b_planes(const uint16_t *xs, int li, int lk
 }
 
 // One 32-deep TN slice with FP32 A: column t of the lane's 4 (output rows
-// t0 + 4 li + t) is MFMA row group t.
+// t0 + 4 li + t) is MFMA row group t.  The slice's six term products start
+// from zero and their sum is added to the running accumulator by the vector
+// unit (FP32, round to nearest): accumulated inside the matrix cores over the
+// whole K, the products of C_j^T = A^T Q_j left a bias in the indicator of the
+// order of 1e-7 ||A||^2 (sums of squares of many columns), which this removes.
 __device__ __forceinline__ void mma_slice_f32(floatx4 (&acc)[16], const ASlot<true, true> &s,
                                               const uint16_t *xs, int li, int lk) {
   static_assert(B16Cfg<true, true>::SL == 32, "one MFMA step per slice");
@@ -390,7 +395,12 @@ __device__ __forceinline__ void mma_slice_f32(floatx4 (&acc)[16], const ASlot<tr
     }
     u32x4 ah, am, al;
     split8(e, ah, am, al);
-    mma_split6(acc + 4 * x, ah, am, al, b);
+    floatx4 t[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) t[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    mma_split6(t, ah, am, al, b);
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[4 * x + ct] += t[ct];
   }
 }
 
