@@ -499,16 +499,20 @@ __global__ __launch_bounds__(kB16Threads) void gemm_bf16_kernel(
 // ------------------------------------------- FP32 A, NN, A staged in LDS
 // A G with FP32 A.  Read straight into the MFMA operand layout, a load
 // instruction covers 16 rows x 64 bytes and the pass streams A at about 3 TB/s
-// whatever the arithmetic; here each 64-deep slice of the workgroup's 256 rows
-// is read as 64 rows x 256 contiguous bytes per instruction (16 lanes per
-// row), kNlRing slices ahead in registers, stored into an LDS tile (row stride
-// 68 floats: the 16-byte stores of a row and the 16-byte operand reads of 8
-// consecutive rows are bank-conflict free), and each of the 16 waves takes the
-// operands of its 16 rows from there; the skinny planes are read one at a time
-// (hi: three products, mid: two, lo: one), so that a wave fits in 128
-// registers and four waves share a SIMD.  The skinny slice is staged in its
-// natural k order.  Two barriers per slice: the tile is single-buffered
-// (256 x 68 floats = 68 KB, plus 27 KB of skinny planes).
+// whatever the arithmetic; here each wave reads the 64-deep slice of its own
+// 16 rows as 4 rows x 256 contiguous bytes per instruction (16 lanes per row),
+// kNlRing slices ahead in registers, stores it into its own part of LDS (row
+// stride 68 floats: the 16-byte stores of a row and the 16-byte operand reads
+// of 8 consecutive rows are bank-conflict free) and reads its MFMA operands
+// back from there.  No other wave touches those rows, and a wave's LDS
+// accesses run in order, so the A tile needs no barrier.  The skinny slice
+// (split into its three BF16 planes once per workgroup, in its natural k
+// order) is shared by the 16 waves and double-buffered: one barrier per slice,
+// after which the next slice's A loads are already in flight and its skinny
+// planes are staged once the MFMAs of this one are issued.  The skinny planes
+// are read one at a time (hi: three products, mid: two, lo: one), so that a
+// wave fits in 128 registers and four waves share a SIMD.  LDS: 16 x 16 x 68
+// floats (68 KB) of A and 2 x 27 KB of skinny planes.
 constexpr int kNlRows = 256;                 // output rows per workgroup
 constexpr int kNlSl = 64;                    // k per slice
 constexpr int kNlLd = kNlSl + 4;             // floats per LDS row of the tile
@@ -519,41 +523,16 @@ constexpr int kNlWaves = 16;
 constexpr int kNlThreads = 64 * kNlWaves;
 
 template <bool AVEC>
-__device__ __forceinline__ void nl_load(const float *A, int64_t lda, int64_t M, int64_t K,
-                                        int64_t r0, int64_t k0, int tid, float4 (&v)[4]) {
-  const int kq = (tid & 15) * 4;
-  const int64_t k4 = (K + 3) & ~int64_t(3);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t row = b16_clamp(r0 + 64 * q + (tid >> 4), M - 1);
-    const float *p = A + row * lda;
-    const int64_t kk = k0 + kq;
-    if (AVEC) {
-      const int64_t g = b16_clamp(kk, k4 - 4);
-      float4 x = *reinterpret_cast<const float4 *>(p + g);
-      if ((K & 3) != 0 && g + 4 > K) {
-        const int64_t nv = K - g;                // 1 .. 3 valid elements
-        x.y = nv > 1 ? x.y : 0.0f;
-        x.z = nv > 2 ? x.z : 0.0f;
-        x.w = 0.0f;
-      }
-      v[q] = x;
-    } else {
-      v[q] = make_float4(p[b16_clamp(kk, K - 1)], p[b16_clamp(kk + 1, K - 1)],
-                         p[b16_clamp(kk + 2, K - 1)], p[b16_clamp(kk + 3, K - 1)]);
-    }
-  }
-}
-
-template <bool AVEC>
 __global__ __launch_bounds__(kNlThreads) void gemm_f32s_nn_lds_kernel(
     const float *__restrict__ A, int64_t lda, const float *xt, int64_t kp, float *__restrict__ C,
     int64_t ldc, int64_t M, int64_t N, int64_t K, int64_t kps, int64_t tiles, int64_t total,
     float alpha, float beta, float *__restrict__ part) {
   using Lds = B16Lds<false, false>;                 // 64-deep skinny slices, natural k order
   static_assert(B16Cfg<false, false>::SL == kNlSl, "skinny slice layout");
-  __shared__ __attribute__((aligned(16))) float al[kNlRows * kNlLd];
-  __shared__ __attribute__((aligned(16))) uint16_t xs[Lds::STAGE];
+  // A: each wave stages its own 16 rows (no other wave reads them); the
+  // skinny planes are shared and double-buffered
+  __shared__ __attribute__((aligned(16))) float al[kNlWaves * 16 * kNlLd];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[2 * Lds::STAGE];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -565,6 +544,8 @@ __global__ __launch_bounds__(kNlThreads) void gemm_f32s_nn_lds_kernel(
   const int64_t nsl = (ke - kb + kNlSl - 1) / kNlSl;
   const int sc = tid >> 4, kq = tid & 15;
   const float *xsrc = xt + sc * kp + kb + 4 * kq;
+  const int wrow = 16 * wave;
+  float *aw = al + wrow * kNlLd;                    // this wave's 16 rows
 
   floatx4 acc[4];
 #pragma unroll
@@ -573,42 +554,71 @@ __global__ __launch_bounds__(kNlThreads) void gemm_f32s_nn_lds_kernel(
   constexpr int R = kNlRing;
   float4 ar[R][4];
   float4 xr[R];
+  // wave w reads rows wrow + 4 q + lane / 16, 16 lanes per row (256 bytes)
   auto issue = [&](int64_t s, int slot) {
     const int64_t sl = s < nsl ? s : nsl - 1;      // clamped: in bounds, never used
     xr[slot] = *reinterpret_cast<const float4 *>(xsrc + sl * kNlSl);
-    nl_load<AVEC>(A, lda, M, K, r0, kb + sl * kNlSl, tid, ar[slot]);
+    const int64_t k0 = kb + sl * kNlSl;
+    const int64_t kk = k0 + 4 * li;
+    const int64_t k4 = (K + 3) & ~int64_t(3);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = b16_clamp(r0 + wrow + 4 * q + lk, M - 1);
+      const float *p = A + row * lda;
+      if (AVEC) {
+        const int64_t g = b16_clamp(kk, k4 - 4);
+        float4 x = *reinterpret_cast<const float4 *>(p + g);
+        if ((K & 3) != 0 && g + 4 > K) {
+          const int64_t nv = K - g;                // 1 .. 3 valid elements
+          x.y = nv > 1 ? x.y : 0.0f;
+          x.z = nv > 2 ? x.z : 0.0f;
+          x.w = 0.0f;
+        }
+        ar[slot][q] = x;
+      } else {
+        ar[slot][q] = make_float4(p[b16_clamp(kk, K - 1)], p[b16_clamp(kk + 1, K - 1)],
+                                  p[b16_clamp(kk + 2, K - 1)], p[b16_clamp(kk + 3, K - 1)]);
+      }
+    }
+  };
+  auto stage_x = [&](int slot, int buf) {
+    uint32_t h0, m0, l0, h1, m1, l1;
+    split_pair(xr[slot].x, xr[slot].y, h0, m0, l0);
+    split_pair(xr[slot].z, xr[slot].w, h1, m1, l1);
+    uint16_t *col = xs + buf * Lds::STAGE + sc * Lds::CS + 4 * kq;
+    *reinterpret_cast<uint2 *>(col) = make_uint2(h0, h1);
+    *reinterpret_cast<uint2 *>(col + Lds::PLANE) = make_uint2(m0, m1);
+    *reinterpret_cast<uint2 *>(col + 2 * Lds::PLANE) = make_uint2(l0, l1);
   };
 #pragma unroll
   for (int d = 0; d < R; ++d) issue(d, d);
-  const int wrow = 16 * wave;
+  stage_x(0, 0);
   for (int64_t s0 = 0; s0 < nsl; s0 += R) {
 #pragma unroll
     for (int d = 0; d < R; ++d) {
-      if (s0 + d >= nsl) break;                    // uniform
-      __syncthreads();                             // slice s0 + d - 1 consumed
+      const int64_t s = s0 + d;
+      if (s >= nsl) break;                         // uniform
+      const int buf = (int)(s & 1);
+      // this wave's rows of slice s; its reads of slice s - 1 were issued
+      // first and a wave's LDS accesses run in order
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        *reinterpret_cast<float4 *>(al + (64 * q + (tid >> 4)) * kNlLd + (tid & 15) * 4) = ar[d][q];
-      {
-        uint32_t h0, m0, l0, h1, m1, l1;
-        split_pair(xr[d].x, xr[d].y, h0, m0, l0);
-        split_pair(xr[d].z, xr[d].w, h1, m1, l1);
-        uint16_t *col = xs + sc * Lds::CS + 4 * kq;
-        *reinterpret_cast<uint2 *>(col) = make_uint2(h0, h1);
-        *reinterpret_cast<uint2 *>(col + Lds::PLANE) = make_uint2(m0, m1);
-        *reinterpret_cast<uint2 *>(col + 2 * Lds::PLANE) = make_uint2(l0, l1);
-      }
-      issue(s0 + d + R, d);
-      __syncthreads();                             // slice s0 + d staged
+        *reinterpret_cast<float4 *>(aw + (4 * q + lk) * kNlLd + 4 * li) = ar[d][q];
+      __builtin_amdgcn_wave_barrier();
+      issue(s + R, d);
+      // skinny slice s staged by every wave; slice s - 1's buffer free
+      __syncthreads();
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        const float *ap = al + (wrow + li) * kNlLd + 32 * ks + 8 * lk;
+        const float *ap = aw + li * kNlLd + 32 * ks + 8 * lk;
         const float4 u = *reinterpret_cast<const float4 *>(ap);
         const float4 w = *reinterpret_cast<const float4 *>(ap + 4);
         const float e[8] = {u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
         u32x4 ah, am, alo;
         split8(e, ah, am, alo);
-        const uint16_t *xb = xs + li * Lds::CS + 32 * ks + 8 * lk;
+        const uint16_t *xb = xs + buf * Lds::STAGE + li * Lds::CS + 32 * ks + 8 * lk;
         u32x4 b[4];
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) b[ct] = *reinterpret_cast<const u32x4 *>(xb + 16 * ct * Lds::CS);
@@ -629,6 +639,7 @@ __global__ __launch_bounds__(kNlThreads) void gemm_f32s_nn_lds_kernel(
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma_bf16(ah, b[ct], acc[ct]);
       }
+      if (s + 1 < nsl) stage_x((d + 1) % R, buf ^ 1);
     }
   }
 
