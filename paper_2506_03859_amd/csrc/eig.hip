@@ -19,6 +19,7 @@
 // exactly zero and never couple (their rotations are the identity).
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 #include "internal.h"
 
@@ -270,43 +271,10 @@ void launch_eig_small(const double *K, int s, int ldk, double *w, double *Vout, 
 constexpr int kBlk = 16;           // block width
 constexpr int kSub = 2 * kBlk;     // subproblem size
 constexpr int kSubLd = kSub + 1;
+constexpr int kPairThreads = 256;
 
 __device__ __forceinline__ int sub_index(int u, int bi, int bj) {
   return u < kBlk ? bi * kBlk + u : bj * kBlk + (u - kBlk);
-}
-
-// One workgroup per pair: one Jacobi sweep of M[S, S], S = block(bi) U block(bj).
-// rflag[pair] = 0 when no off-diagonal entry of the subproblem needed a
-// rotation (R = I exactly), 1 otherwise.
-constexpr int kPairThreads = 256;
-__global__ __launch_bounds__(kPairThreads) void bj_pair_kernel(const double *__restrict__ M, int64_t lp, int nb,
-                                                     int step, double *__restrict__ R,
-                                                     const double *__restrict__ floor_abs,
-                                                     double rel, int *__restrict__ rflag) {
-  __shared__ double a[kSub * kSubLd];
-  __shared__ double a2[kSub * kSubLd];
-  __shared__ double v[kSub * kSubLd];
-  const int pair = blockIdx.x, tid = threadIdx.x;
-  const int bi = rr_player(pair, step, nb), bj = rr_player(nb - 1 - pair, step, nb);
-  for (int e = tid; e < kSub * kSub; e += kPairThreads) {
-    const int u = e / kSub, x = e % kSub;
-    a[u * kSubLd + x] = M[(int64_t)sub_index(u, bi, bj) * lp + sub_index(x, bi, bj)];
-    v[u * kSubLd + x] = (u == x) ? 1.0 : 0.0;
-  }
-  __shared__ int any_big;
-  if (tid == 0) any_big = 0;
-  __syncthreads();
-  const double fl = floor_abs[0];
-  for (int e = tid; e < kSub * kSub; e += kPairThreads) {
-    const int u = e / kSub, x = e % kSub;
-    if (u < x && !negligible(a[u * kSubLd + x], a[u * kSubLd + u], a[x * kSubLd + x], fl, rel)) any_big = 1;
-  }
-  __syncthreads();
-  if (any_big) jacobi_lds<kSub, kSubLd, kPairThreads>(a, a2, v, fl, kPairSweeps, rel);   // else R = I
-  __syncthreads();
-  double *Rp = R + (int64_t)pair * kSub * kSub;
-  for (int e = tid; e < kSub * kSub; e += kPairThreads) Rp[e] = v[(e / kSub) * kSubLd + (e % kSub)];
-  if (tid == 0) rflag[pair] = any_big ? 1 : 0;
 }
 
 // 32 x 32 products on the FP64 matrix cores (v_mfma_f64_16x16x4f64): wave w
@@ -329,31 +297,135 @@ __device__ __forceinline__ doublex4 mm32_quadrant(const double *L, const double 
   return acc;
 }
 
-// Rotate M (pair blocks) and V (row tiles x pair columns) in place:
-// M[S_p, S_q] <- R_p^T M[S_p, S_q] R_q, V[:, S_q] <- V[:, S_q] R_q.  Each
-// workgroup reads its whole block before writing it back.  A block whose
-// rotations are all the identity (rflag 0) is left as it is.
-__global__ __launch_bounds__(256) void bj_update_kernel(double *__restrict__ M, double *__restrict__ V,
-                                                        int64_t lp, int nb, int step,
-                                                        const double *__restrict__ R,
-                                                        const int *__restrict__ rflag) {
-  __shared__ double blk[kSub * kSubLd];
-  __shared__ double tmp[kSub * kSubLd];
-  __shared__ double rq[kSub * kSubLd];
-  __shared__ double rp[kSub * kSubLd];
+// The pair index and half (0: first block, 1: second) of block x at
+// tournament step `step`: the inverse of rr_player.
+__device__ __forceinline__ void rr_slot(int x, int step, int nb, int &pair, int &half) {
+  const int pos = x == 0 ? 0 : ((x - 1 - step) % (nb - 1) + (nb - 1)) % (nb - 1) + 1;
+  pair = pos < nb / 2 ? pos : nb - 1 - pos;
+  half = pos < nb / 2 ? 0 : 1;
+}
+
+// One Jacobi round is one launch: its first npairs workgroups solve the pair
+// subproblems of tournament step `step` (one sweep of M[S, S] in LDS, S =
+// block(bi) U block(bj); rotations to Rcur, fcur[pair] = 0 when no entry
+// needed one, R = I exactly), the others apply the rotations of step - 1
+// (Rprev, fprev) to the whole matrix:
+// M[S_p, S_q] <- R_p^T M[S_p, S_q] R_q (from Msrc into Mdst; a block whose
+// rotations are both the identity is copied), V[:, S_q] <- V[:, S_q] R_q (in
+// place, each row tile by one workgroup).  The pair workgroups do not wait for
+// that update: they form the four 16 x 16 blocks of their subproblem from
+// Msrc and Rprev themselves, with the products, operands and order the update
+// uses for those blocks, so they hold bitwise the values it writes.  The first
+// round of a sweep reads its subproblems straight from Msrc; after the last,
+// an update-only launch (no pair workgroups) applies its rotations.
+constexpr int kRoundLds = 4 * kSub * kSubLd + 4 * kSub * 17;   // doubles
+
+__device__ void pair_role(double *sh, const double *__restrict__ Msrc, int64_t lp, int nb, int step,
+                          const double *__restrict__ Rprev, const int *__restrict__ fprev,
+                          double *__restrict__ Rcur, int *__restrict__ fcur,
+                          const double *__restrict__ floor_abs, double rel, int pair) {
+  double *a = sh, *a2 = sh + kSub * kSubLd, *v = sh + 2 * kSub * kSubLd;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int bi = rr_player(pair, step, nb), bj = rr_player(nb - 1 - pair, step, nb);
+  if (step == 0) {
+    for (int e = tid; e < kSub * kSub; e += kPairThreads) {
+      const int u = e / kSub, x = e % kSub;
+      a[u * kSubLd + x] = Msrc[(int64_t)sub_index(u, bi, bj) * lp + sub_index(x, bi, bj)];
+    }
+  } else {
+    // wave w: block (X, Y) = (w / 2, w % 2) of the subproblem, rows of block
+    // x = X ? bj : bi, columns of block y = Y ? bj : bi
+    const int X = w >> 1, Y = w & 1;
+    const int x = X ? bj : bi, y = Y ? bj : bi;
+    int px, hx, py, hy;
+    rr_slot(x, step - 1, nb, px, hx);
+    rr_slot(y, step - 1, nb, py, hy);
+    if (fprev[px] == 0 && fprev[py] == 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = 4 * t + lk;
+        a[(16 * X + r) * kSubLd + 16 * Y + li] = Msrc[(int64_t)(16 * x + r) * lp + 16 * y + li];
+      }
+    } else {
+      const int pi = rr_player(px, step - 1, nb), pj = rr_player(nb - 1 - px, step - 1, nb);
+      const int qi = rr_player(py, step - 1, nb), qj = rr_player(nb - 1 - py, step - 1, nb);
+      const double *Rp = Rprev + (int64_t)px * kSub * kSub;
+      const double *Rq = Rprev + (int64_t)py * kSub * kSub;
+      // columns 16 hy .. of T = M[S_px, S_py] R_py (the update's quadrants
+      // (0, hy) and (1, hy)), then quadrant (hx, hy) of R_px^T T
+      double *tw = sh + 3 * kSub * kSubLd + w * kSub * 17;
+#pragma unroll
+      for (int qr = 0; qr < 2; ++qr) {
+        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int st = 0; st < kSub / 4; ++st) {
+          const int k = 4 * st + lk;
+          const double av = Msrc[(int64_t)sub_index(16 * qr + li, pi, pj) * lp + sub_index(k, qi, qj)];
+          const double bv = Rq[k * kSub + 16 * hy + li];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) tw[(16 * qr + 4 * t + lk) * 17 + li] = acc[t];
+      }
+      // the wave reads back only what it wrote (a wave's LDS accesses run in order)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      doublex4 o = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < kSub / 4; ++st) {
+        const int k = 4 * st + lk;
+        o = __builtin_amdgcn_mfma_f64_16x16x4f64(Rp[k * kSub + 16 * hx + li], tw[k * 17 + li], o, 0, 0, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[(16 * X + 4 * t + lk) * kSubLd + 16 * Y + li] = o[t];
+    }
+  }
+  for (int e = tid; e < kSub * kSub; e += kPairThreads) {
+    const int u = e / kSub, x = e % kSub;
+    v[u * kSubLd + x] = (u == x) ? 1.0 : 0.0;
+  }
+  __shared__ int any_big;
+  if (tid == 0) any_big = 0;
+  __syncthreads();
+  const double fl = floor_abs[0];
+  for (int e = tid; e < kSub * kSub; e += kPairThreads) {
+    const int u = e / kSub, x = e % kSub;
+    if (u < x && !negligible(a[u * kSubLd + x], a[u * kSubLd + u], a[x * kSubLd + x], fl, rel)) any_big = 1;
+  }
+  __syncthreads();
+  if (any_big) jacobi_lds<kSub, kSubLd, kPairThreads>(a, a2, v, fl, kPairSweeps, rel);   // else R = I
+  __syncthreads();
+  double *Rw = Rcur + (int64_t)pair * kSub * kSub;
+  for (int e = tid; e < kSub * kSub; e += kPairThreads) Rw[e] = v[(e / kSub) * kSubLd + (e % kSub)];
+  if (tid == 0) fcur[pair] = any_big ? 1 : 0;
+}
+
+__device__ void update_role(double *sh, const double *__restrict__ Msrc, double *__restrict__ Mdst,
+                            double *__restrict__ V, int64_t lp, int nb, int step,
+                            const double *__restrict__ R, const int *__restrict__ rflag, int64_t id) {
+  double *blk = sh, *tmp = sh + kSub * kSubLd, *rq = sh + 2 * kSub * kSubLd, *rp = sh + 3 * kSub * kSubLd;
   const int npairs = nb / 2;
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
   const int qr = w >> 1, qc = w & 1, li = lane & 15, lk = lane >> 4;
   const int64_t nm = (int64_t)npairs * npairs;
-  const int64_t id = blockIdx.x;
   const bool is_m = id < nm;
   int p, q;
   int64_t rowtile = 0;
   if (is_m) { p = (int)(id / npairs); q = (int)(id % npairs); }
   else { const int64_t k = id - nm; rowtile = k / npairs; q = (int)(k % npairs); p = -1; }
-  if (rflag[q] == 0 && (!is_m || rflag[p] == 0)) return;      // uniform: the whole workgroup
   const int qi = rr_player(q, step, nb), qj = rr_player(nb - 1 - q, step, nb);
+  if (rflag[q] == 0 && (!is_m || rflag[p] == 0)) {              // uniform: the whole workgroup
+    if (is_m) {
+      const int pi = rr_player(p, step, nb), pj = rr_player(nb - 1 - p, step, nb);
+      for (int e = tid; e < kSub * kSub; e += 256) {
+        const int64_t o = (int64_t)sub_index(e / kSub, pi, pj) * lp + sub_index(e % kSub, qi, qj);
+        Mdst[o] = Msrc[o];
+      }
+    }
+    return;
+  }
   for (int e = tid; e < kSub * kSub; e += 256) {
     rq[(e / kSub) * kSubLd + e % kSub] = R[(int64_t)q * kSub * kSub + e];
   }
@@ -362,7 +434,7 @@ __global__ __launch_bounds__(256) void bj_update_kernel(double *__restrict__ M, 
     for (int e = tid; e < kSub * kSub; e += 256) {
       const int u = e / kSub, x = e % kSub;
       rp[u * kSubLd + x] = R[(int64_t)p * kSub * kSub + e];
-      blk[u * kSubLd + x] = M[(int64_t)sub_index(u, pi, pj) * lp + sub_index(x, qi, qj)];
+      blk[u * kSubLd + x] = Msrc[(int64_t)sub_index(u, pi, pj) * lp + sub_index(x, qi, qj)];
     }
     __syncthreads();
     const doublex4 t = mm32_quadrant<false>(blk, rq, w, lane);      // blk R_q
@@ -372,7 +444,7 @@ __global__ __launch_bounds__(256) void bj_update_kernel(double *__restrict__ M, 
     const doublex4 o = mm32_quadrant<true>(rp, tmp, w, lane);       // R_p^T (blk R_q)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      M[(int64_t)sub_index(16 * qr + 4 * v + lk, pi, pj) * lp + sub_index(16 * qc + li, qi, qj)] = o[v];
+      Mdst[(int64_t)sub_index(16 * qr + 4 * v + lk, pi, pj) * lp + sub_index(16 * qc + li, qi, qj)] = o[v];
   } else {
     const int64_t r0 = rowtile * kSub;
     for (int e = tid; e < kSub * kSub; e += 256) {
@@ -384,6 +456,19 @@ __global__ __launch_bounds__(256) void bj_update_kernel(double *__restrict__ M, 
 #pragma unroll
     for (int v = 0; v < 4; ++v) V[(r0 + 16 * qr + 4 * v + lk) * lp + sub_index(16 * qc + li, qi, qj)] = o[v];
   }
+}
+
+__global__ __launch_bounds__(kPairThreads) void bj_round_kernel(
+    const double *__restrict__ Msrc, double *__restrict__ Mdst, double *__restrict__ V, int64_t lp,
+    int nb, int step, const double *__restrict__ Rprev, const int *__restrict__ fprev,
+    double *__restrict__ Rcur, int *__restrict__ fcur, const double *__restrict__ floor_abs,
+    double rel, int npair_wgs) {
+  static_assert(kPairThreads == 256, "four waves: one per subproblem block and output quadrant");
+  __shared__ double sh[kRoundLds];
+  if ((int)blockIdx.x < npair_wgs)
+    pair_role(sh, Msrc, lp, nb, step, Rprev, fprev, Rcur, fcur, floor_abs, rel, (int)blockIdx.x);
+  else
+    update_role(sh, Msrc, Mdst, V, lp, nb, step - 1, Rprev, fprev, (int64_t)blockIdx.x - npair_wgs);
 }
 
 // floor = abs_factor * max |diag| (one workgroup over the diagonal).
@@ -563,10 +648,10 @@ size_t eig_workspace_bytes(int64_t l) {
   const int64_t lp = padded(l);
   const int64_t nb = lp / kBlk;
   size_t bytes = 0;
-  bytes += (size_t)lp * lp * 8 * 2;                 // M, V
-  bytes += (size_t)(nb / 2) * kSub * kSub * 8;      // rotations
+  bytes += (size_t)lp * lp * 8 * 3;                 // M (two buffers), V
+  bytes += (size_t)(nb / 2) * kSub * kSub * 8 * 2;  // rotations of two rounds
   bytes += (size_t)lp * 4 + 64;                     // perm, counters
-  bytes += (size_t)(nb / 2) * 4 + 64;               // per-pair rotation flags
+  bytes += (size_t)(nb / 2) * 4 * 2 + 64;           // per-pair rotation flags of two rounds
   bytes += 256;
   return bytes;
 }
@@ -588,10 +673,15 @@ int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, dou
   const int npairs = nb / 2;
   char *p = static_cast<char *>(work);
   double *M = reinterpret_cast<double *>(p); p += (size_t)lp * lp * 8;
+  double *M2 = reinterpret_cast<double *>(p); p += (size_t)lp * lp * 8;
   double *V = reinterpret_cast<double *>(p); p += (size_t)lp * lp * 8;
-  double *R = reinterpret_cast<double *>(p); p += (size_t)npairs * kSub * kSub * 8;
+  double *Rb[2];
+  Rb[0] = reinterpret_cast<double *>(p); p += (size_t)npairs * kSub * kSub * 8;
+  Rb[1] = reinterpret_cast<double *>(p); p += (size_t)npairs * kSub * kSub * 8;
   int *perm = reinterpret_cast<int *>(p); p += (size_t)lp * 4;
-  int *rflag = reinterpret_cast<int *>(p); p += (size_t)npairs * 4;
+  int *fb[2];
+  fb[0] = reinterpret_cast<int *>(p); p += (size_t)npairs * 4;
+  fb[1] = reinterpret_cast<int *>(p); p += (size_t)npairs * 4;
   p = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(p) + 63) & ~uintptr_t(63));
   int *count = reinterpret_cast<int *>(p);
   double *floor_abs = reinterpret_cast<double *>(p + 8);
@@ -627,11 +717,17 @@ int eig_sym(const double *K, int64_t l, double *w, double *Vout, void *work, dou
     if (flat_sweeps >= 2 && (ratio <= kStallRel || offa <= kStallAbs * diag)) { conv = true; break; }
     if (sweeps == kEigMaxSweeps) break;
     ++sweeps;
-    for (int step = 0; step < nb - 1; ++step) {
-      hipLaunchKernelGGL(bj_pair_kernel, dim3(npairs), dim3(kPairThreads), 0, st, M, lp, nb, step, R, floor_abs,
-                         rel, rflag);
-      const int64_t nwg = (int64_t)npairs * npairs + (lp / kSub) * npairs;
-      hipLaunchKernelGGL(bj_update_kernel, dim3((unsigned)nwg), dim3(256), 0, st, M, V, lp, nb, step, R, rflag);
+    // round 0: pair subproblems only; rounds 1 .. nb - 2: the previous
+    // round's update and this round's pairs in one launch; then the last
+    // round's update alone.  M moves between the two buffers with every update.
+    const int64_t nwg = (int64_t)npairs * npairs + (lp / kSub) * npairs;
+    for (int step = 0; step < nb; ++step) {
+      const bool pairs = step < nb - 1, update = step > 0;
+      const int64_t grid = (pairs ? npairs : 0) + (update ? nwg : 0);
+      hipLaunchKernelGGL(bj_round_kernel, dim3((unsigned)grid), dim3(kPairThreads), 0, st, M, M2, V, lp, nb,
+                         step, Rb[(step + 1) & 1], fb[(step + 1) & 1], Rb[step & 1], fb[step & 1], floor_abs,
+                         rel, pairs ? npairs : 0);
+      if (update) std::swap(M, M2);
     }
   }
   hipLaunchKernelGGL(bj_rank_kernel, dim3((unsigned)((l + 255) / 256)), dim3(256), 0, st, M, l, lp, perm);

@@ -52,7 +52,7 @@ def _solve_both(fp, a32, **kw):
 
 
 def test_static_run_matches_run_twice(fp):
-    a1 = synth.spectral(1800, 1300, synth.exp_floor_sigma(1300, decay=30.0), seed=31).astype(np.float32)
+    a1 = synth.spectral(1700, 1250, synth.exp_floor_sigma(1250, decay=30.0), seed=31).astype(np.float32)
     a2 = synth.spectral(700, 500, synth.matrix1_sigma(500), seed=32).astype(np.float32)
     i1 = _solve_both(fp, a1, tol=1e-3, block=32, power=2, sketch="sparse_sign", zeta=8, seed=4)
     # the second, smaller call finds the first call's values in the static array
