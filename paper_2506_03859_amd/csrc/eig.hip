@@ -13,8 +13,9 @@
 // Jacobi sweep in LDS (one workgroup per pair), and the whole matrix is then
 // rotated block-by-block,
 // M[S_p, S_q] <- R_p^T M[S_p, S_q] R_q, V[:, S_q] <- V[:, S_q] R_q - every
-// output block depends only on the same input block, so the update runs in
-// place with one workgroup per block.  Sweeps repeat until every off-diagonal
+// output block depends only on the same input block: one workgroup per block,
+// M into a second buffer (V in place), in the same launch as the next round's
+// pair subproblems.  Sweeps repeat until every off-diagonal
 // entry is negligible relative to its diagonal pair.  Padding rows/columns are
 // exactly zero and never couple (their rotations are the identity).
 #include <cmath>
